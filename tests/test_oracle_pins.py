@@ -1,0 +1,623 @@
+"""Pins of the FP64 oracle against closed forms, library routines, printed
+tables and brute force (CPU only).  Each test is chosen so that a plausible
+slip in the oracle (a dropped term, a wrong sign, index or transpose) fails."""
+import math
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.interpolate
+import scipy.special
+import scipy.stats
+import scipy.stats.qmc
+
+from paper_2104_13542_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([float(x) for x in line.split()])
+    return rows
+
+
+# --------------------------------------------------------------------------
+# Sampling (Sec. 3.3)
+# --------------------------------------------------------------------------
+
+def test_halton_golden(oracle_lib):
+    for b, i, v in _golden("halton_radical_inverse.txt"):
+        assert oracle_lib.radical_inverse(int(i), int(b)) == pytest.approx(v, abs=1e-15)
+
+
+def test_halton_matches_scipy(oracle_lib):
+    primes = [2, 3, 5, 7, 11, 13, 17]
+    ref = scipy.stats.qmc.Halton(d=7, scramble=False).random(300)
+    for i in range(300):
+        for j, p in enumerate(primes):
+            assert oracle_lib.radical_inverse(i, p) == pytest.approx(ref[i, j], abs=1e-14)
+
+
+def test_ndtri_golden_and_scipy(oracle_lib):
+    for p, z in _golden("normal_quantiles.txt"):
+        assert oracle_lib.ndtri(p) == pytest.approx(z, abs=1e-12)
+    for p in np.linspace(1e-6, 1 - 1e-6, 57):
+        z = oracle_lib.ndtri(p)
+        assert z == pytest.approx(scipy.special.ndtri(p), abs=1e-11)
+        assert oracle_lib.normal_cdf(z) == pytest.approx(p, rel=1e-12)
+
+
+def test_normal_cdf_matches_scipy(oracle_lib):
+    for x in np.linspace(-6, 6, 25):
+        assert oracle_lib.normal_cdf(x) == pytest.approx(scipy.stats.norm.cdf(x), rel=1e-12, abs=1e-300)
+
+
+@pytest.mark.parametrize("H,K", [(16, 8), (30, 8), (64, 8), (7, 4), (1, 8), (2, 8)])
+def test_bspline_basis_matches_scipy(oracle_lib, H, K):
+    B = oracle_lib.bspline_basis(H, K)
+    knots = np.concatenate([[0.0] * 4, np.arange(1, K - 3) / (K - 3), [1.0] * 4])
+    s = np.array([0.0]) if H == 1 else np.arange(H) / (H - 1)
+    for k in range(K):
+        c = np.zeros(K)
+        c[k] = 1.0
+        ref = scipy.interpolate.BSpline(knots, c, 3, extrapolate=False)(s)
+        np.testing.assert_allclose(B[:, k], ref, atol=1e-14)
+    np.testing.assert_allclose(B.sum(axis=1), 1.0, atol=1e-14)
+    assert B[0, 0] == 1.0
+    if H > 1:
+        assert B[-1, -1] == pytest.approx(1.0, abs=1e-15)
+        # Greville abscissae reproduce linear data exactly.
+        g = np.array([(knots[k + 1] + knots[k + 2] + knots[k + 3]) / 3 for k in range(K)])
+        np.testing.assert_allclose(B @ g, s, atol=1e-14)
+
+
+def test_halton_noise_composition(oracle_lib):
+    nh, H, K = 12, 30, 8
+    eps = oracle_lib.halton_noise(nh, H, K)
+    pts = scipy.stats.qmc.Halton(d=7, scramble=False).random(1 + nh * K)
+    Z = scipy.special.ndtri(pts[1:]).reshape(nh, K, 7)
+    B = oracle_lib.bspline_basis(H, K)
+    ref = np.einsum("hk,ikj->ihj", B, Z)
+    np.testing.assert_allclose(eps, ref, atol=1e-11)
+
+
+_PHILOX_CPP = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+#include <cstdint>
+int main() {
+  unsigned long long seed, sub, off;
+  while (std::scanf("%llu %llu %llu", &seed, &sub, &off) == 3) {
+    at::philox_engine e(seed, sub, off);
+    unsigned a = e(), b = e(), c = e(), d = e();
+    std::printf("%u %u %u %u\n", a, b, c, d);
+  }
+  return 0;
+}
+"""
+
+
+def test_philox_matches_torch_engine(oracle_lib):
+    """The oracle's Philox4x32-10 against PyTorch's independent C++ philox
+    engine, whose counter is (offset_lo, offset_hi, subsequence_lo,
+    subsequence_hi) and key is the 64-bit seed."""
+    import torch
+
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    if not os.path.exists(os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")):
+        pytest.skip("PyTorch C++ headers not installed")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.cpp")
+        exe = os.path.join(d, "p")
+        with open(src, "w") as f:
+            f.write(_PHILOX_CPP)
+        subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", inc, src, "-o", exe])
+        rng = np.random.default_rng(7)
+        cases = [(0, 0, 0), (2**64 - 1, 2**64 - 1, 2**64 - 1), (1234, 5, 6)]
+        cases += [tuple(int(x) for x in rng.integers(0, 2**63, 3)) for _ in range(40)]
+        text = "".join("%d %d %d\n" % c for c in cases)
+        out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (seed, sub, off), line in zip(cases, out):
+        ctr = (off & 0xFFFFFFFF, off >> 32, sub & 0xFFFFFFFF, sub >> 32)
+        key = (seed & 0xFFFFFFFF, seed >> 32)
+        assert oracle_lib.philox4x32_10(ctr, key) == tuple(int(x) for x in line.split())
+
+
+def test_gaussian_noise_statistics(oracle_lib):
+    z = np.array([oracle_lib.gauss7(42, 3, i, h) for i in range(300) for h in range(20)]).reshape(-1)
+    assert abs(z.mean()) < 0.03
+    assert abs(z.var() - 1.0) < 0.04
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    # joints are uncorrelated
+    zz = z.reshape(-1, 7)
+    c = np.corrcoef(zz.T)
+    assert np.max(np.abs(c - np.eye(7))) < 0.06
+    # counter fields matter: a different step or seed changes the draw
+    assert not np.allclose(oracle_lib.gauss7(42, 3, 0, 0), oracle_lib.gauss7(42, 4, 0, 0))
+    assert not np.allclose(oracle_lib.gauss7(42, 3, 0, 0), oracle_lib.gauss7(43, 3, 0, 0))
+
+
+def test_noise_layout(oracle_lib):
+    prob = inputs.config2(0, n_particles=20, horizon=12)
+    prob.params.n_null = 3
+    o = oracle_lib.Oracle(prob)
+    eps = o.noise(5)
+    np.testing.assert_allclose(eps[:10], oracle_lib.halton_noise(10, 12, 8), atol=0)
+    np.testing.assert_array_equal(eps[17:], 0.0)
+    np.testing.assert_allclose(eps[12, 4], oracle_lib.gauss7(prob.params.seed, 5, 12, 4), atol=0)
+
+
+# --------------------------------------------------------------------------
+# Integrator (Sec. 3.1, Eq. 7)
+# --------------------------------------------------------------------------
+
+def test_integrator_closed_form(oracle_lib):
+    H, dt = 16, 0.02
+    rng = np.random.default_rng(1)
+    q0, v0, uc = rng.normal(size=7), rng.normal(size=7), rng.normal(size=7)
+    q, v, a = oracle_lib.integrate(np.full(H, dt), q0, v0, np.tile(uc, (H, 1)))
+    for h in range(H):
+        n = h + 1
+        np.testing.assert_allclose(v[h], v0 + n * dt * uc, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(q[h], q0 + n * dt * v0 + dt * dt * uc * n * (n + 1) / 2, rtol=1e-12, atol=1e-13)
+        np.testing.assert_array_equal(a[h], uc)
+
+
+def test_integrator_linear_and_adjoint(oracle_lib):
+    H = 30
+    rng = np.random.default_rng(2)
+    dt = np.linspace(0.01, 0.1, H)
+    z = np.zeros(7)
+    u1, u2 = rng.normal(size=(H, 7)), rng.normal(size=(H, 7))
+    q1, v1, _ = oracle_lib.integrate(dt, z, z, u1)
+    q2, v2, _ = oracle_lib.integrate(dt, z, z, u2)
+    q3, v3, _ = oracle_lib.integrate(dt, z, z, 2.0 * u1 - 3.0 * u2)
+    np.testing.assert_allclose(q3, 2 * q1 - 3 * q2, atol=1e-12)
+    np.testing.assert_allclose(v3, 2 * v1 - 3 * v2, atol=1e-12)
+    # matrix of the linear map u -> q on one joint, compared with the product
+    # of the two triangular sums S_l(1) diag(dt) applied twice
+    L = np.zeros((H, H))
+    for m in range(H):
+        e = np.zeros((H, 7))
+        e[m, 0] = 1.0
+        L[:, m] = oracle_lib.integrate(dt, z, z, e)[0][:, 0]
+    S = np.tril(np.ones((H, H))) @ np.diag(dt)
+    np.testing.assert_allclose(L, S @ S, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Kinematics (Sec. 3.1, Eq. 8)
+# --------------------------------------------------------------------------
+
+def test_fk_zero_pose_golden(oracle_lib):
+    g = np.array(_golden("panda_zero_pose.txt"))
+    T = oracle_lib.fk(inputs.PANDA_DH, np.zeros(7))[7]
+    np.testing.assert_allclose(T[:3, :3], g[:3], atol=1e-12)
+    np.testing.assert_allclose(T[:3, 3], g[3], atol=1e-12)
+
+
+def test_fk_invariants(oracle_lib):
+    rng = np.random.default_rng(3)
+    dists = None
+    for _ in range(20):
+        q = inputs.random_q(rng)
+        T = oracle_lib.fk(inputs.PANDA_DH, q)
+        for k in range(8):
+            R = T[k][:3, :3]
+            np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-12)
+            assert np.linalg.det(R) == pytest.approx(1.0, abs=1e-12)
+            np.testing.assert_array_equal(T[k][3], [0, 0, 0, 1])
+        d = [np.linalg.norm(T[k + 1][:3, 3] - T[k][:3, 3]) for k in range(7)]
+        if dists is None:
+            dists = d
+        np.testing.assert_allclose(d, dists, atol=1e-12)
+        # joint 1 turns the whole arm about the world z axis
+        dlt = 0.37
+        q2 = q.copy()
+        q2[0] += dlt
+        T2 = oracle_lib.fk(inputs.PANDA_DH, q2)
+        Rz = np.array([[math.cos(dlt), -math.sin(dlt), 0, 0], [math.sin(dlt), math.cos(dlt), 0, 0],
+                       [0, 0, 1, 0], [0, 0, 0, 1]])
+        np.testing.assert_allclose(T2[7], Rz @ T[7], atol=1e-12)
+    np.testing.assert_allclose(dists, [0.0, 0.316, 0.0825, math.hypot(0.0825, 0.384), 0.0, 0.088, 0.107],
+                               atol=1e-12)
+    # frame 1 sits 0.333 m above the base
+    np.testing.assert_allclose(T[0][:3, 3], [0, 0, 0.333], atol=1e-12)
+
+
+def test_jacobian_finite_differences(oracle_lib):
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        q = inputs.random_q(rng)
+        T = oracle_lib.fk(inputs.PANDA_DH, q)
+        J = oracle_lib.jacobian(T)
+        h = 1e-6
+        for k in range(7):
+            qp, qm = q.copy(), q.copy()
+            qp[k] += h
+            qm[k] -= h
+            Tp, Tm = oracle_lib.fk(inputs.PANDA_DH, qp)[7], oracle_lib.fk(inputs.PANDA_DH, qm)[7]
+            dp = (Tp[:3, 3] - Tm[:3, 3]) / (2 * h)
+            dR = (Tp[:3, :3] - Tm[:3, :3]) / (2 * h)
+            W = dR @ T[7][:3, :3].T
+            w = np.array([W[2, 1], W[0, 2], W[1, 0]])
+            np.testing.assert_allclose(J[:3, k], dp, atol=1e-8)
+            np.testing.assert_allclose(J[3:, k], w, atol=1e-8)
+
+
+def test_det_and_manipulability(oracle_lib):
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        A = rng.normal(size=(6, 6))
+        assert oracle_lib.det(A) == pytest.approx(np.linalg.det(A), rel=1e-10)
+        q = inputs.random_q(rng)
+        J = oracle_lib.jacobian(oracle_lib.fk(inputs.PANDA_DH, q))
+        sv = np.linalg.svd(J, compute_uv=False)
+        assert oracle_lib.manipulability(J) == pytest.approx(np.prod(sv), rel=1e-9)
+    # a singular configuration (wrist straight, elbow straight) gives m close to 0
+    assert oracle_lib.det(np.zeros((6, 6))) == 0.0
+
+
+# --------------------------------------------------------------------------
+# Costs (Sec. 3.2, Eq. 9-15)
+# --------------------------------------------------------------------------
+
+def _axis_angle(axis, ang):
+    axis = np.asarray(axis, float) / np.linalg.norm(axis)
+    K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+
+
+def test_pose_cost_closed_form(oracle_lib):
+    prob = inputs.config1(0)
+    o = oracle_lib.Oracle(prob)
+    rng = np.random.default_rng(6)
+    for _ in range(10):
+        Rg = inputs.random_rotation(rng)
+        pg = rng.normal(size=3)
+        phi = rng.uniform(-3.0, 3.0)
+        R = Rg @ _axis_angle(rng.normal(size=3), phi)
+        d = rng.normal(size=3) * 0.3
+        T = np.eye(4)
+        T[:3, :3] = R
+        T[:3, 3] = pg + d
+        goal = np.concatenate([Rg.reshape(-1), pg])
+        pos, rot = _pose(oracle_lib, o, T, goal)
+        assert rot == pytest.approx(2 * math.sqrt(2) * abs(math.sin(phi / 2)), rel=1e-12)
+        assert pos == pytest.approx(np.linalg.norm(d), rel=1e-12)
+        T[:3, :3] = Rg
+        T[:3, 3] = pg
+        pos, rot = _pose(oracle_lib, o, T, goal)
+        assert pos == pytest.approx(0.0, abs=1e-14) and rot == pytest.approx(0.0, abs=1e-14)
+    # axis weights act in the goal frame: a goal-frame x offset is scaled by alpha_pos[0]
+    o.params.alpha_pos[0] = 3.0
+    Rg = inputs.random_rotation(rng)
+    T = np.eye(4)
+    T[:3, :3] = Rg
+    T[:3, 3] = Rg @ np.array([0.2, 0.0, 0.0])
+    pos, _ = _pose(oracle_lib, o, T, np.concatenate([Rg.reshape(-1), np.zeros(3)]))
+    assert pos == pytest.approx(0.6, rel=1e-12)
+
+
+def _pose(oracle_lib, o, T, goal):
+    import ctypes
+
+    pos, rot = ctypes.c_double(), ctypes.c_double()
+    T = np.ascontiguousarray(T)
+    goal = np.ascontiguousarray(goal)
+    oracle_lib.lib().oracle_cost_pose(ctypes.byref(o.params), oracle_lib._d(T), oracle_lib._d(goal),
+                                      ctypes.byref(pos), ctypes.byref(rot))
+    return pos.value, rot.value
+
+
+def test_joint_limit_band(oracle_lib):
+    lo, hi = inputs.PANDA_Q_MIN, inputs.PANDA_Q_MAX
+    L = oracle_lib.lib()
+    f = lambda x, k=0.1: L.oracle_cost_box(oracle_lib._d(np.ascontiguousarray(x, float)), oracle_lib._d(lo),
+                                           oracle_lib._d(hi), k)
+    mid = 0.5 * (lo + hi)
+    assert f(mid) == 0.0
+    x = mid.copy()
+    x[0] = 2.31784  # joint-1 band edge: 2.8973 - 0.1 * 5.7946
+    assert f(x) == pytest.approx(0.0, abs=1e-12)
+    x[0] = 2.5
+    assert f(x) == pytest.approx(2.5 - 2.31784, abs=1e-12)
+    x[1] = -1.7628  # lower limit of joint 2: violation 0.1 * 3.5256
+    assert f(x) == pytest.approx(math.hypot(2.5 - 2.31784, 0.35256), abs=1e-12)
+    assert f(x, 0.0) == pytest.approx(0.0, abs=1e-12)
+
+
+def test_stop_profile(oracle_lib):
+    L = oracle_lib.lib()
+    dt = np.linspace(0.01, 0.1, 30)
+    for h in range(30):
+        assert L.oracle_stop_limit(30, oracle_lib._d(dt), 2.0, h) == pytest.approx(2.0 * dt[h:].sum(), rel=1e-14)
+    v = np.array([0.3, -0.5, 0.1, 0.0, 0.0, 0.0, 0.0])
+    assert L.oracle_cost_stop(oracle_lib._d(v), 0.2) == pytest.approx(math.hypot(0.1, 0.3), rel=1e-14)
+    assert L.oracle_cost_stop(oracle_lib._d(v), 0.6) == 0.0
+    assert L.oracle_cost_manip(0.01, 0.05) == pytest.approx(0.99)
+    assert L.oracle_cost_manip(0.05, 0.05) == 0.0
+
+
+def _frames_identity():
+    T = np.zeros((8, 4, 4))
+    for k in range(8):
+        T[k] = np.eye(4)
+    return T
+
+
+def test_self_collision_brute_force(oracle_lib):
+    prob = inputs.config1(0)
+    # two spheres on bodies 1 and 3 at distance 1.0 with radii 0.5 + 0.5: touching -> 0
+    prob.spheres = np.array([[1, 0, 0, 0, 0.5], [3, 1.0, 0, 0, 0.5]])
+    o = oracle_lib.Oracle(prob)
+    assert o.cost_self(_frames_identity()) == pytest.approx(0.0, abs=1e-15)
+    prob.spheres = np.array([[1, 0, 0, 0, 0.5], [3, 0.5, 0, 0, 0.5]])
+    o = oracle_lib.Oracle(prob)
+    assert o.cost_self(_frames_identity()) == pytest.approx(0.5)
+    # adjacent bodies are ignored
+    prob.spheres = np.array([[1, 0, 0, 0, 0.5], [2, 0.1, 0, 0, 0.5]])
+    o = oracle_lib.Oracle(prob)
+    assert o.cost_self(_frames_identity()) == 0.0
+    # brute force over random small sets, with body frames translated
+    rng = np.random.default_rng(8)
+    for n in range(2, 7):
+        sph = np.column_stack([rng.integers(1, 9, n), rng.normal(size=(n, 3)) * 0.2, rng.uniform(0.05, 0.2, n)])
+        prob.spheres = sph
+        o = oracle_lib.Oracle(prob)
+        T = _frames_identity()
+        off = rng.normal(size=(8, 3)) * 0.1
+        T[:, :3, 3] = off
+        c = sph[:, 1:4] + off[sph[:, 0].astype(int) - 1]
+        best = 0.0
+        for s in range(n):
+            for t in range(n):
+                if s != t and abs(sph[s, 0] - sph[t, 0]) >= 2:
+                    best = max(best, sph[s, 4] + sph[t, 4] - np.linalg.norm(c[s] - c[t]))
+        assert o.cost_self(T) == pytest.approx(best, abs=1e-14)
+
+
+def _box(c, e, R):
+    row = np.zeros(16)
+    row[0] = 1
+    row[1:4] = c
+    row[4:7] = e
+    row[7:16] = np.asarray(R).reshape(-1)
+    return row
+
+
+def test_sdf_hand_cases(oracle_lib):
+    sph = np.zeros(16)
+    sph[1:4] = [1, 2, 3]
+    sph[4] = 0.5
+    assert oracle_lib.sdf(sph, [1, 2, 3]) == pytest.approx(-0.5)
+    assert oracle_lib.sdf(sph, [1, 2, 5]) == pytest.approx(1.5)
+    box = _box([0, 0, 0], [1, 2, 3], np.eye(3))
+    assert oracle_lib.sdf(box, [0, 0, 0]) == pytest.approx(-1.0)  # centre: -min half extent
+    assert oracle_lib.sdf(box, [1.5, 0, 0]) == pytest.approx(0.5)  # face
+    assert oracle_lib.sdf(box, [0.5, 0, 0]) == pytest.approx(-0.5)
+    assert oracle_lib.sdf(box, [2, 3, 0]) == pytest.approx(math.sqrt(2))  # edge
+    assert oracle_lib.sdf(box, [2, 3, 4]) == pytest.approx(math.sqrt(3))  # corner
+    # rotation: a box rotated 90 deg about z swaps its x and y extents
+    Rz = _axis_angle([0, 0, 1], math.pi / 2)
+    boxr = _box([0, 0, 0], [1, 2, 3], Rz)
+    assert oracle_lib.sdf(boxr, [2.5, 0, 0]) == pytest.approx(0.5)
+    assert oracle_lib.sdf(boxr, [0, 1.5, 0]) == pytest.approx(0.5)
+
+
+def test_sdf_brute_force_and_gradient(oracle_lib):
+    rng = np.random.default_rng(9)
+    R = inputs.random_rotation(rng)
+    c = np.array([0.3, -0.2, 0.5])
+    e = np.array([0.1, 0.15, 0.05])
+    box = _box(c, e, R)
+    # dense surface sample of the box
+    g = np.linspace(-1, 1, 81)
+    pts = []
+    for ax in range(3):
+        for sgn in (-1, 1):
+            a, b = np.meshgrid(g, g)
+            loc = np.zeros((a.size, 3))
+            loc[:, ax] = sgn
+            other = [k for k in range(3) if k != ax]
+            loc[:, other[0]] = a.ravel()
+            loc[:, other[1]] = b.ravel()
+            pts.append(loc * e)
+    surf = np.concatenate(pts) @ R.T + c
+    for _ in range(20):
+        x = c + rng.normal(size=3) * 0.3
+        d = oracle_lib.sdf(box, x)
+        local = R.T @ (x - c)
+        if np.all(np.abs(local) <= e):
+            assert d <= 0
+            continue
+        dmin = np.min(np.linalg.norm(surf - x, axis=1))
+        assert d == pytest.approx(dmin, abs=3e-3)
+        # Lipschitz-1 with unit gradient outside
+        h = 1e-6
+        grad = np.array([(oracle_lib.sdf(box, x + h * ei) - oracle_lib.sdf(box, x - h * ei)) / (2 * h)
+                         for ei in np.eye(3)])
+        assert np.linalg.norm(grad) == pytest.approx(1.0, abs=1e-5)
+
+
+def test_env_cost_hand_case(oracle_lib):
+    prob = inputs.config1(0)
+    prob.spheres = np.array([[1, 0, 0, 0, 0.2], [2, 1.0, 0, 0, 0.1]])
+    box = _box([0.25, 0, 0], [0.1, 0.1, 0.1], np.eye(3))  # face at x = 0.15
+    sph = np.zeros(16)
+    sph[1:4] = [1.0, 0.25, 0]
+    sph[4] = 0.2  # surface 0.05 from sphere 2's centre
+    prob.obstacles = np.stack([box, sph])
+    o = oracle_lib.Oracle(prob)
+    # sphere 1: r 0.2, box face 0.15 away -> 0.05; sphere 2: r 0.1, sdf 0.05 -> 0.05
+    assert o.cost_env(_frames_identity()) == pytest.approx(0.1, abs=1e-14)
+
+
+def test_running_cost_weights(oracle_lib):
+    prob = inputs.config2(3, n_particles=4, horizon=5)
+    o = oracle_lib.Oracle(prob)
+    rng = np.random.default_rng(10)
+    q = inputs.random_q(rng)
+    v = rng.normal(size=7) * 2
+    c, t = o.running_cost(q, v, 2)
+    p = prob.params
+    ref = (p.w_pos * t[0] + p.w_rot * t[1] + p.a_joint * t[2] + p.a_vel * t[3] + p.a_stop * t[4]
+           + p.a_manip * t[5] + p.a_coll * (t[6] + t[7]))
+    assert c == pytest.approx(ref, rel=1e-14)
+    T = oracle_lib.fk(inputs.PANDA_DH, q)
+    J = oracle_lib.jacobian(T)
+    m = np.prod(np.linalg.svd(J, compute_uv=False))
+    assert t[5] == pytest.approx((1 - m) if m < 0.05 else 0.0, abs=1e-12)
+    assert t[6] == pytest.approx(o.cost_self(T), rel=1e-14)
+    assert t[7] == pytest.approx(o.cost_env(T), rel=1e-14)
+    # disabled terms are zero
+    o.params.cost_mask = inputs.COST_POSE
+    c2, t2 = o.running_cost(q, v, 2)
+    assert np.all(t2[2:] == 0.0) and c2 == pytest.approx(p.w_pos * t2[0] + p.w_rot * t2[1])
+
+
+# --------------------------------------------------------------------------
+# Rollout composition and update (Sec. 3, Eq. 2, 4-6)
+# --------------------------------------------------------------------------
+
+def test_rollout_composition(oracle_lib):
+    prob = inputs.config2(1, n_particles=6, horizon=9)
+    prob.params.n_null = 1
+    prob.params.gamma = 0.9
+    prob.params.w_term = 2.5
+    o = oracle_lib.Oracle(prob)
+    rng = np.random.default_rng(11)
+    mean = rng.normal(size=(9, 7)) * 0.2
+    sigma = np.full(7, 0.3)
+    eps = o.noise(0)
+    r = o.rollout(mean, sigma, eps)
+    for i in range(6):
+        u = np.zeros((9, 7)) if i == 5 else mean + sigma * eps[i]
+        np.testing.assert_allclose(r["u"][i], u, atol=0)
+        q, v, a = oracle_lib.integrate(prob.params.dt, prob.q0, prob.v0, u)
+        np.testing.assert_allclose(r["q"][i], q, atol=0)
+        np.testing.assert_allclose(r["v"][i], v, atol=0)
+        C = 0.0
+        for h in range(9):
+            c, t = o.running_cost(q[h], v[h], h)
+            assert r["c"][i, h] == pytest.approx(c, rel=1e-15)
+            w = 0.9 ** h * (2.5 if h == 8 else 1.0)
+            C += w * c
+        assert r["C"][i] == pytest.approx(C, rel=1e-13)
+
+
+def test_update_weights_and_mean(oracle_lib):
+    prob = inputs.config1(0)
+    N, H = 64, 16
+    o = oracle_lib.Oracle(prob)
+    rng = np.random.default_rng(12)
+    u = rng.normal(size=(N, H, 7))
+    mean = rng.normal(size=(H, 7))
+    sig2 = np.full(7, 0.01)
+    C = rng.uniform(0, 1, N)
+    r = o.update(C, u, mean, sig2)
+    assert r["w"].sum() == pytest.approx(1.0, rel=1e-14)
+    ref = np.exp(-(C - C.min()) / 0.1)
+    np.testing.assert_allclose(r["w"], ref / ref.sum(), rtol=1e-13)
+    r2 = o.update(C + 1234.5, u, mean, sig2)
+    np.testing.assert_allclose(r2["w"], r["w"], rtol=1e-10)
+    # equal costs -> uniform weights; mean = numpy mean (alpha_mu = 1)
+    r3 = o.update(np.full(N, 7.0), u, mean, sig2)
+    np.testing.assert_allclose(r3["w"], 1.0 / N)
+    np.testing.assert_allclose(r3["mean"], u.mean(axis=0), atol=1e-13)
+    # one dominant particle -> one-hot, mean = its control
+    Cd = np.full(N, 100.0)
+    Cd[17] = 0.0
+    r4 = o.update(Cd, u, mean, sig2)
+    assert r4["w"][17] == pytest.approx(1.0)
+    np.testing.assert_allclose(r4["mean"], u[17], atol=1e-12)
+    # large beta -> uniform
+    o.params.beta = 1e12
+    r5 = o.update(C, u, mean, sig2)
+    np.testing.assert_allclose(r5["w"], 1.0 / N, rtol=1e-9)
+    o.params.beta = 0.1
+    # alpha_mu = 0 keeps the mean
+    o.params.alpha_mu = 0.0
+    r6 = o.update(C, u, mean, sig2)
+    np.testing.assert_allclose(r6["mean"], mean, atol=0)
+    o.params.alpha_mu = 1.0
+    # command and shift
+    np.testing.assert_array_equal(r["cmd"], r["mean"][0])
+    np.testing.assert_array_equal(r["mean_shift"][:-1], r["mean"][1:])
+    np.testing.assert_array_equal(r["mean_shift"][-1], 0.0)
+
+
+def test_update_covariance(oracle_lib):
+    prob = inputs.config1(0)
+    N, H = 64, 16
+    o = oracle_lib.Oracle(prob)
+    rng = np.random.default_rng(13)
+    u = rng.normal(size=(N, H, 7))
+    sig2 = rng.uniform(0.01, 0.1, 7)
+    o.params.alpha_sigma = 1.0
+    r = o.update(np.zeros(N), u, np.zeros((H, 7)), sig2)
+    ref = np.mean(np.var(u, axis=0, ddof=0), axis=0)
+    np.testing.assert_allclose(r["sigma2"], ref, rtol=1e-12)
+    o.params.alpha_sigma = 0.0
+    r = o.update(np.zeros(N), u, np.zeros((H, 7)), sig2)
+    np.testing.assert_allclose(r["sigma2"], sig2, rtol=0)
+    o.params.alpha_sigma = 0.25
+    r = o.update(np.zeros(N), u, np.zeros((H, 7)), sig2)
+    np.testing.assert_allclose(r["sigma2"], 0.75 * sig2 + 0.25 * ref, rtol=1e-12)
+    o.params.sigma2_min = 10.0
+    r = o.update(np.zeros(N), u, np.zeros((H, 7)), sig2)
+    np.testing.assert_allclose(r["sigma2"], 10.0)
+
+
+def test_update_rejects_nonfinite(oracle_lib):
+    prob = inputs.config1(0)
+    o = oracle_lib.Oracle(prob)
+    C = np.zeros(64)
+    C[3] = np.nan
+    mean = np.ones((16, 7))
+    r = o.update(C, np.zeros((64, 16, 7)), mean, np.full(7, 0.01))
+    assert r["bad"]
+    np.testing.assert_array_equal(r["mean"], mean)
+
+
+# --------------------------------------------------------------------------
+# Gradient of the expected horizon cost
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mask", [inputs.COST_POSE | inputs.COST_JOINT,
+                                  inputs.COST_POSE | inputs.COST_JOINT | inputs.COST_VEL | inputs.COST_STOP])
+def test_gradient_finite_differences(oracle_lib, mask):
+    prob = inputs.config4(2)
+    prob.params.n_particles = 24
+    prob.params.horizon = 8
+    prob.params.dt = np.linspace(0.02, 0.08, 8)
+    prob.params.cost_mask = mask
+    prob.params.n_null = 2
+    prob.params.gamma = 0.95
+    prob.q0 = np.array([2.5, 1.6, -2.5, -2.9, 2.5, 3.6, 2.5])  # near limits: joint terms active
+    prob.v0 = np.array([2.0, -2.0, 1.5, 0.0, 2.5, -2.5, 1.0])
+    o = oracle_lib.Oracle(prob)
+    rng = np.random.default_rng(14)
+    mean = rng.normal(size=(8, 7)) * 0.5
+    sigma = np.full(7, 0.4)
+    eps = rng.normal(size=(24, 8, 7))
+    g, J = o.grad(mean, sigma, eps)
+    assert J == pytest.approx(o.expected_cost(mean, sigma, eps), rel=1e-13)
+    h = 1e-3
+    fd = np.zeros_like(g)
+    for t in range(8):
+        for j in range(7):
+            mp, mm = mean.copy(), mean.copy()
+            mp[t, j] += h
+            mm[t, j] -= h
+            fd[t, j] = (o.expected_cost(mp, sigma, eps) - o.expected_cost(mm, sigma, eps)) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-3 * np.linalg.norm(fd)
+    # last-step control moves no earlier state: only its own step's cost, through dt^2
+    assert np.linalg.norm(g) > 0
