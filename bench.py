@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the STORM MPPI step on one MI355X.
+
+Workload: the STORM-shaped problem - N = 500 particles (250 Halton + cubic
+B-spline, 250 Gaussian), H = 30 steps with dt = linspace(0.01, 0.1, 30), every
+cost term, the 52-sphere body model and 30 sphere + 20 cuboid obstacles.  A
+step is one whole MPC iteration: sample -> roll out -> horizon cost ->
+exponentiated-cost update -> next command + shift.  Inputs are resident on the
+GPU before timing; the timed region is K back-to-back steps on one stream.
+
+Prints one JSON line: rollout-steps/s (N * H * K / device time), the MPC-step
+latency (host wall clock from enqueue to the command being readable on the
+host) p50/p99, the roofline position of the rollout kernel (algorithmic FP32
+FLOPs per launch / its average duration from HIP events recorded around each
+launch in the timed region) and the FP64 CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rollout-steps/s & MPC-step p50/p99 latency, batched vs plain, N=500 H=30"
+
+# MI355X published peaks.
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # packed FP32 vector
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # one FP32 op per lane per cycle (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_particle_step(mask, n_spheres, n_pairs, n_sph_obs, n_box_obs, gaussian_fraction):
+    """Algorithmic FP32 FLOPs of one (particle, step) point of the rollout
+    kernel (FMA = 2, add/mul/min/max/compare = 1, sqrt/sin/cos/log = 1)."""
+    from paper_2104_13542_amd import inputs as I
+
+    f = 0.0
+    f += 28.0 * gaussian_fraction  # Box-Muller, 7 normals (Philox is integer work)
+    f += 14.0  # u = mu + sigma eps
+    f += 42.0  # integrator: two prefix sums and the dt products, 7 joints
+    f += 398.0  # forward kinematics: 8 DH transforms (48 each) + 7 sin + 7 cos
+    if mask & (I.COST_JOINT | I.COST_VEL | I.COST_STOP):
+        f += 129.0  # joint / velocity / stop hinges (7 joints) + 3 norms
+    if mask & I.COST_POSE:
+        f += 110.0  # R_g^T R, position in goal frame, two weighted norms
+    if mask & I.COST_MANIP:
+        f += 450.0  # Jacobian (84), J J^T (294), LDL^T determinant, sqrt
+    if mask & (I.COST_SELF | I.COST_ENV):
+        f += 18.0 * n_spheres  # world sphere centres
+    if mask & I.COST_ENV:
+        f += n_spheres * (11.0 * n_sph_obs + 30.0 * n_box_obs)
+    if mask & I.COST_SELF:
+        f += 9.0 * n_pairs
+    f += 22.0  # weighted sum (Eq. 15) and horizon weight (Eq. 2)
+    return f
+
+
+def self_pair_count(spheres):
+    b = spheres[:, 0].astype(int)
+    n = 0
+    for s in range(len(b)):
+        for t in range(s + 1, len(b)):
+            if abs(b[s] - b[t]) >= 2:
+                n += 1
+    return n
+
+
+def cpu_baseline(prob, budget_s):
+    """FP64 oracle (single thread, as it stands) on whole steps of the same
+    workload until budget_s seconds have elapsed."""
+    import numpy as np
+
+    import oracle
+
+    p = prob.params
+    o = oracle.Oracle(prob)
+    mean = np.zeros((p.horizon, 7))
+    sig2 = np.asarray(p.sigma_init, dtype=np.float64) ** 2
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        _, up = o.step(steps, mean, sig2)
+        mean, sig2 = up["mean_shift"], up["sigma2"]
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {
+        "value": p.n_particles * p.horizon * steps / el,
+        "unit": "rollout-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "%d whole steps (noise + rollout + update) of the N=%d H=%d workload, %.1f s, 1 thread"
+                  % (steps, p.n_particles, p.horizon, el),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--latency-steps", type=int, default=1000)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work (0 = skip)")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the MPC step of one problem runs on a single MI355X "
+              "(multi-GPU sharding is not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    torch.cuda.set_device(0)
+    prob = inputs.config2(args.seed)
+    p = prob.params
+    N, H = p.n_particles, p.horizon
+    r = storm.Rollout(prob)
+    qg = torch.tensor(prob.q_goal, dtype=torch.float32, device="cuda").reshape(1, 7)
+    goal = storm.fk(qg)[0][0].contiguous()
+    C = torch.empty(N, dtype=torch.float32, device="cuda")
+    cmd = torch.empty(7, dtype=torch.float32, device="cuda")
+
+    def one_step():
+        r.step(goal, C=C)
+        r.update(shift=True, want_mean=False, cmd=cmd)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(K):
+        ev[k][0].record()
+        r.step(goal, C=C)
+        ev[k][1].record()
+        r.update(shift=True, want_mean=False, cmd=cmd)
+    end.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    rollout_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms_per_step = total_ms / K
+    value = N * H * K / (total_ms * 1e-3)
+
+    # latency: enqueue -> command readable on the host
+    lat = []
+    cmd_host = torch.empty(7, dtype=torch.float32, pin_memory=True)
+    for _ in range(args.latency_steps):
+        t0 = time.perf_counter()
+        one_step()
+        cmd_host.copy_(cmd, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.array(lat)
+    r.close()
+
+    n_sph = prob.spheres.shape[0]
+    kinds = prob.obstacles[:, 0]
+    n_so = int(np.sum(kinds == inputs.OBS_SPHERE))
+    n_bo = int(np.sum(kinds == inputs.OBS_CUBOID))
+    n_pairs = self_pair_count(prob.spheres)
+    gfrac = (N - p.n_halton - p.n_null) / N
+    fpp = flops_per_particle_step(p.cost_mask, n_sph, n_pairs, n_so, n_bo, gfrac)
+    achieved = fpp * N * H / (rollout_ms * 1e-3) / 1e12
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "STORM-shaped MPPI step (plain): N=500 (250 Halton+B-spline, 250 Gaussian), H=30, "
+                        "dt 0.01->0.1, all cost terms, 52 body spheres (%d self pairs), %d sphere + %d cuboid "
+                        "obstacles" % (n_pairs, n_so, n_bo),
+            "N": N, "H": H, "problems": 1,
+        },
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "steps": int(len(lat))},
+        "roofline": {
+            "kernel": "rollout_kernel",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+            "flops_per_launch": fpp * N * H,
+            "avg_launch_us": rollout_ms * 1e3,
+            "traffic": None,
+        },
+    }
+    if args.cpu_budget > 0:
+        line["cpu_baseline"] = cpu_baseline(inputs.config2(args.seed), args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * storm.h - C ABI of the MI355X (gfx950) STORM MPPI library.
+ *
+ * One MPC iteration of STORM (arXiv 2104.13542): sample N control sequences
+ * (Sec. 3.3), integrate each over H steps (Sec. 3.1, Eq. 7), evaluate forward
+ * kinematics and the Jacobian (Eq. 8), the running cost (Sec. 3.2, Eq. 9-15)
+ * and the horizon cost (Eq. 2), then update the Gaussian policy with
+ * exponentiated-cost weights (Eq. 4-6), emit the next command and shift the
+ * mean (Alg. 1).
+ *
+ * Conventions for every call:
+ *   - Every function returns a storm_status (0 = success, < 0 = error).
+ *   - Arguments named h_* or passed inside structs at init are host memory;
+ *     the library copies them and never touches them after the call returns.
+ *   - Arguments named d_* are device memory owned by the caller.  They must
+ *     stay valid until the work enqueued on `stream` has completed.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     that enqueue work (step, update, grad, batch_*) allocate nothing and do
+ *     not synchronise, so they can be captured into a HIP graph.
+ *   - Validation errors are reported before anything is enqueued.  A HIP
+ *     launch failure returns STORM_E_DEVICE and makes that context sticky:
+ *     later calls on it return STORM_E_DEVICE.
+ *   - One context is used from one stream at a time; contexts are not
+ *     thread-safe.  Data are FP32.
+ *
+ * Layouts (all contiguous, FP32):
+ *   x0     [3][7]        q0, v0, a0 (joint position, velocity, acceleration)
+ *   goal   [12]          goal rotation R_g (row-major 3x3), then position p_g
+ *   mean   [H][7]        Gaussian means of the controls (joint accelerations)
+ *   sigma2 [7]           per-joint control variance (shared over the horizon)
+ *   noise  [7][N][H]     standard-normal override (joint, particle, step)
+ *   u, q, v, a [7][N][H] controls and states (joint, particle, step)
+ *   c      [N][H]        running cost; terms [8][N][H] unweighted terms in the
+ *                        order pos, rot, joint, vel, stop, manip, self, env
+ *   C      [N]           horizon cost per particle
+ */
+#ifndef STORM_H
+#define STORM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STORM_DOF 7
+#define STORM_NFRAMES 8
+#define STORM_MAX_HORIZON 64
+#define STORM_MAX_SPHERES 64
+#define STORM_MAX_OBSTACLES 256
+#define STORM_MAX_PARTICLES (1 << 20)
+#define STORM_OBSTACLE_STRIDE 16
+#define STORM_NTERMS 8
+
+/* Status codes. */
+#define STORM_OK 0
+#define STORM_E_NULL (-1)        /* a required pointer is NULL */
+#define STORM_E_RANGE (-2)       /* a size is out of range (N, H, K, spheres, obstacles) */
+#define STORM_E_PARAM (-3)       /* a parameter is invalid (beta <= 0, dt <= 0, alpha outside [0,1], NaN) */
+#define STORM_E_DEVICE (-4)      /* a HIP call failed; the context is unusable */
+#define STORM_E_STATE (-5)       /* calls out of order (update without a step, ...) */
+#define STORM_E_NOMEM (-6)       /* device allocation failed */
+#define STORM_E_UNSUPPORTED (-7) /* valid request the library does not implement */
+
+/* Cost-term switches for the running cost (Sec. 3.2, Eq. 15). */
+#define STORM_COST_POSE (1u << 0)  /* Eq. 9 */
+#define STORM_COST_JOINT (1u << 1) /* Eq. 11 on positions */
+#define STORM_COST_VEL (1u << 2)   /* Eq. 11 form on velocities */
+#define STORM_COST_STOP (1u << 3)  /* Eq. 10 */
+#define STORM_COST_MANIP (1u << 4) /* Eq. 12 */
+#define STORM_COST_SELF (1u << 5)  /* Eq. 13, as sphere-pair penetration */
+#define STORM_COST_ENV (1u << 6)   /* Eq. 14, as sphere vs obstacle signed distance */
+#define STORM_COST_ALL 0x7Fu
+
+/* Asynchronous device status flags (storm_rollout_status). */
+#define STORM_FLAG_NONFINITE_COST (1u << 0) /* some C_i was NaN/Inf: update kept mu, sigma2 */
+#define STORM_FLAG_ZERO_WEIGHT (1u << 1)    /* weight sum not positive: update kept mu, sigma2 */
+
+/* Obstacle record kinds (first value of each 16-float record). */
+#define STORM_OBSTACLE_SPHERE 0 /* [0, cx, cy, cz, r, -, -, ...] */
+#define STORM_OBSTACLE_CUBOID 1 /* [1, cx, cy, cz, ex, ey, ez, R00..R22]: half extents, box-to-world R */
+
+/* Parameters of one MPC problem.  Sec. 2-3 name N, H, K, dt, beta, gamma and
+ * the step sizes; Sec. 3.2 the cost weights and thresholds; Sec. 3.3 the
+ * sampling strategy.  Particles [0, n_halton) use the Halton + cubic
+ * B-spline table (drawn once at init), [n_halton, n_particles - n_null) use
+ * Philox4x32-10 Gaussian noise, and the last n_null particles are
+ * zero-acceleration ("null") sequences. */
+typedef struct storm_params {
+    int32_t n_particles; /* N, 1 .. STORM_MAX_PARTICLES */
+    int32_t horizon;     /* H, 1 .. STORM_MAX_HORIZON */
+    int32_t n_halton;    /* 0 .. N - n_null */
+    int32_t n_null;      /* 0 .. N */
+    int32_t n_knots;     /* B-spline control points K, 4 .. 32 (ignored if n_halton = 0) */
+    uint32_t cost_mask;  /* STORM_COST_* */
+    uint64_t seed;       /* Philox key */
+    const float *dt;     /* host [H], each > 0 */
+    float sigma_init[STORM_DOF]; /* initial per-joint standard deviation, > 0 */
+    float beta;          /* temperature of Eq. 3/6, > 0 */
+    float gamma;         /* discount of Eq. 2, in [0, 1] */
+    float alpha_mu;      /* mean step size of Eq. 4, in [0, 1] */
+    float alpha_sigma;   /* covariance step size of Eq. 5, in [0, 1] */
+    float w_term;        /* terminal-step scale (terminal cost = running cost), >= 0 */
+    float sigma2_min;    /* variance floor, >= 0 */
+    float acc_stop;      /* maximum acceleration of the stop cost (Eq. 10), >= 0 */
+    float k_jl;          /* joint-limit safety ratio (Eq. 11), in [0, 0.5) */
+    float k_vl;          /* velocity-limit safety ratio, in [0, 0.5) */
+    float k_m;           /* manipulability threshold (Eq. 12) */
+    float w_pos, w_rot;  /* pose weights (position, orientation) of alpha_p */
+    float alpha_pos[3];  /* goal-frame axis weights of the position error (Eq. 9 alpha_2) */
+    float alpha_rot[3];  /* row weights of the rotation error (Eq. 9 alpha_1) */
+    float a_stop, a_joint, a_vel, a_manip, a_coll; /* Eq. 15 weights */
+} storm_params;
+
+/* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame
+ * 8 being the end-effector flange (theta = 0).  Row k of dh holds
+ * (a_{k-1}, d_k, alpha_{k-1}).  Spheres rows: (body 1..8, x, y, z, r) in the
+ * body frame, sorted by body; self-collision checks pairs on bodies at least
+ * two apart. */
+typedef struct storm_robot {
+    float dh[STORM_NFRAMES][3];
+    float q_min[STORM_DOF], q_max[STORM_DOF]; /* joint position limits */
+    float qd_max[STORM_DOF];                  /* joint speed limits */
+    int32_t n_spheres;                        /* 0 .. STORM_MAX_SPHERES */
+    const float *spheres;                     /* host [n_spheres][5] */
+} storm_robot;
+
+/* Static scene: obstacle records of STORM_OBSTACLE_STRIDE floats. */
+typedef struct storm_scene {
+    int32_t n_obstacles;     /* 0 .. STORM_MAX_OBSTACLES */
+    const float *obstacles;  /* host [n_obstacles][16] */
+} storm_scene;
+
+/* Optional per-step outputs (each pointer nullable, device memory). */
+typedef struct storm_debug {
+    float *u, *q, *v, *a; /* [7][N][H] */
+    float *c;             /* [N][H] */
+    float *terms;         /* [8][N][H] */
+} storm_debug;
+
+typedef struct storm_ctx_s *storm_ctx;
+
+/* Create a context for one problem (Alg. 1 set-up).  Copies params, robot and
+ * scene; allocates all device workspace; builds the dt, stop-velocity,
+ * horizon-weight and limit tables and the Halton + B-spline noise table on
+ * the device; sets mu = 0, sigma2 = sigma_init^2 and the step counter to 0.
+ * Synchronises `stream` before returning.  Not capturable.
+ * Errors: E_NULL, E_RANGE, E_PARAM, E_NOMEM, E_DEVICE. */
+int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const storm_robot *robot,
+                           const storm_scene *scene, void *stream);
+
+/* Sample + roll out (Alg. 1 sample_controls and generate_rollouts): controls
+ * u = mu + sigma * eps (Sec. 3.3), triple integrator (Eq. 7), FK and
+ * Jacobian (Eq. 8), running cost (Eq. 9-15) and horizon cost (Eq. 2).
+ * d_x0 [3][7] and d_goal [12] are read on the device.  d_noise (nullable)
+ * replaces the sampled standard noise of every non-null particle.  d_C
+ * (nullable) receives a copy of C [N].  dbg (nullable) selects extra
+ * outputs.  Errors: E_NULL, E_STATE (a step is pending its update), E_DEVICE. */
+int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_noise,
+                           const storm_debug *dbg, float *d_C, void *stream);
+
+/* Policy update (Alg. 1 update_distribution, Eq. 4-6) from the last step,
+ * then next_command: d_cmd [7] = updated mu_0.  d_mean [H][7] and d_sigma2
+ * [7] (nullable) receive the updated (unshifted) mean and variance.  With
+ * shift != 0 the stored mean is shifted one step and a zero mean appended
+ * (the warm start of the next control step); otherwise it is stored as is
+ * (for K > 1 iterations).  Non-finite costs or a zero weight sum keep mu and
+ * sigma2 and raise a status flag.  Increments the sampling step counter.
+ * Errors: E_NULL (d_cmd), E_STATE (no step since the last update), E_DEVICE. */
+int32_t storm_rollout_update(storm_ctx ctx, float *d_mean, float *d_sigma2, float *d_cmd, int32_t shift,
+                             void *stream);
+
+/* Free everything (synchronises the context's device first).  NULL is a no-op. */
+int32_t storm_rollout_destroy(storm_ctx ctx);
+
+/* Read and clear the asynchronous status flags (STORM_FLAG_*).  Synchronises
+ * `stream`; not for the hot loop. */
+int32_t storm_rollout_status(storm_ctx ctx, uint32_t *h_flags, void *stream);
+
+/* Read the policy state to host memory (mean [H][7], sigma2 [7], step
+ * counter); any pointer may be NULL.  Synchronises `stream`. */
+int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, uint32_t *h_step, void *stream);
+
+/* Restore the policy state from host memory (NULL pointers leave that part
+ * unchanged).  Clears a pending step.  Synchronises `stream`. */
+int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float *h_sigma2, const uint32_t *h_step,
+                                void *stream);
+
+/* Batched forward kinematics of the robot (Sec. 3.1, Eq. 8): for n joint
+ * configurations d_q [7][n], writes the flange pose d_pose [12][n] (R
+ * row-major, then p) and, if d_manip is not NULL, the manipulability
+ * sqrt(det(J J^T)) (Eq. 12) [n].  Errors: E_NULL, E_RANGE (n < 0), E_DEVICE. */
+int32_t storm_fk(const storm_robot *robot, const float *d_q, int32_t n, float *d_pose, float *d_manip,
+                 void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *storm_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STORM_H */

@@ -1,0 +1,459 @@
+// C ABI of the STORM MPPI library: validation, device workspace and launch
+// order for init / step / update / destroy (Alg. 1), status and state I/O.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "storm_internal.h"
+
+using namespace storm;
+
+struct storm_ctx_s {
+    int device = 0;
+    int waves = 16;
+    int32_t error = STORM_OK;  // sticky device error
+    bool pending = false;      // a step waits for its update
+    storm_params params{};
+    ProblemDev P{};
+    RobotDev R{};
+    std::vector<void *> allocs;  // every device allocation of this context
+};
+
+namespace {
+
+bool finite_f(float x) { return isfinite(x) != 0; }
+
+int32_t validate_robot(const storm_robot *robot)
+{
+    if (!robot) return STORM_E_NULL;
+    if (robot->n_spheres < 0 || robot->n_spheres > STORM_MAX_SPHERES) return STORM_E_RANGE;
+    if (robot->n_spheres > 0 && !robot->spheres) return STORM_E_NULL;
+    for (int k = 0; k < STORM_NFRAMES; ++k)
+        for (int c = 0; c < 3; ++c)
+            if (!finite_f(robot->dh[k][c])) return STORM_E_PARAM;
+    for (int j = 0; j < STORM_DOF; ++j) {
+        if (!finite_f(robot->q_min[j]) || !finite_f(robot->q_max[j]) || !(robot->q_min[j] < robot->q_max[j]))
+            return STORM_E_PARAM;
+        if (!finite_f(robot->qd_max[j]) || !(robot->qd_max[j] > 0.0f)) return STORM_E_PARAM;
+    }
+    for (int s = 0; s < robot->n_spheres; ++s) {
+        const float *r = robot->spheres + 5 * s;
+        const int b = (int)r[0];
+        if ((float)b != r[0] || b < 1 || b > STORM_NFRAMES) return STORM_E_PARAM;
+        if (s > 0 && r[0] < robot->spheres[5 * (s - 1)]) return STORM_E_PARAM;  // sorted by body
+        for (int c = 1; c < 5; ++c)
+            if (!finite_f(r[c])) return STORM_E_PARAM;
+        if (!(r[4] > 0.0f)) return STORM_E_PARAM;
+    }
+    return STORM_OK;
+}
+
+int32_t validate_scene(const storm_scene *scene)
+{
+    if (!scene) return STORM_OK;  // no obstacles
+    if (scene->n_obstacles < 0 || scene->n_obstacles > STORM_MAX_OBSTACLES) return STORM_E_RANGE;
+    if (scene->n_obstacles > 0 && !scene->obstacles) return STORM_E_NULL;
+    for (int o = 0; o < scene->n_obstacles; ++o) {
+        const float *r = scene->obstacles + STORM_OBSTACLE_STRIDE * o;
+        for (int c = 0; c < STORM_OBSTACLE_STRIDE; ++c)
+            if (!finite_f(r[c])) return STORM_E_PARAM;
+        if (r[0] == (float)STORM_OBSTACLE_SPHERE) {
+            if (!(r[4] > 0.0f)) return STORM_E_PARAM;
+        } else if (r[0] == (float)STORM_OBSTACLE_CUBOID) {
+            if (!(r[4] > 0.0f && r[5] > 0.0f && r[6] > 0.0f)) return STORM_E_PARAM;
+        } else {
+            return STORM_E_PARAM;
+        }
+    }
+    return STORM_OK;
+}
+
+int32_t validate_params(const storm_params *p)
+{
+    if (!p) return STORM_E_NULL;
+    if (p->n_particles < 1 || p->n_particles > STORM_MAX_PARTICLES) return STORM_E_RANGE;
+    if (p->horizon < 1 || p->horizon > STORM_MAX_HORIZON) return STORM_E_RANGE;
+    if (p->n_null < 0 || p->n_null > p->n_particles) return STORM_E_RANGE;
+    if (p->n_halton < 0 || p->n_halton > p->n_particles - p->n_null) return STORM_E_RANGE;
+    if (p->n_halton > 0 && (p->n_knots < 4 || p->n_knots > 32)) return STORM_E_RANGE;
+    if (p->cost_mask & ~STORM_COST_ALL) return STORM_E_PARAM;
+    if (!p->dt) return STORM_E_NULL;
+    for (int h = 0; h < p->horizon; ++h)
+        if (!finite_f(p->dt[h]) || !(p->dt[h] > 0.0f)) return STORM_E_PARAM;
+    for (int j = 0; j < STORM_DOF; ++j)
+        if (!finite_f(p->sigma_init[j]) || !(p->sigma_init[j] > 0.0f)) return STORM_E_PARAM;
+    const float scalars[] = {p->beta,  p->gamma, p->alpha_mu, p->alpha_sigma, p->w_term, p->sigma2_min,
+                             p->acc_stop, p->k_jl, p->k_vl, p->k_m, p->w_pos, p->w_rot,
+                             p->a_stop, p->a_joint, p->a_vel, p->a_manip, p->a_coll};
+    for (float s : scalars)
+        if (!finite_f(s)) return STORM_E_PARAM;
+    for (int c = 0; c < 3; ++c)
+        if (!finite_f(p->alpha_pos[c]) || !finite_f(p->alpha_rot[c])) return STORM_E_PARAM;
+    if (!(p->beta > 0.0f)) return STORM_E_PARAM;
+    if (p->gamma < 0.0f || p->gamma > 1.0f) return STORM_E_PARAM;
+    if (p->alpha_mu < 0.0f || p->alpha_mu > 1.0f) return STORM_E_PARAM;
+    if (p->alpha_sigma < 0.0f || p->alpha_sigma > 1.0f) return STORM_E_PARAM;
+    if (p->w_term < 0.0f || p->sigma2_min < 0.0f || p->acc_stop < 0.0f) return STORM_E_PARAM;
+    if (p->k_jl < 0.0f || p->k_jl >= 0.5f || p->k_vl < 0.0f || p->k_vl >= 0.5f) return STORM_E_PARAM;
+    return STORM_OK;
+}
+
+// Robot constants in device form.  cos/sin of the DH twist are formed in
+// double; values within 1e-12 of 0 or +-1 are snapped so that the usual
+// twists of +-pi/2 give exact axis permutations.
+void fill_robot_consts(const storm_robot *robot, RobotDev &R)
+{
+    for (int k = 0; k < STORM_NFRAMES; ++k) {
+        double c = cos((double)robot->dh[k][2]), s = sin((double)robot->dh[k][2]);
+        if (fabs(c) < 1e-12) c = 0.0;
+        if (fabs(s) < 1e-12) s = 0.0;
+        if (fabs(fabs(c) - 1.0) < 1e-12) c = c > 0 ? 1.0 : -1.0;
+        if (fabs(fabs(s) - 1.0) < 1e-12) s = s > 0 ? 1.0 : -1.0;
+        R.ca[k] = (float)c;
+        R.sa[k] = (float)s;
+        R.a[k] = robot->dh[k][0];
+        R.d[k] = robot->dh[k][1];
+    }
+    R.n_spheres = robot->n_spheres;
+}
+
+// Index list of sphere pairs on bodies at least two apart (self-collision set).
+std::vector<int> self_pairs(const storm_robot *robot)
+{
+    std::vector<int> idx;
+    for (int s = 0; s < robot->n_spheres; ++s)
+        for (int t = s + 1; t < robot->n_spheres; ++t) {
+            const int bs = (int)robot->spheres[5 * s], bt = (int)robot->spheres[5 * t];
+            if (abs(bs - bt) >= 2) {
+                idx.push_back(s);
+                idx.push_back(t);
+            }
+        }
+    return idx;
+}
+
+template <typename T>
+hipError_t dalloc(storm_ctx c, T **ptr, size_t count)
+{
+    void *p = nullptr;
+    const size_t bytes = count > 0 ? count * sizeof(T) : 16;
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    c->allocs.push_back(p);
+    *ptr = static_cast<T *>(p);
+    return hipSuccess;
+}
+
+void free_all(storm_ctx c)
+{
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+int32_t map_error(hipError_t e) { return e == hipErrorOutOfMemory ? STORM_E_NOMEM : STORM_E_DEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+const char *storm_status_str(int32_t status)
+{
+    switch (status) {
+    case STORM_OK: return "ok";
+    case STORM_E_NULL: return "null pointer";
+    case STORM_E_RANGE: return "size out of range";
+    case STORM_E_PARAM: return "invalid parameter";
+    case STORM_E_DEVICE: return "device error";
+    case STORM_E_STATE: return "call out of order";
+    case STORM_E_NOMEM: return "out of device memory";
+    case STORM_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const storm_robot *robot,
+                           const storm_scene *scene, void *stream)
+{
+    if (!out) return STORM_E_NULL;
+    *out = nullptr;
+    int32_t st = validate_params(params);
+    if (st != STORM_OK) return st;
+    st = validate_robot(robot);
+    if (st != STORM_OK) return st;
+    st = validate_scene(scene);
+    if (st != STORM_OK) return st;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    storm_ctx c = new (std::nothrow) storm_ctx_s();
+    if (!c) return STORM_E_NOMEM;
+    c->params = *params;
+    c->params.dt = nullptr;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return STORM_E_DEVICE;
+    }
+    if (storm::set_rollout_lds_limit() != hipSuccess) {
+        delete c;
+        return STORM_E_DEVICE;
+    }
+
+    const int N = params->n_particles, H = params->horizon;
+    const int n_obs = scene ? scene->n_obstacles : 0;
+    std::vector<float> sph_raw, box_raw, obs_sorted;
+    int n_sph_obs = 0, n_box_obs = 0;
+    for (int o = 0; o < n_obs; ++o) {
+        const float *r = scene->obstacles + STORM_OBSTACLE_STRIDE * o;
+        if (r[0] == (float)STORM_OBSTACLE_SPHERE) ++n_sph_obs; else ++n_box_obs;
+    }
+    const std::vector<int> pair_idx = self_pairs(robot);
+    const int n_pairs = (int)pair_idx.size() / 2;
+
+    ProblemDev &P = c->P;
+    P.N = N;
+    P.H = H;
+    P.n_halton = params->n_halton;
+    P.n_null = params->n_null;
+    P.n_sph_obs = n_sph_obs;
+    P.n_box_obs = n_box_obs;
+    P.ppt = storm::kLanes / H;
+    P.n_tiles = (N + P.ppt - 1) / P.ppt;
+    P.cost_mask = params->cost_mask;
+    P.seed_lo = (uint32_t)params->seed;
+    P.seed_hi = (uint32_t)(params->seed >> 32);
+    P.beta = params->beta;
+    P.alpha_mu = params->alpha_mu;
+    P.alpha_sigma = params->alpha_sigma;
+    P.sigma2_min = params->sigma2_min;
+    P.k_m = params->k_m;
+    P.w_pos = params->w_pos;
+    P.w_rot = params->w_rot;
+    P.a_stop = params->a_stop;
+    P.a_joint = params->a_joint;
+    P.a_vel = params->a_vel;
+    P.a_manip = params->a_manip;
+    P.a_coll = params->a_coll;
+    for (int k = 0; k < 3; ++k) {
+        P.alpha_pos[k] = params->alpha_pos[k];
+        P.alpha_rot[k] = params->alpha_rot[k];
+    }
+    fill_robot_consts(robot, c->R);
+    c->R.n_pairs = n_pairs;
+
+    float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
+    float4 *sph_obs, *sph_local;
+    int32_t *sph_body;
+    int4 *pairs;
+    int2 *pair_idx_d;
+    uint32_t *counters;
+    hipError_t e = hipSuccess;
+#define STORM_TRY(expr)        \
+    do {                       \
+        e = (expr);            \
+        if (e != hipSuccess) { \
+            goto fail;         \
+        }                      \
+    } while (0)
+    STORM_TRY(dalloc(c, &tables, storm::kTabSize));
+    STORM_TRY(dalloc(c, &halton, (size_t)STORM_DOF * params->n_halton * H));
+    STORM_TRY(dalloc(c, &sph_obs, (size_t)n_sph_obs));
+    STORM_TRY(dalloc(c, &box_obs, (size_t)16 * n_box_obs));
+    STORM_TRY(dalloc(c, &mean, (size_t)H * STORM_DOF));
+    STORM_TRY(dalloc(c, &sigma2, (size_t)STORM_DOF));
+    STORM_TRY(dalloc(c, &u, (size_t)STORM_DOF * N * H));
+    STORM_TRY(dalloc(c, &C, (size_t)N));
+    STORM_TRY(dalloc(c, &counters, (size_t)2));
+    STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
+    STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
+    STORM_TRY(dalloc(c, &pairs, (size_t)n_pairs));
+    // staging copies of the host inputs (freed at destroy with the rest)
+    STORM_TRY(dalloc(c, &dt_raw, (size_t)H));
+    STORM_TRY(dalloc(c, &lim_raw, (size_t)3 * STORM_DOF));
+    STORM_TRY(dalloc(c, &sig_raw, (size_t)STORM_DOF));
+    STORM_TRY(dalloc(c, &obs_raw, (size_t)STORM_OBSTACLE_STRIDE * n_obs));
+    STORM_TRY(dalloc(c, &sph_raw_d, (size_t)5 * robot->n_spheres));
+    STORM_TRY(dalloc(c, &pair_idx_d, (size_t)n_pairs));
+    {
+        float lim[3 * STORM_DOF];
+        for (int j = 0; j < STORM_DOF; ++j) {
+            lim[j] = robot->q_min[j];
+            lim[STORM_DOF + j] = robot->q_max[j];
+            lim[2 * STORM_DOF + j] = robot->qd_max[j];
+        }
+        STORM_TRY(hipMemcpyAsync(dt_raw, params->dt, sizeof(float) * H, hipMemcpyHostToDevice, s));
+        STORM_TRY(hipMemcpyAsync(lim_raw, lim, sizeof(lim), hipMemcpyHostToDevice, s));
+        STORM_TRY(hipMemcpyAsync(sig_raw, params->sigma_init, sizeof(float) * STORM_DOF, hipMemcpyHostToDevice, s));
+        if (n_obs > 0)
+            STORM_TRY(hipMemcpyAsync(obs_raw, scene->obstacles, sizeof(float) * STORM_OBSTACLE_STRIDE * n_obs,
+                                     hipMemcpyHostToDevice, s));
+        if (robot->n_spheres > 0)
+            STORM_TRY(hipMemcpyAsync(sph_raw_d, robot->spheres, sizeof(float) * 5 * robot->n_spheres,
+                                     hipMemcpyHostToDevice, s));
+        if (n_pairs > 0)
+            STORM_TRY(hipMemcpyAsync(pair_idx_d, pair_idx.data(), sizeof(int) * pair_idx.size(),
+                                     hipMemcpyHostToDevice, s));
+        P.tables = tables;
+        P.halton = halton;
+        P.sph_obs = sph_obs;
+        P.box_obs = box_obs;
+        P.mean = mean;
+        P.sigma2 = sigma2;
+        P.u = u;
+        P.C = C;
+        P.step = counters;
+        P.status = counters + 1;
+        c->R.sph_local = sph_local;
+        c->R.sph_body = sph_body;
+        c->R.pairs = pairs;
+        STORM_TRY(storm::launch_init_tables(P, dt_raw, lim_raw, params->acc_stop, params->gamma, params->w_term,
+                                            params->k_jl, params->k_vl, sig_raw, params->n_knots, obs_raw, n_obs,
+                                            sph_obs, box_obs, sph_raw_d, robot->n_spheres, sph_local, sph_body,
+                                            pairs, pair_idx_d, n_pairs, s));
+        STORM_TRY(hipStreamSynchronize(s));
+    }
+#undef STORM_TRY
+    *out = c;
+    return STORM_OK;
+fail:
+    (void)hipStreamSynchronize(s);
+    free_all(c);
+    delete c;
+    return map_error(e);
+}
+
+int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_noise,
+                           const storm_debug *dbg, float *d_C, void *stream)
+{
+    if (!ctx || !d_x0 || !d_goal) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    StepOut out{};
+    if (dbg) {
+        out.u = dbg->u;
+        out.q = dbg->q;
+        out.v = dbg->v;
+        out.a = dbg->a;
+        out.c = dbg->c;
+        out.terms = dbg->terms;
+    }
+    out.C = d_C;
+    const hipError_t e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, d_noise, out, ctx->waves,
+                                               static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    ctx->pending = true;
+    return STORM_OK;
+}
+
+int32_t storm_rollout_update(storm_ctx ctx, float *d_mean, float *d_sigma2, float *d_cmd, int32_t shift,
+                             void *stream)
+{
+    if (!ctx || !d_cmd) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    if (!ctx->pending) return STORM_E_STATE;
+    const hipError_t e = storm::launch_update(ctx->P, d_mean, d_sigma2, d_cmd, shift != 0,
+                                              static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    ctx->pending = false;
+    return STORM_OK;
+}
+
+int32_t storm_rollout_destroy(storm_ctx ctx)
+{
+    if (!ctx) return STORM_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_all(ctx);
+    (void)hipSetDevice(prev);
+    delete ctx;
+    return STORM_OK;
+}
+
+int32_t storm_rollout_status(storm_ctx ctx, uint32_t *h_flags, void *stream)
+{
+    if (!ctx || !h_flags) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, ctx->P.status, sizeof(v), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const uint32_t zero = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->P.status, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    *h_flags = v;
+    return STORM_OK;
+}
+
+int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, uint32_t *h_step, void *stream)
+{
+    if (!ctx) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (h_mean)
+        e = hipMemcpyAsync(h_mean, ctx->P.mean, sizeof(float) * ctx->P.H * STORM_DOF, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && h_sigma2)
+        e = hipMemcpyAsync(h_sigma2, ctx->P.sigma2, sizeof(float) * STORM_DOF, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && h_step) e = hipMemcpyAsync(h_step, ctx->P.step, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    return STORM_OK;
+}
+
+int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float *h_sigma2, const uint32_t *h_step,
+                                void *stream)
+{
+    if (!ctx) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    if (h_mean)
+        for (int k = 0; k < ctx->P.H * STORM_DOF; ++k)
+            if (!finite_f(h_mean[k])) return STORM_E_PARAM;
+    if (h_sigma2)
+        for (int j = 0; j < STORM_DOF; ++j)
+            if (!finite_f(h_sigma2[j]) || h_sigma2[j] < 0.0f) return STORM_E_PARAM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (h_mean)
+        e = hipMemcpyAsync(ctx->P.mean, h_mean, sizeof(float) * ctx->P.H * STORM_DOF, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && h_sigma2)
+        e = hipMemcpyAsync(ctx->P.sigma2, h_sigma2, sizeof(float) * STORM_DOF, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && h_step) e = hipMemcpyAsync(ctx->P.step, h_step, sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    ctx->pending = false;
+    return STORM_OK;
+}
+
+int32_t storm_fk(const storm_robot *robot, const float *d_q, int32_t n, float *d_pose, float *d_manip, void *stream)
+{
+    if (!robot) return STORM_E_NULL;
+    if (n < 0) return STORM_E_RANGE;
+    if (n > 0 && (!d_q || !d_pose)) return STORM_E_NULL;
+    for (int k = 0; k < STORM_NFRAMES; ++k)
+        for (int c = 0; c < 3; ++c)
+            if (!finite_f(robot->dh[k][c])) return STORM_E_PARAM;
+    RobotDev R{};
+    fill_robot_consts(robot, R);
+    R.n_spheres = 0;
+    const hipError_t e = storm::launch_fk(R, d_q, n, d_pose, d_manip, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? STORM_OK : STORM_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Device kinematics shared by the rollout and FK kernels: one modified-DH
+// link transform (Sec. 3.1, Eq. 8) and the manipulability measure of Eq. 12.
+#pragma once
+
+#include "storm_internal.h"
+
+namespace storm {
+
+// F <- F RotX(alpha) TransX(a) RotZ(theta) TransZ(d) for a frame held as a
+// row-major rotation r[9] and origin p[3].  RotX mixes rotation columns 1 and
+// 2, RotZ mixes columns 0 and 1, the translations move the origin along the
+// current x and z axes.
+__device__ __forceinline__ void dh_step(float r[9], float p[3], float ca, float sa, float a, float d, float ct,
+                                        float st)
+{
+#pragma unroll
+    for (int row = 0; row < 3; ++row) {
+        const float y = r[row * 3 + 1], z = r[row * 3 + 2];
+        r[row * 3 + 1] = fmaf(ca, y, sa * z);
+        r[row * 3 + 2] = fmaf(-sa, y, ca * z);
+    }
+#pragma unroll
+    for (int row = 0; row < 3; ++row) p[row] = fmaf(a, r[row * 3 + 0], p[row]);
+#pragma unroll
+    for (int row = 0; row < 3; ++row) {
+        const float x = r[row * 3 + 0], y = r[row * 3 + 1];
+        r[row * 3 + 0] = fmaf(ct, x, st * y);
+        r[row * 3 + 1] = fmaf(-st, x, ct * y);
+    }
+#pragma unroll
+    for (int row = 0; row < 3; ++row) p[row] = fmaf(d, r[row * 3 + 2], p[row]);
+}
+
+// sqrt(det(J J^T)) for the geometric Jacobian whose column k is
+// [z_k x (p_e - o_k); z_k].  J J^T (6x6, symmetric positive semi-definite) is
+// accumulated over the seven columns and factorised as L D L^T; the
+// determinant is the product of the pivots.  A non-positive pivot means a
+// singular configuration (m = 0).
+__device__ __forceinline__ float manipulability(const float z[kDof][3], const float o[kDof][3], const float pe[3])
+{
+    float M[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) M[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kDof; ++k) {
+        const float rx = pe[0] - o[k][0], ry = pe[1] - o[k][1], rz = pe[2] - o[k][2];
+        float col[6];
+        col[0] = z[k][1] * rz - z[k][2] * ry;
+        col[1] = z[k][2] * rx - z[k][0] * rz;
+        col[2] = z[k][0] * ry - z[k][1] * rx;
+        col[3] = z[k][0];
+        col[4] = z[k][1];
+        col[5] = z[k][2];
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                const int idx = i * (i + 1) / 2 + j;
+                M[idx] = fmaf(col[i], col[j], M[idx]);
+            }
+    }
+    // L D L^T in place on the packed lower triangle: after step i, M(i,i)
+    // holds D_i and M(j,i) (j > i) holds L_ji.
+    float det = 1.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const int ii = i * (i + 1) / 2 + i;
+        float di = M[ii];
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            const float lik = M[i * (i + 1) / 2 + k];
+            di = fmaf(-lik * lik, M[k * (k + 1) / 2 + k], di);
+        }
+        M[ii] = di;
+        det *= di;
+        const float inv = di > 0.0f ? 1.0f / di : 0.0f;
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+            float s = M[j * (j + 1) / 2 + i];
+#pragma unroll
+            for (int k = 0; k < i; ++k)
+                s = fmaf(-M[j * (j + 1) / 2 + k] * M[i * (i + 1) / 2 + k], M[k * (k + 1) / 2 + k], s);
+            M[j * (j + 1) / 2 + i] = s * inv;
+        }
+        if (!(di > 0.0f)) det = 0.0f;
+    }
+    return det > 0.0f ? sqrtf(det) : 0.0f;
+}
+
+}  // namespace storm

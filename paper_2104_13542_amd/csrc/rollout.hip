@@ -1,0 +1,373 @@
+// Kernel R: sample -> integrate -> kinematics -> running cost -> horizon cost
+// for one MPC problem (STORM, Sec. 3.1-3.3, Eq. 2 and 7-15).
+//
+// Work decomposition.  A tile is one 64-lane point set holding
+// ppt = floor(64 / H) whole particles, lane = particle_in_tile * H + step.
+// One workgroup of W wavefronts owns one tile; the waves split the work of
+// the tile's 64 (particle, step) points and exchange data through LDS:
+//   A0  waves 0-1  standard noise: one Philox4x32-10 call gives four normals
+//                  (joints 4k..4k+3); or the Halton table; or the override
+//   A1  waves 0-6  one joint each: u = mu + sigma eps, then the two
+//                  segmented prefix sums of the triple integrator (Eq. 7) as
+//                  wavefront shuffle scans over the particle's lanes
+//   B   wave 0     forward kinematics (Eq. 8), eight frames to LDS
+//       wave 1     joint / velocity / stop costs (Eq. 10-11)
+//   C   all waves  world centres of the body spheres to LDS
+//   D   all waves  environment (spheres x obstacles) and self-collision
+//                  (sphere pairs) split over waves; pose cost (Eq. 9) and
+//                  manipulability (Eq. 12) on the last two waves
+//   E   wave 0     weighted running cost (Eq. 15), horizon sum (Eq. 2)
+// Obstacle, sphere and pair records are indexed by wave-uniform loop
+// counters, so they are fetched with scalar loads into SGPRs; every per-point
+// LDS array is [row][lane] (conflict-free).  Reductions run in a fixed order:
+// results are bitwise reproducible.
+#include "kinematics.h"
+
+namespace storm {
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products with the Weyl key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                              uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Box-Muller on 24-bit uniforms u1 in (0, 1], u2 in [0, 1).
+__device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float &zc, float &zs)
+{
+    const float u1 = (float)((x0 >> 8) + 1u) * 0x1.0p-24f;
+    const float u2 = (float)(x1 >> 8) * 0x1.0p-24f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    zc = r * c;
+    zs = r * s;
+}
+
+// Inclusive prefix sum over the lanes of one particle (lanes p*H .. p*H+H-1),
+// Kogge-Stone with wavefront shuffles; h = step index of this lane.
+__device__ __forceinline__ float segmented_scan(float x, int h, int H)
+{
+    for (int off = 1; off < H; off <<= 1) {
+        const float y = __shfl_up(x, (unsigned)off, kLanes);
+        if (h >= off) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float hinge_box(float x, float lo, float hi)
+{
+    return fmaxf(lo - x, 0.0f) + fmaxf(x - hi, 0.0f);
+}
+
+template <int W>
+__global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, RobotDev R,
+                                                             const float *__restrict__ x0,
+                                                             const float *__restrict__ goal,
+                                                             const float *__restrict__ noise, StepOut out)
+{
+    extern __shared__ float smem[];
+    const int S = R.n_spheres;
+    float *s_eps = smem;                    // [8][64]
+    float *s_q = s_eps + 8 * kLanes;        // [7][64]
+    float *s_v = s_q + kDof * kLanes;       // [7][64]
+    float *s_fr = s_v + kDof * kLanes;      // [8 frames][12][64]: R row-major, p
+    float *s_cen = s_fr + 96 * kLanes;      // [S][3][64]
+    float *s_penv = s_cen + 3 * S * kLanes; // [W][64]
+    float *s_pself = s_penv + W * kLanes;   // [W][64]
+    float *s_terms = s_pself + W * kLanes;  // [8][64]
+    float *s_cw = s_terms + 8 * kLanes;     // [64]
+
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int N = P.N, H = P.H;
+    const int pl = lane / H;
+    const int h = lane - pl * H;
+    const int i = blockIdx.x * P.ppt + pl;
+    const bool valid = pl < P.ppt && i < N;
+    const bool live = valid && i < N - P.n_null;  // sampled (non-null) particle
+    const uint32_t mask = P.cost_mask;
+    const float *__restrict__ tab = P.tables;
+
+    // ---- A0: standard noise ------------------------------------------------
+    if (wave < 2) {
+        const int j0 = wave * 4;
+        float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (live) {
+            if (noise != nullptr) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (j0 + m < kDof) e[m] = noise[((size_t)(j0 + m) * N + i) * H + h];
+            } else if (i < P.n_halton) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (j0 + m < kDof) e[m] = P.halton[((size_t)(j0 + m) * P.n_halton + i) * H + h];
+            } else {
+                uint32_t c0 = (uint32_t)i, c1 = (uint32_t)h, c2 = (uint32_t)wave, c3 = *P.step;
+                philox4x32_10(c0, c1, c2, c3, P.seed_lo, P.seed_hi);
+                box_muller(c0, c1, e[0], e[1]);
+                box_muller(c2, c3, e[2], e[3]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) s_eps[(j0 + m) * kLanes + lane] = e[m];
+    }
+    __syncthreads();
+
+    // ---- A1: controls and the triple integrator (Eq. 7) ---------------------
+    if (wave < kDof) {
+        const int j = wave;
+        float u = 0.0f;
+        if (live) u = fmaf(sqrtf(P.sigma2[j]), s_eps[j * kLanes + lane], P.mean[h * kDof + j]);
+        const float dt = tab[kTabDt + h];
+        const float v = x0[kDof + j] + segmented_scan(dt * u, h, H);
+        const float q = x0[j] + segmented_scan(dt * v, h, H);
+        s_q[j * kLanes + lane] = q;
+        s_v[j * kLanes + lane] = v;
+        if (valid) {
+            const size_t o = ((size_t)j * N + i) * H + h;
+            P.u[o] = u;
+            if (out.u) out.u[o] = u;
+            if (out.q) out.q[o] = q;
+            if (out.v) out.v[o] = v;
+            if (out.a) out.a[o] = u;
+        }
+    }
+    __syncthreads();
+
+    // ---- B: forward kinematics | limit costs --------------------------------
+    if (wave == 0) {
+        float r[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+        float p[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int f = 0; f < kFrames; ++f) {
+            float st = 0.0f, ct = 1.0f;
+            if (f < kDof) sincosf(s_q[f * kLanes + lane], &st, &ct);
+            dh_step(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) s_fr[(f * 12 + c) * kLanes + lane] = r[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_fr[(f * 12 + 9 + c) * kLanes + lane] = p[c];
+        }
+    } else if (wave == 1) {
+        float ej = 0.0f, ev = 0.0f, es = 0.0f;
+        const float vs = tab[kTabVstop + h];
+#pragma unroll
+        for (int j = 0; j < kDof; ++j) {
+            const float q = s_q[j * kLanes + lane], v = s_v[j * kLanes + lane];
+            const float a = hinge_box(q, tab[kTabJlo + j], tab[kTabJhi + j]);
+            const float b = hinge_box(v, tab[kTabVlo + j], tab[kTabVhi + j]);
+            const float c = fmaxf(fabsf(v) - vs, 0.0f);
+            ej = fmaf(a, a, ej);
+            ev = fmaf(b, b, ev);
+            es = fmaf(c, c, es);
+        }
+        s_terms[2 * kLanes + lane] = sqrtf(ej);
+        s_terms[3 * kLanes + lane] = sqrtf(ev);
+        s_terms[4 * kLanes + lane] = sqrtf(es);
+    }
+    __syncthreads();
+
+    // ---- C: world centres of the body spheres --------------------------------
+    const bool need_centres = (mask & (STORM_COST_SELF | STORM_COST_ENV)) != 0;
+    if (need_centres) {
+        for (int s = wave; s < S; s += W) {
+            const float4 sl = R.sph_local[s];
+            const float *F = s_fr + R.sph_body[s] * 12 * kLanes + lane;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                s_cen[(s * 3 + c) * kLanes + lane] =
+                    fmaf(F[(c * 3 + 0) * kLanes], sl.x,
+                         fmaf(F[(c * 3 + 1) * kLanes], sl.y, fmaf(F[(c * 3 + 2) * kLanes], sl.z, F[(9 + c) * kLanes])));
+        }
+        __syncthreads();
+    }
+
+    // ---- D: collision terms, pose, manipulability -----------------------------
+    float env = 0.0f, selfpen = 0.0f;
+    if (mask & STORM_COST_ENV) {
+        for (int s = wave; s < S; s += W) {
+            const float x = s_cen[(s * 3 + 0) * kLanes + lane];
+            const float y = s_cen[(s * 3 + 1) * kLanes + lane];
+            const float z = s_cen[(s * 3 + 2) * kLanes + lane];
+            const float rs = R.sph_local[s].w;
+            const float rs2 = rs * rs;
+            float best = 0.0f;
+            for (int o = 0; o < P.n_sph_obs; ++o) {
+                const float4 ob = P.sph_obs[o];
+                const float dx = x - ob.x, dy = y - ob.y, dz = z - ob.z;
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float rr = rs + ob.w;
+                if (d2 < rr * rr) best = fmaxf(best, rr - sqrtf(d2));
+            }
+            for (int o = 0; o < P.n_box_obs; ++o) {
+                const float *b = P.box_obs + o * 16;
+                const float lx = fmaf(b[0], x, fmaf(b[1], y, fmaf(b[2], z, b[9])));
+                const float ly = fmaf(b[3], x, fmaf(b[4], y, fmaf(b[5], z, b[10])));
+                const float lz = fmaf(b[6], x, fmaf(b[7], y, fmaf(b[8], z, b[11])));
+                const float qx = fabsf(lx) - b[12], qy = fabsf(ly) - b[13], qz = fabsf(lz) - b[14];
+                const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
+                const float out2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+                if (out2 < rs2) {
+                    const float sdf = sqrtf(out2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);
+                    best = fmaxf(best, rs - sdf);
+                }
+            }
+            env += best;
+        }
+    }
+    if (mask & STORM_COST_SELF) {
+        const int np = R.n_pairs;
+        const int k0 = (int)(((long long)np * wave) / W), k1 = (int)(((long long)np * (wave + 1)) / W);
+        for (int k = k0; k < k1; ++k) {
+            const int4 pr = R.pairs[k];
+            const float dx = s_cen[(pr.x * 3 + 0) * kLanes + lane] - s_cen[(pr.y * 3 + 0) * kLanes + lane];
+            const float dy = s_cen[(pr.x * 3 + 1) * kLanes + lane] - s_cen[(pr.y * 3 + 1) * kLanes + lane];
+            const float dz = s_cen[(pr.x * 3 + 2) * kLanes + lane] - s_cen[(pr.y * 3 + 2) * kLanes + lane];
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (d2 < __int_as_float(pr.w)) selfpen = fmaxf(selfpen, __int_as_float(pr.z) - sqrtf(d2));
+        }
+    }
+    s_penv[wave * kLanes + lane] = env;
+    s_pself[wave * kLanes + lane] = selfpen;
+
+    if (wave == W - 1 && (mask & STORM_COST_POSE)) {
+        // Eq. 9: rotation error |diag(alpha_rot)(I - R_g^T R)|_F and position
+        // error |diag(alpha_pos) R_g^T (p - p_g)|.
+        const float *E = s_fr + 7 * 12 * kLanes + lane;
+        float Re[9], pe[3];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Re[c] = E[c * kLanes];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pe[c] = E[(9 + c) * kLanes];
+        float rot2 = 0.0f, pos2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float m = fmaf(goal[0 * 3 + r], Re[0 * 3 + c],
+                                     fmaf(goal[1 * 3 + r], Re[1 * 3 + c], goal[2 * 3 + r] * Re[2 * 3 + c]));
+                const float e = P.alpha_rot[r] * ((r == c ? 1.0f : 0.0f) - m);
+                rot2 = fmaf(e, e, rot2);
+            }
+            const float l = fmaf(goal[0 * 3 + r], pe[0] - goal[9],
+                                 fmaf(goal[1 * 3 + r], pe[1] - goal[10], goal[2 * 3 + r] * (pe[2] - goal[11])));
+            const float e = P.alpha_pos[r] * l;
+            pos2 = fmaf(e, e, pos2);
+        }
+        s_terms[0 * kLanes + lane] = sqrtf(pos2);
+        s_terms[1 * kLanes + lane] = sqrtf(rot2);
+    }
+    if (wave == W - 2 && (mask & STORM_COST_MANIP)) {
+        float z[kDof][3], o[kDof][3], pe[3];
+#pragma unroll
+        for (int k = 0; k < kDof; ++k) {
+            const float *F = s_fr + k * 12 * kLanes + lane;
+            z[k][0] = F[2 * kLanes];
+            z[k][1] = F[5 * kLanes];
+            z[k][2] = F[8 * kLanes];
+            o[k][0] = F[9 * kLanes];
+            o[k][1] = F[10 * kLanes];
+            o[k][2] = F[11 * kLanes];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pe[c] = s_fr[(7 * 12 + 9 + c) * kLanes + lane];
+        s_terms[5 * kLanes + lane] = manipulability(z, o, pe);
+    }
+    __syncthreads();
+
+    // ---- E: running cost (Eq. 15) and horizon cost (Eq. 2) ------------------
+    if (wave == 0) {
+        float t[kTerms];
+#pragma unroll
+        for (int k = 0; k < kTerms; ++k) t[k] = 0.0f;
+        if (mask & STORM_COST_POSE) {
+            t[0] = s_terms[0 * kLanes + lane];
+            t[1] = s_terms[1 * kLanes + lane];
+        }
+        if (mask & STORM_COST_JOINT) t[2] = s_terms[2 * kLanes + lane];
+        if (mask & STORM_COST_VEL) t[3] = s_terms[3 * kLanes + lane];
+        if (mask & STORM_COST_STOP) t[4] = s_terms[4 * kLanes + lane];
+        if (mask & STORM_COST_MANIP) {
+            const float m = s_terms[5 * kLanes + lane];
+            t[5] = m < P.k_m ? 1.0f - m : 0.0f;
+        }
+        if (mask & STORM_COST_SELF)
+            for (int w = 0; w < W; ++w) t[6] = fmaxf(t[6], s_pself[w * kLanes + lane]);
+        if (mask & STORM_COST_ENV)
+            for (int w = 0; w < W; ++w) t[7] += s_penv[w * kLanes + lane];
+        float c = P.w_pos * t[0];
+        c = fmaf(P.w_rot, t[1], c);
+        c = fmaf(P.a_joint, t[2], c);
+        c = fmaf(P.a_vel, t[3], c);
+        c = fmaf(P.a_stop, t[4], c);
+        c = fmaf(P.a_manip, t[5], c);
+        c = fmaf(P.a_coll, t[6] + t[7], c);
+        if (valid) {
+            if (out.c) out.c[(size_t)i * H + h] = c;
+            if (out.terms)
+#pragma unroll
+                for (int k = 0; k < kTerms; ++k) out.terms[((size_t)k * N + i) * H + h] = t[k];
+        }
+        s_cw[lane] = tab[kTabHw + h] * c;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < P.ppt) {
+        const int ip = blockIdx.x * P.ppt + lane;
+        if (ip < N) {
+            float acc = 0.0f;
+            for (int k = 0; k < H; ++k) acc += s_cw[lane * H + k];
+            P.C[ip] = acc;
+            if (out.C) out.C[ip] = acc;
+        }
+    }
+}
+
+size_t rollout_lds_bytes(int S, int W)
+{
+    return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms + 1) * kLanes * sizeof(float);
+}
+
+}  // namespace
+
+hipError_t set_rollout_lds_limit()
+{
+    const int bytes16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16);
+    const int bytes8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rollout_kernel<16>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes16);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&rollout_kernel<8>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes8);
+}
+
+hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,
+                          const float *noise, const StepOut &out, int waves, hipStream_t stream)
+{
+    const size_t lds = rollout_lds_bytes(R.n_spheres, waves);
+    const dim3 grid((unsigned)P.n_tiles);
+    if (waves == 16) {
+        hipLaunchKernelGGL(rollout_kernel<16>, grid, dim3(16 * kLanes), lds, stream, P, R, x0, goal, noise, out);
+    } else if (waves == 8) {
+        hipLaunchKernelGGL(rollout_kernel<8>, grid, dim3(8 * kLanes), lds, stream, P, R, x0, goal, noise, out);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace storm

@@ -1,0 +1,78 @@
+// Internal definitions of the HIP library: device-side problem descriptors,
+// table offsets and the kernel launchers shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "storm.h"
+
+namespace storm {
+
+constexpr int kDof = STORM_DOF;
+constexpr int kFrames = STORM_NFRAMES;
+constexpr int kTerms = STORM_NTERMS;
+constexpr int kLanes = 64;  // CDNA wavefront width
+constexpr int kMaxH = STORM_MAX_HORIZON;
+
+// Offsets (in floats) inside the per-problem table block built at init.
+constexpr int kTabDt = 0;           // dt[H]
+constexpr int kTabVstop = 64;       // stop-cost velocity limit per step [H]
+constexpr int kTabHw = 128;         // horizon weight gamma^h (terminal scaled) [H]
+constexpr int kTabJlo = 192;        // band-shrunk joint position limits [7]
+constexpr int kTabJhi = 200;
+constexpr int kTabVlo = 208;        // band-shrunk joint velocity limits [7]
+constexpr int kTabVhi = 216;
+constexpr int kTabSize = 224;
+
+// Per-problem description read by the kernels.  All pointers are device memory.
+struct ProblemDev {
+    int32_t N, H, n_halton, n_null;
+    int32_t n_sph_obs, n_box_obs, ppt, n_tiles;  // ppt = particles per 64-lane tile
+    uint32_t cost_mask, seed_lo, seed_hi, pad0;
+    float beta, alpha_mu, alpha_sigma, sigma2_min;
+    float k_m, w_pos, w_rot, a_stop;
+    float a_joint, a_vel, a_manip, a_coll;
+    float alpha_pos[3], alpha_rot[3], pad1[2];
+    const float *tables;    // [kTabSize]
+    const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
+    const float4 *sph_obs;  // [n_sph_obs] centre, radius
+    const float *box_obs;   // [n_box_obs][16]: M = R^T (9, row-major), t = -R^T c (3), half extents (3), pad
+    float *mean;            // [H][7]
+    float *sigma2;          // [7]
+    float *u;               // [7][N][H] controls of the last step
+    float *C;               // [N] horizon costs of the last step
+    uint32_t *step;         // sampling step counter (Philox counter word 3)
+    uint32_t *status;       // asynchronous status flags
+};
+
+// Robot constants, passed by value (kernel-argument segment, wave-uniform).
+struct RobotDev {
+    float ca[kFrames], sa[kFrames], a[kFrames], d[kFrames];  // DH: cos/sin alpha_{k-1}, a_{k-1}, d_k
+    int32_t n_spheres, n_pairs, pad0, pad1;
+    const float4 *sph_local;  // [S] body-frame centre (x, y, z), radius
+    const int32_t *sph_body;  // [S] frame index 0..7 the sphere is attached to
+    const int4 *pairs;        // [P] (s, t, bits(r_s + r_t), bits((r_s + r_t)^2)), bodies >= 2 apart
+};
+
+// Optional per-step outputs.
+struct StepOut {
+    float *u, *q, *v, *a, *c, *terms, *C;
+};
+
+// Launchers (defined in the .hip translation units).
+hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
+                              float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
+                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
+                              const float *d_sph_raw, int n_spheres, float4 *d_sph_local, int32_t *d_sph_body,
+                              int4 *d_pairs, const int2 *d_pair_idx, int n_pairs, hipStream_t stream);
+hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,
+                          const float *noise, const StepOut &out, int waves, hipStream_t stream);
+// Raise the dynamic-LDS limit of the rollout kernels to what the largest
+// sphere model needs (idempotent).
+hipError_t set_rollout_lds_limit();
+hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
+                         hipStream_t stream);
+hipError_t launch_fk(const RobotDev &R, const float *q, int n, float *pose, float *manip, hipStream_t stream);
+
+}  // namespace storm

@@ -1,0 +1,272 @@
+"""Python binding of the HIP library ``libstorm.so`` (ctypes).
+
+Argument marshalling only: tensors are allocated with torch on the current
+HIP device, their device pointers and the current stream are handed to the C
+ABI declared in ``include/storm.h``, and every step of the MPC iteration runs
+in the library's kernels.  There is no fallback: if the library has not been
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import inputs
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libstorm.so")
+
+DOF = 7
+NTERMS = 8
+TERM_NAMES = ("pos", "rot", "joint", "vel", "stop", "manip", "self", "env")
+
+STORM_OK = 0
+STORM_E_NULL = -1
+STORM_E_RANGE = -2
+STORM_E_PARAM = -3
+STORM_E_DEVICE = -4
+STORM_E_STATE = -5
+STORM_E_NOMEM = -6
+STORM_E_UNSUPPORTED = -7
+FLAG_NONFINITE_COST = 1
+FLAG_ZERO_WEIGHT = 2
+
+
+class StormError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (where, status_str(code), code))
+
+
+class storm_params(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int32), ("horizon", ctypes.c_int32), ("n_halton", ctypes.c_int32),
+        ("n_null", ctypes.c_int32), ("n_knots", ctypes.c_int32), ("cost_mask", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64), ("dt", ctypes.POINTER(ctypes.c_float)),
+        ("sigma_init", ctypes.c_float * 7),
+        ("beta", ctypes.c_float), ("gamma", ctypes.c_float), ("alpha_mu", ctypes.c_float),
+        ("alpha_sigma", ctypes.c_float), ("w_term", ctypes.c_float), ("sigma2_min", ctypes.c_float),
+        ("acc_stop", ctypes.c_float), ("k_jl", ctypes.c_float), ("k_vl", ctypes.c_float), ("k_m", ctypes.c_float),
+        ("w_pos", ctypes.c_float), ("w_rot", ctypes.c_float),
+        ("alpha_pos", ctypes.c_float * 3), ("alpha_rot", ctypes.c_float * 3),
+        ("a_stop", ctypes.c_float), ("a_joint", ctypes.c_float), ("a_vel", ctypes.c_float),
+        ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float),
+    ]
+
+
+class storm_robot(ctypes.Structure):
+    _fields_ = [
+        ("dh", (ctypes.c_float * 3) * 8),
+        ("q_min", ctypes.c_float * 7), ("q_max", ctypes.c_float * 7), ("qd_max", ctypes.c_float * 7),
+        ("n_spheres", ctypes.c_int32), ("spheres", ctypes.POINTER(ctypes.c_float)),
+    ]
+
+
+class storm_scene(ctypes.Structure):
+    _fields_ = [("n_obstacles", ctypes.c_int32), ("obstacles", ctypes.POINTER(ctypes.c_float))]
+
+
+class storm_debug(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("u", "q", "v", "a", "c", "terms")]
+
+
+_lib = None
+
+# every symbol declared in include/storm.h
+EXPORTS = (
+    "storm_rollout_init", "storm_rollout_step", "storm_rollout_update", "storm_rollout_destroy",
+    "storm_rollout_status", "storm_rollout_get_state", "storm_rollout_set_state", "storm_fk",
+    "storm_status_str",
+)
+
+
+def lib():
+    """Load libstorm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libstorm.so is not built (run paper_2104_13542_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i32 = ctypes.c_int32
+        L.storm_status_str.argtypes = [i32]
+        L.storm_status_str.restype = ctypes.c_char_p
+        L.storm_rollout_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(storm_params),
+                                         ctypes.POINTER(storm_robot), ctypes.POINTER(storm_scene), vp]
+        L.storm_rollout_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(storm_debug), vp, vp]
+        L.storm_rollout_update.argtypes = [vp, vp, vp, vp, i32, vp]
+        L.storm_rollout_destroy.argtypes = [vp]
+        L.storm_rollout_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
+        L.storm_rollout_get_state.argtypes = [vp, vp, vp, vp, vp]
+        L.storm_rollout_set_state.argtypes = [vp, vp, vp, vp, vp]
+        L.storm_fk.argtypes = [ctypes.POINTER(storm_robot), vp, i32, vp, vp, vp]
+        for name in EXPORTS:
+            getattr(L, name).restype = ctypes.c_char_p if name == "storm_status_str" else i32
+        _lib = L
+    return _lib
+
+
+def status_str(code):
+    return lib().storm_status_str(int(code)).decode()
+
+
+def _check(code, where):
+    if code != STORM_OK:
+        raise StormError(code, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_params(p: "inputs.Params"):
+    """Fill a storm_params from an inputs.Params; returns (struct, keep-alive)."""
+    sp = storm_params()
+    sp.n_particles, sp.horizon = p.n_particles, p.horizon
+    sp.n_halton, sp.n_null, sp.n_knots = p.n_halton, p.n_null, p.n_knots
+    sp.cost_mask, sp.seed = p.cost_mask, p.seed
+    dt = np.ascontiguousarray(p.dt, dtype=np.float32)
+    sp.dt = dt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    for j in range(DOF):
+        sp.sigma_init[j] = float(p.sigma_init[j])
+    for k in ("beta", "gamma", "alpha_mu", "alpha_sigma", "w_term", "sigma2_min", "acc_stop", "k_jl", "k_vl",
+              "k_m", "w_pos", "w_rot", "a_stop", "a_joint", "a_vel", "a_manip", "a_coll"):
+        setattr(sp, k, float(getattr(p, k)))
+    for c in range(3):
+        sp.alpha_pos[c] = float(p.alpha_pos[c])
+        sp.alpha_rot[c] = float(p.alpha_rot[c])
+    return sp, dt
+
+
+def make_robot(spheres=None, dh=None, q_min=None, q_max=None, qd_max=None):
+    r = storm_robot()
+    dh = inputs.PANDA_DH if dh is None else dh
+    for k in range(8):
+        for c in range(3):
+            r.dh[k][c] = float(dh[k][c])
+    qlo = inputs.PANDA_Q_MIN if q_min is None else q_min
+    qhi = inputs.PANDA_Q_MAX if q_max is None else q_max
+    qd = inputs.PANDA_QD_MAX if qd_max is None else qd_max
+    for j in range(DOF):
+        r.q_min[j], r.q_max[j], r.qd_max[j] = float(qlo[j]), float(qhi[j]), float(qd[j])
+    sph = np.ascontiguousarray(np.zeros((0, 5)) if spheres is None else spheres, dtype=np.float32)
+    r.n_spheres = sph.shape[0]
+    r.spheres = sph.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if sph.size else None
+    return r, sph
+
+
+def make_scene(obstacles):
+    s = storm_scene()
+    obs = np.ascontiguousarray(obstacles.reshape(-1, inputs.OBSTACLE_STRIDE), dtype=np.float32)
+    s.n_obstacles = obs.shape[0]
+    s.obstacles = obs.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if obs.size else None
+    return s, obs
+
+
+class Rollout:
+    """One MPC problem on the current HIP device (plain form)."""
+
+    def __init__(self, problem: "inputs.Problem", device=None):
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.problem = problem
+        p = problem.params
+        self.N, self.H = p.n_particles, p.horizon
+        sp, self._dt = make_params(p)
+        rb, self._sph = make_robot(problem.spheres)
+        sc, self._obs = make_scene(problem.obstacles)
+        self._robot = rb
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().storm_rollout_init(ctypes.byref(handle), ctypes.byref(sp), ctypes.byref(rb),
+                                            ctypes.byref(sc), _stream()), "storm_rollout_init")
+        self._h = handle
+        self.x0 = torch.tensor(np.concatenate([problem.q0, problem.v0, problem.a0]), dtype=torch.float32,
+                               device=self.device)
+        self.cmd = torch.zeros(DOF, dtype=torch.float32, device=self.device)
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().storm_rollout_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- MPC iteration -----------------------------------------------------
+    def step(self, goal, x0=None, noise=None, debug=False, C=None):
+        """Sample + roll out.  goal: [12] device tensor.  noise: optional
+        [7][N][H] standard normals.  Returns a dict of the requested outputs."""
+        N, H = self.N, self.H
+        x0 = self.x0 if x0 is None else x0
+        out = {}
+        dbg = None
+        if debug:
+            kw = dict(dtype=torch.float32, device=self.device)
+            for k in ("u", "q", "v", "a"):
+                out[k] = torch.empty((DOF, N, H), **kw)
+            out["c"] = torch.empty((N, H), **kw)
+            out["terms"] = torch.empty((NTERMS, N, H), **kw)
+            dbg = storm_debug(*[ctypes.c_void_p(out[k].data_ptr()) for k in ("u", "q", "v", "a", "c", "terms")])
+        if C is None:
+            C = torch.empty(N, dtype=torch.float32, device=self.device)
+        out["C"] = C
+        _check(lib().storm_rollout_step(self._h, _ptr(x0), _ptr(goal), _ptr(noise),
+                                        ctypes.byref(dbg) if dbg is not None else None, _ptr(C), _stream()),
+               "storm_rollout_step")
+        return out
+
+    def update(self, shift=True, want_mean=True, cmd=None):
+        """Policy update; returns (cmd [7], mean' [H][7] or None, sigma2' [7] or None)."""
+        kw = dict(dtype=torch.float32, device=self.device)
+        mean = torch.empty((self.H, DOF), **kw) if want_mean else None
+        sigma2 = torch.empty(DOF, **kw) if want_mean else None
+        cmd = self.cmd if cmd is None else cmd
+        _check(lib().storm_rollout_update(self._h, _ptr(mean), _ptr(sigma2), _ptr(cmd), int(bool(shift)),
+                                          _stream()), "storm_rollout_update")
+        return cmd, mean, sigma2
+
+    # -- state -------------------------------------------------------------
+    def get_state(self):
+        mean = np.zeros((self.H, DOF), dtype=np.float32)
+        sigma2 = np.zeros(DOF, dtype=np.float32)
+        step = ctypes.c_uint32()
+        _check(lib().storm_rollout_get_state(self._h, mean.ctypes.data, sigma2.ctypes.data, ctypes.addressof(step),
+                                             _stream()), "storm_rollout_get_state")
+        return mean, sigma2, step.value
+
+    def set_state(self, mean=None, sigma2=None, step=None):
+        m = None if mean is None else np.ascontiguousarray(mean, dtype=np.float32)
+        s = None if sigma2 is None else np.ascontiguousarray(sigma2, dtype=np.float32)
+        st = None if step is None else ctypes.c_uint32(int(step))
+        _check(lib().storm_rollout_set_state(self._h, None if m is None else m.ctypes.data,
+                                             None if s is None else s.ctypes.data,
+                                             None if st is None else ctypes.addressof(st), _stream()),
+               "storm_rollout_set_state")
+
+    def status(self):
+        f = ctypes.c_uint32()
+        _check(lib().storm_rollout_status(self._h, ctypes.byref(f), _stream()), "storm_rollout_status")
+        return f.value
+
+
+def fk(q, spheres=None):
+    """Batched flange pose [n][12] and manipulability [n] of joint
+    configurations q [n][7] (device tensor) through storm_fk."""
+    n = q.shape[0]
+    qs = q.t().contiguous()
+    pose = torch.empty((12, n), dtype=torch.float32, device=q.device)
+    manip = torch.empty(n, dtype=torch.float32, device=q.device)
+    rb, _keep = make_robot(spheres)
+    _check(lib().storm_fk(ctypes.byref(rb), _ptr(qs), int(n), _ptr(pose), _ptr(manip), _stream()), "storm_fk")
+    return pose.t(), manip

@@ -1,0 +1,113 @@
+"""Helpers shared by the GPU parity tests: run one step on the HIP path and on
+the FP64 oracle with the same inputs, and compare them."""
+import numpy as np
+import torch
+
+from paper_2104_13542_amd import inputs
+
+# Tolerances: states 1e-5 (m, rad, rad/s), costs 1e-4 relative, updated mean 1e-4.
+TOL_STATE = 1e-5
+TOL_COST_REL = 1e-4
+TOL_MEAN = 1e-4
+# Running costs are compared relative to max(|c|, COST_FLOOR): a cost of a few
+# units made of terms of unit scale cannot be resolved below ~1e-6 absolute in
+# FP32 arithmetic.
+COST_FLOOR = 1.0
+
+
+def to_nhj(t):
+    """[7][N][H] device tensor -> [N][H][7] float64 numpy."""
+    return t.detach().cpu().double().numpy().transpose(1, 2, 0)
+
+
+def device_goal(o):
+    return torch.tensor(o.goal, dtype=torch.float32, device="cuda")
+
+
+def f32(a):
+    """Round to float32 and back, so that both sides get identical inputs."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def run_pair(problem, oracle_mod, noise_nhj=None, step_index=0, mean=None, sigma2=None):
+    """One step + update on both sides.  Returns (gpu dict, oracle rollout,
+    oracle update, eps used)."""
+    from paper_2104_13542_amd import storm
+
+    p = problem.params
+    N, H = p.n_particles, p.horizon
+    # the robot and scene both sides see are the float32-rounded inputs
+    problem.spheres = f32(problem.spheres)
+    problem.obstacles = f32(problem.obstacles)
+    problem.q0, problem.v0, problem.a0 = f32(problem.q0), f32(problem.v0), f32(problem.a0)
+    o = oracle_mod.Oracle(problem, dh=f32(inputs.PANDA_DH), q_min=f32(inputs.PANDA_Q_MIN),
+                          q_max=f32(inputs.PANDA_Q_MAX), qd_max=f32(inputs.PANDA_QD_MAX))
+    o.dt = f32(p.dt)
+    o.goal = f32(o.goal)
+    r = storm.Rollout(problem)
+    try:
+        if mean is not None or sigma2 is not None or step_index:
+            r.set_state(mean=mean, sigma2=sigma2, step=step_index)
+        mean0 = np.zeros((H, 7)) if mean is None else f32(mean)
+        sig2_0 = f32(np.asarray(p.sigma_init) ** 2) if sigma2 is None else f32(sigma2)
+        goal = device_goal(o)
+        noise_t = None
+        if noise_nhj is not None:
+            noise_nhj = f32(noise_nhj)
+            noise_t = torch.tensor(noise_nhj.transpose(2, 0, 1).copy(), dtype=torch.float32, device="cuda")
+        out = r.step(goal, noise=noise_t, debug=True)
+        cmd, mean_new, sig2_new = r.update(shift=True)
+        torch.cuda.synchronize()
+        g = {k: v.detach().cpu().double().numpy() for k, v in out.items()}
+        for k in ("u", "q", "v", "a"):
+            g[k] = g[k].transpose(1, 2, 0)
+        g["terms"] = g["terms"].transpose(1, 2, 0)
+        g["cmd"] = cmd.cpu().double().numpy()
+        g["mean"] = mean_new.cpu().double().numpy()
+        g["sigma2"] = sig2_new.cpu().double().numpy()
+        g["state_after"] = r.get_state()
+    finally:
+        r.close()
+    if noise_nhj is None:
+        eps = o.noise(step_index)
+        eps[N - p.n_null:] = 0.0
+    else:
+        eps = noise_nhj.copy()
+        eps[N - p.n_null:] = 0.0
+    sigma = np.sqrt(sig2_0)
+    ro = o.rollout(mean0, sigma, eps)
+    up = o.update(ro["C"], ro["u"], mean0, sig2_0)
+    return g, ro, up, o, eps
+
+
+def manip_values(o, q_nhj):
+    """Oracle manipulability at every state [N][H]."""
+    N, H = q_nhj.shape[:2]
+    m = np.zeros((N, H))
+    for i in range(N):
+        for h in range(H):
+            T = o_fk(o, q_nhj[i, h])
+            m[i, h] = o_manip(o, T)
+    return m
+
+
+def o_fk(o, q):
+    import oracle
+
+    return oracle.fk(o.dh, q)
+
+
+def o_manip(o, T):
+    import oracle
+
+    return oracle.manipulability(oracle.jacobian(T))
+
+
+def assert_states(g, ro):
+    for k in ("u", "a", "v", "q"):
+        err = np.max(np.abs(g[k] - ro[k]))
+        assert err <= TOL_STATE, "%s max abs error %.3g" % (k, err)
+
+
+def cost_error(gc, oc):
+    return np.abs(gc - oc) / np.maximum(np.abs(oc), COST_FLOOR)

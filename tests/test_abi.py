@@ -1,0 +1,139 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/storm.h declares, and rejects invalid arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2104_13542_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "storm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(storm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def storm():
+    from paper_2104_13542_amd import storm as s
+
+    if not os.path.exists(s.LIB_PATH):
+        from paper_2104_13542_amd import build
+
+        build.build()
+    s.lib()
+    return s
+
+
+def test_exports_every_declared_symbol(storm):
+    names = _declared_functions()
+    assert "storm_rollout_init" in names and len(names) >= 9
+    L = storm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(storm.EXPORTS) | set(names)
+    assert set(storm.EXPORTS) == set(names)
+
+
+def test_status_strings(storm):
+    for code in range(-7, 1):
+        assert storm.status_str(code) not in ("", "unknown status")
+    assert storm.status_str(-99) == "unknown status"
+
+
+def _args(storm, prob=None):
+    prob = prob or inputs.config2(0, n_particles=32, horizon=10)
+    sp, dt = storm.make_params(prob.params)
+    rb, sph = storm.make_robot(prob.spheres)
+    sc, obs = storm.make_scene(prob.obstacles)
+    return sp, rb, sc, (dt, sph, obs)
+
+
+def _init(storm, sp, rb, sc):
+    h = ctypes.c_void_p()
+    return storm.lib().storm_rollout_init(ctypes.byref(h), ctypes.byref(sp) if sp is not None else None,
+                                          ctypes.byref(rb) if rb is not None else None,
+                                          ctypes.byref(sc) if sc is not None else None, None)
+
+
+def test_init_validation(storm):
+    E = storm
+    sp, rb, sc, keep = _args(storm)
+    assert _init(storm, None, rb, sc) == E.STORM_E_NULL
+    assert _init(storm, sp, None, sc) == E.STORM_E_NULL
+    assert storm.lib().storm_rollout_init(None, ctypes.byref(sp), ctypes.byref(rb), ctypes.byref(sc), None) \
+        == E.STORM_E_NULL
+    cases = [
+        ("n_particles", 0, E.STORM_E_RANGE), ("horizon", 0, E.STORM_E_RANGE), ("horizon", 65, E.STORM_E_RANGE),
+        ("n_null", 33, E.STORM_E_RANGE), ("n_halton", 40, E.STORM_E_RANGE), ("n_knots", 3, E.STORM_E_RANGE),
+        ("beta", 0.0, E.STORM_E_PARAM), ("beta", float("nan"), E.STORM_E_PARAM), ("gamma", 1.5, E.STORM_E_PARAM),
+        ("alpha_mu", -0.1, E.STORM_E_PARAM), ("alpha_sigma", 2.0, E.STORM_E_PARAM),
+        ("k_jl", 0.5, E.STORM_E_PARAM), ("sigma2_min", -1.0, E.STORM_E_PARAM),
+        ("cost_mask", 0x80, E.STORM_E_PARAM), ("w_pos", float("inf"), E.STORM_E_PARAM),
+    ]
+    for field, val, want in cases:
+        sp2, rb2, sc2, keep2 = _args(storm)
+        setattr(sp2, field, val)
+        assert _init(storm, sp2, rb2, sc2) == want, field
+    sp2, rb2, sc2, keep2 = _args(storm)
+    keep2[0][3] = -0.01  # a non-positive dt
+    assert _init(storm, sp2, rb2, sc2) == E.STORM_E_PARAM
+    sp2, rb2, sc2, keep2 = _args(storm)
+    sp2.sigma_init[2] = 0.0
+    assert _init(storm, sp2, rb2, sc2) == E.STORM_E_PARAM
+    sp2, rb2, sc2, keep2 = _args(storm)
+    sp2.dt = None
+    assert _init(storm, sp2, rb2, sc2) == E.STORM_E_NULL
+
+
+def test_robot_and_scene_validation(storm):
+    E = storm
+    prob = inputs.config2(0, n_particles=32, horizon=10)
+    bad = prob.spheres.copy()
+    bad[3, 0] = 9  # body out of range
+    sp, rb, sc, keep = _args(storm)
+    rb2, k2 = storm.make_robot(bad)
+    assert _init(storm, sp, rb2, sc) == E.STORM_E_PARAM
+    bad = prob.spheres.copy()
+    bad[5, 4] = 0.0  # zero radius
+    rb2, k2 = storm.make_robot(bad)
+    assert _init(storm, sp, rb2, sc) == E.STORM_E_PARAM
+    bad = prob.spheres[::-1].copy()  # not sorted by body
+    rb2, k2 = storm.make_robot(bad)
+    assert _init(storm, sp, rb2, sc) == E.STORM_E_PARAM
+    rb2, k2 = storm.make_robot(np.zeros((65, 5)) + [1, 0, 0, 0, 0.1])
+    assert _init(storm, sp, rb2, sc) == E.STORM_E_RANGE
+    qlo = inputs.PANDA_Q_MAX.copy()
+    rb2, k2 = storm.make_robot(prob.spheres, q_min=qlo)
+    assert _init(storm, sp, rb2, sc) == E.STORM_E_PARAM
+    obs = prob.obstacles.copy()
+    obs[0, 0] = 7  # unknown kind
+    sc2, k3 = storm.make_scene(obs)
+    assert _init(storm, sp, rb, sc2) == E.STORM_E_PARAM
+    obs = prob.obstacles.copy()
+    obs[-1, 5] = -0.1  # negative cuboid extent
+    sc2, k3 = storm.make_scene(obs)
+    assert _init(storm, sp, rb, sc2) == E.STORM_E_PARAM
+    sc2, k3 = storm.make_scene(np.zeros((257, 16)) + np.r_[0, 0, 0, 0, 0.1, np.zeros(11)])
+    assert _init(storm, sp, rb, sc2) == E.STORM_E_RANGE
+
+
+def test_call_validation_before_device(storm):
+    L = storm.lib()
+    E = storm
+    assert L.storm_rollout_step(None, None, None, None, None, None, None) == E.STORM_E_NULL
+    assert L.storm_rollout_update(None, None, None, None, 1, None) == E.STORM_E_NULL
+    assert L.storm_rollout_destroy(None) == E.STORM_OK
+    assert L.storm_rollout_status(None, None, None) == E.STORM_E_NULL
+    assert L.storm_rollout_get_state(None, None, None, None, None) == E.STORM_E_NULL
+    assert L.storm_rollout_set_state(None, None, None, None, None) == E.STORM_E_NULL
+    rb, keep = storm.make_robot(None)
+    assert L.storm_fk(None, None, 1, None, None, None) == E.STORM_E_NULL
+    assert L.storm_fk(ctypes.byref(rb), None, -1, None, None, None) == E.STORM_E_RANGE
+    assert L.storm_fk(ctypes.byref(rb), None, 5, None, None, None) == E.STORM_E_NULL

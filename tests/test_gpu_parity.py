@@ -1,0 +1,280 @@
+"""GPU parity of the HIP path against the FP64 oracle (marked gpu).
+
+Every test calls the C ABI through the ctypes binding and compares element by
+element with the oracle on the same seeded inputs: states to 1e-5, running and
+horizon costs to 1e-4 relative, the updated mean to 1e-4."""
+import numpy as np
+import pytest
+
+from paper_2104_13542_amd import inputs
+from tests.gpu_common import (COST_FLOOR, TOL_COST_REL, TOL_MEAN, TOL_STATE, assert_states, cost_error, f32,
+                              manip_values, run_pair, to_nhj)
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_13542_amd import storm
+
+    storm.lib()
+
+
+def _update_bound(ro, up, gC, beta):
+    """First-order bound of the updated-mean error caused by the horizon-cost
+    error dC: |d mu'_hj| <= (1/beta) sum_i w_i |u_ihj - mu'_hj| |dC_i - dC_w|
+    with dC_w the weighted mean of dC (a common shift of all C changes
+    nothing)."""
+    w = up["w"]
+    dC = gC - ro["C"]
+    dCc = dC - np.sum(w * dC)
+    dev = np.abs(ro["u"] - up["mean"][None])
+    return np.sum(w[:, None, None] * dev * np.abs(dCc)[:, None, None], axis=0) / beta
+
+
+def test_fk_parity(oracle_lib):
+    from paper_2104_13542_amd import storm
+
+    rng = np.random.default_rng(0)
+    n = 777
+    q = f32(np.stack([inputs.random_q(rng) for _ in range(n)]))
+    pose, manip = storm.fk(torch.tensor(q, dtype=torch.float32, device="cuda"))
+    pose = pose.cpu().double().numpy()
+    manip = manip.cpu().double().numpy()
+    dh = f32(inputs.PANDA_DH)
+    for k in range(n):
+        T = oracle_lib.fk(dh, q[k])[7]
+        ref = np.concatenate([T[:3, :3].reshape(-1), T[:3, 3]])
+        assert np.max(np.abs(pose[k] - ref)) < 2e-6
+        m = oracle_lib.manipulability(oracle_lib.jacobian(oracle_lib.fk(dh, q[k])))
+        assert abs(manip[k] - m) <= 1e-4 * max(m, 1e-2)
+    # empty batch is a no-op
+    storm.fk(torch.zeros((0, 7), device="cuda"))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_config1_noise_override(oracle_lib, seed):
+    prob = inputs.config1(seed)
+    p = prob.params
+    eps = inputs.standard_normal(100 + seed, (p.n_particles, p.horizon, 7))
+    g, ro, up, o, _ = run_pair(prob, oracle_lib, noise_nhj=eps)
+    assert_states(g, ro)
+    assert np.max(cost_error(g["c"], ro["c"])) <= TOL_COST_REL
+    assert np.max(cost_error(g["C"], ro["C"])) <= TOL_COST_REL
+    np.testing.assert_allclose(g["terms"][..., :3], ro["terms"][..., :3], rtol=1e-4, atol=2e-6)
+    # decoupled update: the oracle's update on the GPU's horizon costs and controls
+    upd = o.update(g["C"], g["u"], np.zeros((p.horizon, 7)), f32(np.asarray(p.sigma_init) ** 2))
+    assert np.max(np.abs(g["mean"] - upd["mean"])) <= TOL_MEAN
+    assert np.max(np.abs(g["sigma2"] - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"])
+    np.testing.assert_allclose(g["cmd"], upd["cmd"], atol=TOL_MEAN)
+    # end to end, within 1e-4 plus the propagated cost rounding
+    bound = _update_bound(ro, up, g["C"], p.beta)
+    assert np.all(np.abs(g["mean"] - up["mean"]) <= TOL_MEAN + 2.0 * bound)
+    # stored state: shifted mean, new variance, step counter advanced
+    mean_s, sig_s, step = g["state_after"]
+    np.testing.assert_allclose(mean_s[:-1], g["mean"][1:], atol=0)
+    assert np.all(mean_s[-1] == 0)
+    np.testing.assert_allclose(sig_s, g["sigma2"], atol=0)
+    assert step == 1
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_config1_philox_noise(oracle_lib, seed):
+    prob = inputs.config1(seed, v0_random=True)
+    g, ro, up, o, eps = run_pair(prob, oracle_lib)
+    assert_states(g, ro)
+    assert np.max(cost_error(g["c"], ro["c"])) <= TOL_COST_REL
+    assert np.max(cost_error(g["C"], ro["C"])) <= TOL_COST_REL
+    bound = _update_bound(ro, up, g["C"], prob.params.beta)
+    assert np.all(np.abs(g["mean"] - up["mean"]) <= TOL_MEAN + 2.0 * bound)
+
+
+def _config2_checks(g, ro, o, prob):
+    p = prob.params
+    assert_states(g, ro)
+    # the manipulability cost jumps by (1 - k_m) at m = k_m: states within
+    # 1e-4 of the threshold may fall on either side in FP32 and are masked
+    m = manip_values(o, ro["q"])
+    near = np.abs(m - p.k_m) < 1e-4
+    err = cost_error(g["c"], ro["c"])
+    assert np.max(np.where(near, 0.0, err)) <= TOL_COST_REL, "max running-cost error %.3g" % np.max(err[~near])
+    clean = ~near.any(axis=1)
+    assert clean.sum() >= 0.9 * p.n_particles
+    assert np.max(cost_error(g["C"], ro["C"])[clean]) <= TOL_COST_REL
+    # individual terms (unweighted), scaled by their weights
+    wts = np.array([p.w_pos, p.w_rot, p.a_joint, p.a_vel, p.a_stop, p.a_manip, p.a_coll, p.a_coll])
+    for k in range(8):
+        d = np.abs(g["terms"][..., k] - ro["terms"][..., k]) * wts[k]
+        d = np.where(near, 0.0, d)
+        assert np.max(d / np.maximum(np.abs(ro["c"]), COST_FLOOR)) <= TOL_COST_REL, "term %d" % k
+    return clean
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_config2_full(oracle_lib, seed):
+    prob = inputs.config2(seed)
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    clean = _config2_checks(g, ro, o, prob)
+    # collision terms are exercised by this scene
+    assert np.any(ro["terms"][..., 6] > 0) or np.any(ro["terms"][..., 7] > 0)
+    p = prob.params
+    upd = o.update(g["C"], g["u"], np.zeros((p.horizon, 7)), f32(np.asarray(p.sigma_init) ** 2))
+    assert np.max(np.abs(g["mean"] - upd["mean"])) <= TOL_MEAN
+    assert np.max(np.abs(g["sigma2"] - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"])
+    if clean.all():
+        bound = _update_bound(ro, up, g["C"], p.beta)
+        assert np.all(np.abs(g["mean"] - up["mean"]) <= TOL_MEAN + 2.0 * bound)
+
+
+def test_config2_override_and_halton_table(oracle_lib):
+    """Noise override on a STORM-shaped problem with null particles, and the
+    Halton + B-spline table against the oracle's."""
+    prob = inputs.config2(5, n_particles=123, horizon=30)
+    prob.params.n_null = 7
+    p = prob.params
+    g, ro, up, o, eps = run_pair(prob, oracle_lib)
+    _config2_checks(g, ro, o, prob)
+    sig = np.sqrt(f32(np.asarray(p.sigma_init) ** 2))
+    # recover the GPU's standard noise of the Halton particles from u = sigma eps (mu = 0)
+    eps_gpu = g["u"][: p.n_halton] / sig
+    ref = oracle_lib.halton_noise(p.n_halton, p.horizon, p.n_knots)
+    assert np.max(np.abs(eps_gpu - ref)) < 2e-5
+    assert np.all(g["u"][p.n_particles - p.n_null:] == 0.0)
+
+
+@pytest.mark.parametrize("N,H", [(1, 1), (1, 64), (3, 64), (5, 33), (70, 7), (130, 21), (257, 16), (64, 30)])
+def test_shapes_and_ragged(oracle_lib, N, H):
+    prob = inputs.config2(11, n_particles=N, horizon=H, n_obs_spheres=5, n_obs_cuboids=5)
+    prob.params.n_halton = N // 3
+    prob.params.n_null = 1 if N > 2 else 0
+    prob.params.gamma = 0.97
+    prob.params.w_term = 3.0
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    _config2_checks(g, ro, o, prob)
+
+
+def test_determinism():
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(2)
+    outs = []
+    for _ in range(2):
+        r = storm.Rollout(prob)
+        from tests.gpu_common import device_goal  # noqa: F401
+        goal = torch.zeros(12, device="cuda")
+        goal[0] = goal[4] = goal[8] = 1.0
+        goal[9:] = torch.tensor([0.5, 0.0, 0.5])
+        o = r.step(goal, debug=True)
+        cmd, mean, sig = r.update()
+        o2 = r.step(goal, debug=True)
+        torch.cuda.synchronize()
+        outs.append([o["C"].cpu(), o["c"].cpu(), o["q"].cpu(), mean.cpu(), sig.cpu(), o2["C"].cpu()])
+        r.close()
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_multi_step_shift_chain(oracle_lib):
+    """Three control steps (step, update with shift) compared with the oracle
+    chain fed the same noise; the oracle update runs on the GPU's costs so the
+    chain does not drift through the softmin."""
+    from paper_2104_13542_amd import storm
+    from tests.gpu_common import device_goal
+
+    prob = inputs.config1(4)
+    p = prob.params
+    N, H = p.n_particles, p.horizon
+    prob.q0, prob.v0, prob.a0 = f32(prob.q0), f32(prob.v0), f32(prob.a0)
+    o = oracle_lib.Oracle(prob, dh=f32(inputs.PANDA_DH), q_min=f32(inputs.PANDA_Q_MIN),
+                          q_max=f32(inputs.PANDA_Q_MAX), qd_max=f32(inputs.PANDA_QD_MAX))
+    o.goal = f32(o.goal)
+    r = storm.Rollout(prob)
+    goal = device_goal(o)
+    mean = np.zeros((H, 7))
+    sig2 = f32(np.asarray(p.sigma_init) ** 2)
+    try:
+        for step in range(3):
+            eps = f32(inputs.standard_normal(500 + step, (N, H, 7)))
+            nt = torch.tensor(eps.transpose(2, 0, 1).copy(), dtype=torch.float32, device="cuda")
+            out = r.step(goal, noise=nt, debug=True)
+            cmd, mean_new, sig_new = r.update(shift=True)
+            torch.cuda.synchronize()
+            ro = o.rollout(mean, np.sqrt(sig2), eps)
+            assert np.max(np.abs(to_nhj(out["q"]) - ro["q"])) <= TOL_STATE
+            gC = out["C"].cpu().double().numpy()
+            assert np.max(cost_error(gC, ro["C"])) <= TOL_COST_REL
+            upd = o.update(gC, to_nhj(out["u"]), mean, sig2)
+            assert np.max(np.abs(mean_new.cpu().numpy() - upd["mean"])) <= TOL_MEAN
+            mean = f32(upd["mean_shift"])
+            sig2 = f32(sig_new.cpu().numpy())
+            gm, gs, gstep = r.get_state()
+            assert np.max(np.abs(gm - mean)) <= TOL_MEAN
+            assert gstep == step + 1
+    finally:
+        r.close()
+
+
+def test_state_roundtrip_reproduces(oracle_lib):
+    """get_state / set_state restore a run bit for bit (counter-based RNG)."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(6, n_particles=200, horizon=30)
+    goal = torch.tensor([1, 0, 0, 0, -1, 0, 0, 0, -1, 0.5, 0.1, 0.4], dtype=torch.float32, device="cuda")
+    r = storm.Rollout(prob)
+    try:
+        for _ in range(3):
+            r.step(goal)
+            r.update()
+        snap = r.get_state()
+        ref = []
+        for _ in range(2):
+            o = r.step(goal)
+            c, m, s = r.update()
+            ref.append((o["C"].clone(), m.clone()))
+        r.set_state(*snap)
+        for k in range(2):
+            o = r.step(goal)
+            c, m, s = r.update()
+            assert torch.equal(o["C"], ref[k][0]) and torch.equal(m, ref[k][1])
+    finally:
+        r.close()
+
+
+def test_nonfinite_cost_keeps_policy():
+    """A non-finite start state makes every cost non-finite: the update keeps
+    mu and sigma2 and raises the status flag (forced from the host)."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config1(0)
+    r = storm.Rollout(prob)
+    try:
+        goal = torch.tensor([1, 0, 0, 0, 1, 0, 0, 0, 1, 0.5, 0, 0.5], dtype=torch.float32, device="cuda")
+        mean0, sig0, _ = r.get_state()
+        x0 = r.x0.clone()
+        x0[0] = float("nan")
+        r.step(goal, x0=x0)
+        cmd, mean, sig = r.update(shift=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(mean.cpu().numpy(), mean0)
+        assert np.array_equal(sig.cpu().numpy(), sig0)
+        assert r.status() & storm.FLAG_NONFINITE_COST
+        assert r.status() == 0  # cleared by the read
+    finally:
+        r.close()
+
+
+def test_abi_errors_on_gpu():
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config1(0)
+    r = storm.Rollout(prob)
+    try:
+        with pytest.raises(storm.StormError) as e:
+            r.update()
+        assert e.value.code == storm.STORM_E_STATE
+    finally:
+        r.close()
