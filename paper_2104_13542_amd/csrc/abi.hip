@@ -119,19 +119,43 @@ void fill_robot_consts(const storm_robot *robot, RobotDev &R)
     R.n_spheres = robot->n_spheres;
 }
 
-// Index list of sphere pairs on bodies at least two apart (self-collision set).
-std::vector<int> self_pairs(const storm_robot *robot)
+// Self-collision work split.  With spheres sorted by body, the partners t > s
+// of sphere s on bodies at least two further along the chain form one
+// contiguous range [t0(s), S).  The pairs, taken s-major, are cut into
+// `waves` nearly equal parts, each written as segments (s, t_begin, t_end).
+// Returns the pair count; off[w] .. off[w + 1] are wave w's segments.
+int self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
 {
-    std::vector<int> idx;
-    for (int s = 0; s < robot->n_spheres; ++s)
-        for (int t = s + 1; t < robot->n_spheres; ++t) {
-            const int bs = (int)robot->spheres[5 * s], bt = (int)robot->spheres[5 * t];
-            if (abs(bs - bt) >= 2) {
-                idx.push_back(s);
-                idx.push_back(t);
+    const int S = robot->n_spheres;
+    std::vector<int> t0(S, S);
+    for (int s = 0; s < S; ++s)
+        for (int t = s + 1; t < S; ++t)
+            if ((int)robot->spheres[5 * t] - (int)robot->spheres[5 * s] >= 2) {
+                t0[s] = t;
+                break;
             }
+    long long total = 0;
+    for (int s = 0; s < S; ++s) total += S - t0[s];
+    seg.clear();
+    off.assign(waves + 1, 0);
+    for (int w = 0; w < waves; ++w) {
+        off[w] = (int)seg.size() / 4;
+        const long long k0 = total * w / waves, k1 = total * (w + 1) / waves;
+        long long base = 0;
+        for (int s = 0; s < S; ++s) {
+            const long long n = S - t0[s];
+            const long long a = k0 > base ? k0 : base, b = k1 < base + n ? k1 : base + n;
+            if (a < b) {
+                seg.push_back(s);
+                seg.push_back(t0[s] + (int)(a - base));
+                seg.push_back(t0[s] + (int)(b - base));
+                seg.push_back(0);
+            }
+            base += n;
         }
-    return idx;
+    }
+    off[waves] = (int)seg.size() / 4;
+    return (int)total;
 }
 
 template <typename T>
@@ -201,14 +225,21 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
 
     const int N = params->n_particles, H = params->horizon;
     const int n_obs = scene ? scene->n_obstacles : 0;
-    std::vector<float> sph_raw, box_raw, obs_sorted;
+    // obstacle records re-ordered: spheres first, then cuboids
+    std::vector<float> obs_sorted;
+    obs_sorted.reserve((size_t)STORM_OBSTACLE_STRIDE * n_obs);
     int n_sph_obs = 0, n_box_obs = 0;
-    for (int o = 0; o < n_obs; ++o) {
-        const float *r = scene->obstacles + STORM_OBSTACLE_STRIDE * o;
-        if (r[0] == (float)STORM_OBSTACLE_SPHERE) ++n_sph_obs; else ++n_box_obs;
-    }
-    const std::vector<int> pair_idx = self_pairs(robot);
-    const int n_pairs = (int)pair_idx.size() / 2;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int o = 0; o < n_obs; ++o) {
+            const float *r = scene->obstacles + STORM_OBSTACLE_STRIDE * o;
+            const bool is_sphere = r[0] == (float)STORM_OBSTACLE_SPHERE;
+            if (is_sphere != (pass == 0)) continue;
+            obs_sorted.insert(obs_sorted.end(), r, r + STORM_OBSTACLE_STRIDE);
+            if (is_sphere) ++n_sph_obs; else ++n_box_obs;
+        }
+    std::vector<int> seg, seg_off;
+    const int n_pairs = self_segments(robot, c->waves, seg, seg_off);
+    const int n_seg = (int)seg.size() / 4;
 
     ProblemDev &P = c->P;
     P.N = N;
@@ -242,10 +273,10 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     c->R.n_pairs = n_pairs;
 
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
-    float4 *sph_obs, *sph_local;
-    int32_t *sph_body;
-    int4 *pairs;
-    int2 *pair_idx_d;
+    float *self_rr2;
+    float4 *sph_obs, *env_sph, *sph_local;
+    int32_t *sph_body, *self_off;
+    int4 *self_seg;
     uint32_t *counters;
     hipError_t e = hipSuccess;
 #define STORM_TRY(expr)        \
@@ -258,22 +289,24 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &tables, storm::kTabSize));
     STORM_TRY(dalloc(c, &halton, (size_t)STORM_DOF * params->n_halton * H));
     STORM_TRY(dalloc(c, &sph_obs, (size_t)n_sph_obs));
+    STORM_TRY(dalloc(c, &env_sph, (size_t)n_sph_obs * robot->n_spheres));
     STORM_TRY(dalloc(c, &box_obs, (size_t)16 * n_box_obs));
     STORM_TRY(dalloc(c, &mean, (size_t)H * STORM_DOF));
     STORM_TRY(dalloc(c, &sigma2, (size_t)STORM_DOF));
     STORM_TRY(dalloc(c, &u, (size_t)STORM_DOF * N * H));
     STORM_TRY(dalloc(c, &C, (size_t)N));
-    STORM_TRY(dalloc(c, &counters, (size_t)2));
+    STORM_TRY(dalloc(c, &counters, (size_t)4));
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
-    STORM_TRY(dalloc(c, &pairs, (size_t)n_pairs));
+    STORM_TRY(dalloc(c, &self_rr2, (size_t)robot->n_spheres * robot->n_spheres));
+    STORM_TRY(dalloc(c, &self_seg, (size_t)n_seg));
+    STORM_TRY(dalloc(c, &self_off, seg_off.size()));
     // staging copies of the host inputs (freed at destroy with the rest)
     STORM_TRY(dalloc(c, &dt_raw, (size_t)H));
     STORM_TRY(dalloc(c, &lim_raw, (size_t)3 * STORM_DOF));
     STORM_TRY(dalloc(c, &sig_raw, (size_t)STORM_DOF));
     STORM_TRY(dalloc(c, &obs_raw, (size_t)STORM_OBSTACLE_STRIDE * n_obs));
     STORM_TRY(dalloc(c, &sph_raw_d, (size_t)5 * robot->n_spheres));
-    STORM_TRY(dalloc(c, &pair_idx_d, (size_t)n_pairs));
     {
         float lim[3 * STORM_DOF];
         for (int j = 0; j < STORM_DOF; ++j) {
@@ -285,17 +318,18 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         STORM_TRY(hipMemcpyAsync(lim_raw, lim, sizeof(lim), hipMemcpyHostToDevice, s));
         STORM_TRY(hipMemcpyAsync(sig_raw, params->sigma_init, sizeof(float) * STORM_DOF, hipMemcpyHostToDevice, s));
         if (n_obs > 0)
-            STORM_TRY(hipMemcpyAsync(obs_raw, scene->obstacles, sizeof(float) * STORM_OBSTACLE_STRIDE * n_obs,
+            STORM_TRY(hipMemcpyAsync(obs_raw, obs_sorted.data(), sizeof(float) * obs_sorted.size(),
                                      hipMemcpyHostToDevice, s));
         if (robot->n_spheres > 0)
             STORM_TRY(hipMemcpyAsync(sph_raw_d, robot->spheres, sizeof(float) * 5 * robot->n_spheres,
                                      hipMemcpyHostToDevice, s));
-        if (n_pairs > 0)
-            STORM_TRY(hipMemcpyAsync(pair_idx_d, pair_idx.data(), sizeof(int) * pair_idx.size(),
-                                     hipMemcpyHostToDevice, s));
+        if (n_seg > 0)
+            STORM_TRY(hipMemcpyAsync(self_seg, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice, s));
+        STORM_TRY(hipMemcpyAsync(self_off, seg_off.data(), sizeof(int) * seg_off.size(), hipMemcpyHostToDevice, s));
         P.tables = tables;
         P.halton = halton;
         P.sph_obs = sph_obs;
+        P.env_sph = env_sph;
         P.box_obs = box_obs;
         P.mean = mean;
         P.sigma2 = sigma2;
@@ -305,11 +339,13 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         P.status = counters + 1;
         c->R.sph_local = sph_local;
         c->R.sph_body = sph_body;
-        c->R.pairs = pairs;
+        c->R.self_rr2 = self_rr2;
+        c->R.self_seg = self_seg;
+        c->R.self_off = self_off;
         STORM_TRY(storm::launch_init_tables(P, dt_raw, lim_raw, params->acc_stop, params->gamma, params->w_term,
                                             params->k_jl, params->k_vl, sig_raw, params->n_knots, obs_raw, n_obs,
-                                            sph_obs, box_obs, sph_raw_d, robot->n_spheres, sph_local, sph_body,
-                                            pairs, pair_idx_d, n_pairs, s));
+                                            sph_obs, env_sph, box_obs, sph_raw_d, robot->n_spheres, sph_local,
+                                            sph_body, self_rr2, s));
         STORM_TRY(hipStreamSynchronize(s));
     }
 #undef STORM_TRY

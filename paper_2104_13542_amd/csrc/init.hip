@@ -41,46 +41,52 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
     }
 }
 
-// Obstacles: spheres keep (centre, radius); cuboids are stored as the
-// world-to-box map l = M x + t with M = R^T, t = -R^T c, plus half extents.
-// Body spheres: (local centre, radius) and the frame index; pairs: the two
-// sphere indices and r_s + r_t and its square.
-__global__ void geometry_kernel(const float *obs_raw, int n_obs, float4 *sph_obs, float *box_obs,
-                                const float *sph_raw, int n_spheres, float4 *sph_local, int32_t *sph_body,
-                                const int2 *pair_idx, int n_pairs, int4 *pairs)
+// Geometry records in device form, one flat index space over all of them.
+//   sphere obstacles: (centre, radius) and, for every body sphere s, the
+//                     record (centre, (r_s + r_o)^2) used by the penetration test
+//   cuboids:          the world-to-box map l = M x + t with M = R^T,
+//                     t = -R^T c, then the half extents
+//   body spheres:     (local centre, radius) and the frame index
+//   self pairs:       (r_s + r_t)^2 for every sphere pair
+__global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float *box_raw, int n_bo,
+                                float4 *sph_obs, float4 *env_sph, float *box_obs, const float *sph_raw, int S,
+                                float4 *sph_local, int32_t *sph_body, float *self_rr2)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) {
-        int ns = 0, nb = 0;
-        for (int o = 0; o < n_obs; ++o) {
-            const float *r = obs_raw + o * STORM_OBSTACLE_STRIDE;
-            if ((int)r[0] == STORM_OBSTACLE_SPHERE) {
-                sph_obs[ns++] = make_float4(r[1], r[2], r[3], r[4]);
-            } else {
-                float *b = box_obs + 16 * nb++;
-                const float *Rw = r + 7;
-                for (int row = 0; row < 3; ++row) {
-                    double tt = 0.0;
-                    for (int c = 0; c < 3; ++c) {
-                        b[row * 3 + c] = Rw[c * 3 + row];
-                        tt -= (double)Rw[c * 3 + row] * (double)r[1 + c];
-                    }
-                    b[9 + row] = (float)tt;
-                    b[12 + row] = r[4 + row];
-                }
-                b[15] = 0.0f;
+    if (t < n_so) {
+        const float *r = sph_obs_raw + t * STORM_OBSTACLE_STRIDE;
+        sph_obs[t] = make_float4(r[1], r[2], r[3], r[4]);
+    }
+    if (t < S * n_so) {
+        const int s = t / n_so, o = t - s * n_so;
+        const float *r = sph_obs_raw + o * STORM_OBSTACLE_STRIDE;
+        const double rr = (double)sph_raw[s * 5 + 4] + (double)r[4];
+        env_sph[t] = make_float4(r[1], r[2], r[3], (float)(rr * rr));
+    }
+    if (t < n_bo) {
+        const float *r = box_raw + t * STORM_OBSTACLE_STRIDE;
+        float *b = box_obs + 16 * t;
+        const float *Rw = r + 7;
+        for (int row = 0; row < 3; ++row) {
+            double tt = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                b[row * 3 + c] = Rw[c * 3 + row];
+                tt -= (double)Rw[c * 3 + row] * (double)r[1 + c];
             }
+            b[9 + row] = (float)tt;
+            b[12 + row] = r[4 + row];
         }
+        b[15] = 0.0f;
     }
-    if (t < n_spheres) {
-        const float *s = sph_raw + t * 5;
-        sph_local[t] = make_float4(s[1], s[2], s[3], s[4]);
-        sph_body[t] = (int32_t)s[0] - 1;
+    if (t < S) {
+        const float *q = sph_raw + t * 5;
+        sph_local[t] = make_float4(q[1], q[2], q[3], q[4]);
+        sph_body[t] = (int32_t)q[0] - 1;
     }
-    if (t < n_pairs) {
-        const int2 p = pair_idx[t];
-        const double rs = (double)sph_raw[p.x * 5 + 4] + (double)sph_raw[p.y * 5 + 4];
-        pairs[t] = make_int4(p.x, p.y, __float_as_int((float)rs), __float_as_int((float)(rs * rs)));
+    if (t < S * S) {
+        const int a = t / S, b = t - a * S;
+        const double rs = (double)sph_raw[a * 5 + 4] + (double)sph_raw[b * 5 + 4];
+        self_rr2[t] = (float)(rs * rs);
     }
 }
 
@@ -174,19 +180,26 @@ __global__ void halton_smooth_kernel(int n_halton, int K, int H, const double *Z
 
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
-                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
-                              const float *d_sph_raw, int n_spheres, float4 *d_sph_local, int32_t *d_sph_body,
-                              int4 *d_pairs, const int2 *d_pair_idx, int n_pairs, hipStream_t stream)
+                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
+                              float *d_box_obs, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
+                              int32_t *d_sph_body, float *d_self_rr2, hipStream_t stream)
 {
+    (void)n_obs;
     hipLaunchKernelGGL(tables_kernel, dim3(1), dim3(kMaxH), 0, stream, P, const_cast<float *>(P.tables), d_dt_raw,
                        d_lim_raw, acc_stop, gamma, w_term, k_jl, k_vl, d_sigma_init);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int ng = n_spheres > n_pairs ? n_spheres : n_pairs;
+    // d_obs_raw holds the sphere records first, then the cuboid records
+    const int S = n_spheres, n_so = P.n_sph_obs, n_bo = P.n_box_obs;
+    int ng = S * S;
+    if (S * n_so > ng) ng = S * n_so;
+    if (n_so > ng) ng = n_so;
+    if (n_bo > ng) ng = n_bo;
     const int gthreads = 256;
     const int gblocks = ng > 0 ? (ng + gthreads - 1) / gthreads : 1;
-    hipLaunchKernelGGL(geometry_kernel, dim3(gblocks), dim3(gthreads), 0, stream, d_obs_raw, n_obs, d_sph_obs,
-                       d_box_obs, d_sph_raw, n_spheres, d_sph_local, d_sph_body, d_pair_idx, n_pairs, d_pairs);
+    hipLaunchKernelGGL(geometry_kernel, dim3(gblocks), dim3(gthreads), 0, stream, d_obs_raw, n_so,
+                       d_obs_raw + (size_t)STORM_OBSTACLE_STRIDE * n_so, n_bo, d_sph_obs, d_env_sph, d_box_obs,
+                       d_sph_raw, S, d_sph_local, d_sph_body, d_self_rr2);
     e = hipGetLastError();
     if (e != hipSuccess || P.n_halton == 0) return e;
     double *Z = nullptr;

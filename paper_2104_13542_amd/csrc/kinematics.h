@@ -84,7 +84,7 @@ __device__ __forceinline__ float manipulability(const float z[kDof][3], const fl
         }
         if (!(di > 0.0f)) det = 0.0f;
     }
-    return det > 0.0f ? sqrtf(det) : 0.0f;
+    return det > 0.0f ? fast_sqrt(det) : 0.0f;
 }
 
 }  // namespace storm

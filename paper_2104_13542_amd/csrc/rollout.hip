@@ -176,9 +176,9 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
             ev = fmaf(b, b, ev);
             es = fmaf(c, c, es);
         }
-        s_terms[2 * kLanes + lane] = sqrtf(ej);
-        s_terms[3 * kLanes + lane] = sqrtf(ev);
-        s_terms[4 * kLanes + lane] = sqrtf(es);
+        s_terms[2 * kLanes + lane] = fast_sqrt(ej);
+        s_terms[3 * kLanes + lane] = fast_sqrt(ev);
+        s_terms[4 * kLanes + lane] = fast_sqrt(es);
     }
     __syncthreads();
 
@@ -186,60 +186,154 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
     const bool need_centres = (mask & (STORM_COST_SELF | STORM_COST_ENV)) != 0;
     if (need_centres) {
         for (int s = wave; s < S; s += W) {
-            const float4 sl = R.sph_local[s];
-            const float *F = s_fr + R.sph_body[s] * 12 * kLanes + lane;
+            const STORM_CONST_AS float *sl = uniform_ptr(reinterpret_cast<const float *>(R.sph_local)) + 4 * s;
+            const float *F = s_fr + uniform_ptr(R.sph_body)[s] * 12 * kLanes + lane;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 s_cen[(s * 3 + c) * kLanes + lane] =
-                    fmaf(F[(c * 3 + 0) * kLanes], sl.x,
-                         fmaf(F[(c * 3 + 1) * kLanes], sl.y, fmaf(F[(c * 3 + 2) * kLanes], sl.z, F[(9 + c) * kLanes])));
+                    fmaf(F[(c * 3 + 0) * kLanes], sl[0],
+                         fmaf(F[(c * 3 + 1) * kLanes], sl[1], fmaf(F[(c * 3 + 2) * kLanes], sl[2], F[(9 + c) * kLanes])));
         }
         __syncthreads();
     }
 
     // ---- D: collision terms, pose, manipulability -----------------------------
+    // Both collision loops test four records per round: the squared distance
+    // of each is compared with its squared contact distance, the four lane
+    // masks are OR-ed in SGPRs and the square roots (penetration depths) run
+    // only when some lane of the wave touches one of them.
     float env = 0.0f, selfpen = 0.0f;
     if (mask & STORM_COST_ENV) {
+        const STORM_CONST_AS float *esph = uniform_ptr(reinterpret_cast<const float *>(P.env_sph));
+        const STORM_CONST_AS float *box = uniform_ptr(P.box_obs);
+        const STORM_CONST_AS float *sloc = uniform_ptr(reinterpret_cast<const float *>(R.sph_local));
+        const int nso = P.n_sph_obs, nbo = P.n_box_obs;
         for (int s = wave; s < S; s += W) {
             const float x = s_cen[(s * 3 + 0) * kLanes + lane];
             const float y = s_cen[(s * 3 + 1) * kLanes + lane];
             const float z = s_cen[(s * 3 + 2) * kLanes + lane];
-            const float rs = R.sph_local[s].w;
+            const float rs = sloc[4 * s + 3];
             const float rs2 = rs * rs;
             float best = 0.0f;
-            for (int o = 0; o < P.n_sph_obs; ++o) {
-                const float4 ob = P.sph_obs[o];
-                const float dx = x - ob.x, dy = y - ob.y, dz = z - ob.z;
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float rr = rs + ob.w;
-                if (d2 < rr * rr) best = fmaxf(best, rr - sqrtf(d2));
+            const STORM_CONST_AS float *row = esph + (size_t)4 * s * nso;
+            int o = 0;
+            for (; o + 4 <= nso; o += 4) {
+                float d2[4];
+                bool hit[4];
+                uint64_t any = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const STORM_CONST_AS float *ob = row + 4 * (o + m);
+                    const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
+                    d2[m] = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    hit[m] = d2[m] < ob[3];
+                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
+                }
+                if (__builtin_expect(any != 0, 0)) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const float pen = fast_sqrt(row[4 * (o + m) + 3]) - fast_sqrt(d2[m]);
+                        if (hit[m]) best = fmaxf(best, pen);
+                    }
+                }
             }
-            for (int o = 0; o < P.n_box_obs; ++o) {
-                const float *b = P.box_obs + o * 16;
-                const float lx = fmaf(b[0], x, fmaf(b[1], y, fmaf(b[2], z, b[9])));
-                const float ly = fmaf(b[3], x, fmaf(b[4], y, fmaf(b[5], z, b[10])));
-                const float lz = fmaf(b[6], x, fmaf(b[7], y, fmaf(b[8], z, b[11])));
-                const float qx = fabsf(lx) - b[12], qy = fabsf(ly) - b[13], qz = fabsf(lz) - b[14];
+            for (; o < nso; ++o) {
+                const STORM_CONST_AS float *ob = row + 4 * o;
+                const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const bool hit = d2 < ob[3];
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
+                    const float pen = fast_sqrt(ob[3]) - fast_sqrt(d2);
+                    if (hit) best = fmaxf(best, pen);
+                }
+            }
+            int b = 0;
+            for (; b + 2 <= nbo; b += 2) {
+                float out2[2], qin[2];
+                bool hit[2];
+                uint64_t any = 0;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const STORM_CONST_AS float *bb = box + (size_t)(b + m) * 16;
+                    const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
+                    const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
+                    const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
+                    const float qx = fabsf(lx) - bb[12], qy = fabsf(ly) - bb[13], qz = fabsf(lz) - bb[14];
+                    const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
+                    out2[m] = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+                    qin[m] = fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);
+                    hit[m] = out2[m] < rs2;
+                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
+                }
+                if (__builtin_expect(any != 0, 0)) {
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) {
+                        const float pen = rs - (fast_sqrt(out2[m]) + qin[m]);
+                        if (hit[m]) best = fmaxf(best, pen);
+                    }
+                }
+            }
+            for (; b < nbo; ++b) {
+                const STORM_CONST_AS float *bb = box + (size_t)b * 16;
+                const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
+                const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
+                const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
+                const float qx = fabsf(lx) - bb[12], qy = fabsf(ly) - bb[13], qz = fabsf(lz) - bb[14];
                 const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
                 const float out2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
-                if (out2 < rs2) {
-                    const float sdf = sqrtf(out2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);
-                    best = fmaxf(best, rs - sdf);
+                const bool hit = out2 < rs2;
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
+                    const float pen = rs - (fast_sqrt(out2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f));
+                    if (hit) best = fmaxf(best, pen);
                 }
             }
             env += best;
         }
     }
     if (mask & STORM_COST_SELF) {
-        const int np = R.n_pairs;
-        const int k0 = (int)(((long long)np * wave) / W), k1 = (int)(((long long)np * (wave + 1)) / W);
-        for (int k = k0; k < k1; ++k) {
-            const int4 pr = R.pairs[k];
-            const float dx = s_cen[(pr.x * 3 + 0) * kLanes + lane] - s_cen[(pr.y * 3 + 0) * kLanes + lane];
-            const float dy = s_cen[(pr.x * 3 + 1) * kLanes + lane] - s_cen[(pr.y * 3 + 1) * kLanes + lane];
-            const float dz = s_cen[(pr.x * 3 + 2) * kLanes + lane] - s_cen[(pr.y * 3 + 2) * kLanes + lane];
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            if (d2 < __int_as_float(pr.w)) selfpen = fmaxf(selfpen, __int_as_float(pr.z) - sqrtf(d2));
+        const STORM_CONST_AS int32_t *segs = uniform_ptr(reinterpret_cast<const int32_t *>(R.self_seg));
+        const STORM_CONST_AS int32_t *off = uniform_ptr(R.self_off);
+        const STORM_CONST_AS float *rr2 = uniform_ptr(R.self_rr2);
+        const int g1 = off[wave + 1];
+        for (int g = off[wave]; g < g1; ++g) {
+            const int ss = segs[4 * g], t_end = segs[4 * g + 2];
+            const float cx = s_cen[(ss * 3 + 0) * kLanes + lane];
+            const float cy = s_cen[(ss * 3 + 1) * kLanes + lane];
+            const float cz = s_cen[(ss * 3 + 2) * kLanes + lane];
+            const STORM_CONST_AS float *row = rr2 + (size_t)ss * S;
+            int t = segs[4 * g + 1];
+            for (; t + 4 <= t_end; t += 4) {
+                float d2[4];
+                bool hit[4];
+                uint64_t any = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float dx = cx - s_cen[((t + m) * 3 + 0) * kLanes + lane];
+                    const float dy = cy - s_cen[((t + m) * 3 + 1) * kLanes + lane];
+                    const float dz = cz - s_cen[((t + m) * 3 + 2) * kLanes + lane];
+                    d2[m] = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    hit[m] = d2[m] < row[t + m];
+                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
+                }
+                if (__builtin_expect(any != 0, 0)) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const float pen = fast_sqrt(row[t + m]) - fast_sqrt(d2[m]);
+                        if (hit[m]) selfpen = fmaxf(selfpen, pen);
+                    }
+                }
+            }
+            for (; t < t_end; ++t) {
+                const float dx = cx - s_cen[(t * 3 + 0) * kLanes + lane];
+                const float dy = cy - s_cen[(t * 3 + 1) * kLanes + lane];
+                const float dz = cz - s_cen[(t * 3 + 2) * kLanes + lane];
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const bool hit = d2 < row[t];
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
+                    const float pen = fast_sqrt(row[t]) - fast_sqrt(d2);
+                    if (hit) selfpen = fmaxf(selfpen, pen);
+                }
+            }
         }
     }
     s_penv[wave * kLanes + lane] = env;
@@ -269,8 +363,8 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
             const float e = P.alpha_pos[r] * l;
             pos2 = fmaf(e, e, pos2);
         }
-        s_terms[0 * kLanes + lane] = sqrtf(pos2);
-        s_terms[1 * kLanes + lane] = sqrtf(rot2);
+        s_terms[0 * kLanes + lane] = fast_sqrt(pos2);
+        s_terms[1 * kLanes + lane] = fast_sqrt(rot2);
     }
     if (wave == W - 2 && (mask & STORM_COST_MANIP)) {
         float z[kDof][3], o[kDof][3], pe[3];

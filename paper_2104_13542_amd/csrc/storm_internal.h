@@ -25,6 +25,7 @@ constexpr int kTabVlo = 208;        // band-shrunk joint velocity limits [7]
 constexpr int kTabVhi = 216;
 constexpr int kTabSize = 224;
 
+
 // Per-problem description read by the kernels.  All pointers are device memory.
 struct ProblemDev {
     int32_t N, H, n_halton, n_null;
@@ -37,6 +38,7 @@ struct ProblemDev {
     const float *tables;    // [kTabSize]
     const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
     const float4 *sph_obs;  // [n_sph_obs] centre, radius
+    const float4 *env_sph;  // [S][n_sph_obs] obstacle centre, (r_s + r_o)^2 for body sphere s
     const float *box_obs;   // [n_box_obs][16]: M = R^T (9, row-major), t = -R^T c (3), half extents (3), pad
     float *mean;            // [H][7]
     float *sigma2;          // [7]
@@ -52,8 +54,22 @@ struct RobotDev {
     int32_t n_spheres, n_pairs, pad0, pad1;
     const float4 *sph_local;  // [S] body-frame centre (x, y, z), radius
     const int32_t *sph_body;  // [S] frame index 0..7 the sphere is attached to
-    const int4 *pairs;        // [P] (s, t, bits(r_s + r_t), bits((r_s + r_t)^2)), bodies >= 2 apart
+    const float *self_rr2;    // [S][S] (r_s + r_t)^2
+    const int4 *self_seg;     // self-collision segments (s, t_begin, t_end, 0): pairs (s, t), bodies >= 2 apart
+    const int32_t *self_off;  // [W + 1] segment range of each wave of the rollout workgroup
 };
+
+// Wave-uniform reads through the constant address space: the backend turns
+// them into scalar loads whose results feed VALU instructions as SGPR operands.
+#define STORM_CONST_AS __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const STORM_CONST_AS T *uniform_ptr(const T *p)
+{
+    return (const STORM_CONST_AS T *)(p);
+}
+
+// Hardware square root (v_sqrt_f32, 1 ulp) for norms and distances.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Optional per-step outputs.
 struct StepOut {
@@ -63,9 +79,9 @@ struct StepOut {
 // Launchers (defined in the .hip translation units).
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
-                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
-                              const float *d_sph_raw, int n_spheres, float4 *d_sph_local, int32_t *d_sph_body,
-                              int4 *d_pairs, const int2 *d_pair_idx, int n_pairs, hipStream_t stream);
+                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
+                              float *d_box_obs, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
+                              int32_t *d_sph_body, float *d_self_rr2, hipStream_t stream);
 hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,
                           const float *noise, const StepOut &out, int waves, hipStream_t stream);
 // Raise the dynamic-LDS limit of the rollout kernels to what the largest
