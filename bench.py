@@ -127,42 +127,64 @@ def main():
     C = torch.empty(N, dtype=torch.float32, device="cuda")
     cmd = torch.empty(7, dtype=torch.float32, device="cuda")
 
-    def one_step():
-        r.step(goal, C=C)
+    x0 = r.x0.clone()
+    # one control step = one launch of the captured graph (step + update + shift)
+    graph = r.graph(x0, goal, cmd, iterations=1, shift=True)
+
+    def eager_step():
+        r.step(goal, x0=x0, C=C)
         r.update(shift=True, want_mean=False, cmd=cmd)
 
     for _ in range(args.warmup):
-        one_step()
+        graph.launch()
+        eager_step()
     torch.cuda.synchronize()
 
     K = args.steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
-    for k in range(K):
-        ev[k][0].record()
-        r.step(goal, C=C)
-        ev[k][1].record()
-        r.update(shift=True, want_mean=False, cmd=cmd)
+    for _ in range(K):
+        graph.launch()
     end.record()
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
-    rollout_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ms_per_step = total_ms / K
     value = N * H * K / (total_ms * 1e-3)
+
+    # the rollout kernel alone, launch after launch, timed by HIP events on
+    # the stream it runs on (its average duration prices the roofline)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    for k in range(K):
+        ev[k][0].record()
+        r.step(goal, x0=x0, C=C)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    rollout_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    r.update(shift=True, want_mean=False, cmd=cmd)
+
+    # eager (two launches per step from the host) for comparison
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(K):
+        eager_step()
+    end.record()
+    torch.cuda.synchronize()
+    eager_ms = start.elapsed_time(end) / K
 
     # latency: enqueue -> command readable on the host
     lat = []
     cmd_host = torch.empty(7, dtype=torch.float32, pin_memory=True)
     for _ in range(args.latency_steps):
         t0 = time.perf_counter()
-        one_step()
+        graph.launch()
         cmd_host.copy_(cmd, non_blocking=True)
         torch.cuda.current_stream().synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
     lat = np.array(lat)
+    graph.close()
     r.close()
 
     n_sph = prob.spheres.shape[0]
@@ -195,6 +217,8 @@ def main():
         },
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "steps": int(len(lat))},
+        "launch": "one HIP graph launch per control step (rollout + update + shift)",
+        "eager_ms_per_step": eager_ms,
         "roofline": {
             "kernel": "rollout_kernel",
             "bound": "alu",

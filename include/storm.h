@@ -186,6 +186,28 @@ int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, u
 int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float *h_sigma2, const uint32_t *h_step,
                                 void *stream);
 
+/* Opaque handle of an instantiated HIP graph of one control step. */
+typedef struct storm_graph_s *storm_graph;
+
+/* Capture one whole control step of Alg. 1 into a HIP graph: `iterations`
+ * (K >= 1) rounds of storm_rollout_step + storm_rollout_update, the shift
+ * applied after the last round only, reading d_x0 [3][7] and d_goal [12]
+ * and writing d_cmd [7] (device buffers whose addresses are baked into the
+ * graph: refresh their contents before each launch).  `stream` is used for
+ * the capture (NULL: a private stream); the context must not be used on
+ * any other stream during the call.  Each launch advances the sampling step
+ * counter like the eager calls.  Errors: E_NULL, E_RANGE (iterations < 1),
+ * E_DEVICE. */
+int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                                   int32_t iterations, int32_t shift, void *stream, storm_graph *out);
+
+/* Enqueue one captured control step on `stream`.  Allocates nothing.
+ * Errors: E_NULL, E_DEVICE. */
+int32_t storm_rollout_graph_launch(storm_graph graph, void *stream);
+
+/* Free a captured graph (NULL is a no-op). */
+int32_t storm_rollout_graph_destroy(storm_graph graph);
+
 /* Batched forward kinematics of the robot (Sec. 3.1, Eq. 8): for n joint
  * configurations d_q [7][n], writes the flange pose d_pose [12][n] (R
  * row-major, then p) and, if d_manip is not NULL, the manipulability

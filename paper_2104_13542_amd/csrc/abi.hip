@@ -477,6 +477,75 @@ int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float 
     return STORM_OK;
 }
 
+struct storm_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    storm_ctx ctx = nullptr;
+};
+
+int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                                   int32_t iterations, int32_t shift, void *stream, storm_graph *out)
+{
+    if (!out) return STORM_E_NULL;
+    *out = nullptr;
+    if (!ctx || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
+    if (iterations < 1) return STORM_E_RANGE;
+    if (ctx->error != STORM_OK) return ctx->error;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStream_t own = nullptr;
+    if (s == nullptr) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return STORM_E_DEVICE;
+        s = own;
+    }
+    storm_graph g = new (std::nothrow) storm_graph_s();
+    if (!g) {
+        if (own) (void)hipStreamDestroy(own);
+        return STORM_E_NOMEM;
+    }
+    g->ctx = ctx;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    StepOut none{};
+    for (int k = 0; e == hipSuccess && k < iterations; ++k) {
+        e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, nullptr, none, ctx->waves, s);
+        if (e == hipSuccess)
+            e = storm::launch_update(ctx->P, nullptr, nullptr, d_cmd, (k == iterations - 1) && shift != 0, s);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    g->graph = graph;
+    if (own) (void)hipStreamDestroy(own);
+    if (e != hipSuccess) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return STORM_E_DEVICE;
+    }
+    *out = g;
+    return STORM_OK;
+}
+
+int32_t storm_rollout_graph_launch(storm_graph graph, void *stream)
+{
+    if (!graph) return STORM_E_NULL;
+    if (graph->ctx->error != STORM_OK) return graph->ctx->error;
+    if (hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        graph->ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    return STORM_OK;
+}
+
+int32_t storm_rollout_graph_destroy(storm_graph graph)
+{
+    if (!graph) return STORM_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return STORM_OK;
+}
+
 int32_t storm_fk(const storm_robot *robot, const float *d_q, int32_t n, float *d_pose, float *d_manip, void *stream)
 {
     if (!robot) return STORM_E_NULL;

@@ -16,7 +16,8 @@
 //   D   all waves  environment (spheres x obstacles) and self-collision
 //                  (sphere pairs) split over waves; pose cost (Eq. 9) and
 //                  manipulability (Eq. 12) on the last two waves
-//   E   wave 0     weighted running cost (Eq. 15), horizon sum (Eq. 2)
+//   E   wave 0     weighted running cost (Eq. 15), horizon sum (Eq. 2) as a
+//                  segmented shuffle scan
 // Obstacle, sphere and pair records are indexed by wave-uniform loop
 // counters, so they are fetched with scalar loads into SGPRs; every per-point
 // LDS array is [row][lane] (conflict-free).  Reductions run in a fixed order:
@@ -90,7 +91,6 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
     float *s_penv = s_cen + 3 * S * kLanes; // [W][64]
     float *s_pself = s_penv + W * kLanes;   // [W][64]
     float *s_terms = s_pself + W * kLanes;  // [8][64]
-    float *s_cw = s_terms + 8 * kLanes;     // [64]
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -102,6 +102,14 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
     const bool live = valid && i < N - P.n_null;  // sampled (non-null) particle
     const uint32_t mask = P.cost_mask;
     const float *__restrict__ tab = P.tables;
+
+    // Per-joint inputs of phase A1, loaded up front so that their latency
+    // overlaps the noise generation.
+    const int jw = wave < kDof ? wave : 0;
+    const float mu_j = live ? P.mean[h * kDof + jw] : 0.0f;
+    const float sig_j = sqrtf(P.sigma2[jw]);
+    const float dt_h = tab[kTabDt + h];
+    const float q0_j = x0[jw], v0_j = x0[kDof + jw];
 
     // ---- A0: standard noise ------------------------------------------------
     if (wave < 2) {
@@ -132,10 +140,9 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
     if (wave < kDof) {
         const int j = wave;
         float u = 0.0f;
-        if (live) u = fmaf(sqrtf(P.sigma2[j]), s_eps[j * kLanes + lane], P.mean[h * kDof + j]);
-        const float dt = tab[kTabDt + h];
-        const float v = x0[kDof + j] + segmented_scan(dt * u, h, H);
-        const float q = x0[j] + segmented_scan(dt * v, h, H);
+        if (live) u = fmaf(sig_j, s_eps[j * kLanes + lane], mu_j);
+        const float v = v0_j + segmented_scan(dt_h * u, h, H);
+        const float q = q0_j + segmented_scan(dt_h * v, h, H);
         s_q[j * kLanes + lane] = q;
         s_v[j * kLanes + lane] = v;
         if (valid) {
@@ -417,23 +424,19 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
 #pragma unroll
                 for (int k = 0; k < kTerms; ++k) out.terms[((size_t)k * N + i) * H + h] = t[k];
         }
-        s_cw[lane] = tab[kTabHw + h] * c;
-    }
-    __syncthreads();
-    if (wave == 0 && lane < P.ppt) {
-        const int ip = blockIdx.x * P.ppt + lane;
-        if (ip < N) {
-            float acc = 0.0f;
-            for (int k = 0; k < H; ++k) acc += s_cw[lane * H + k];
-            P.C[ip] = acc;
-            if (out.C) out.C[ip] = acc;
+        // horizon cost (Eq. 2): segmented inclusive scan of the weighted
+        // running costs; the particle's last lane holds its total
+        const float C_i = segmented_scan(tab[kTabHw + h] * c, h, H);
+        if (valid && h == H - 1) {
+            P.C[i] = C_i;
+            if (out.C) out.C[i] = C_i;
         }
     }
 }
 
 size_t rollout_lds_bytes(int S, int W)
 {
-    return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms + 1) * kLanes * sizeof(float);
+    return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms) * kLanes * sizeof(float);
 }
 
 }  // namespace

@@ -7,9 +7,9 @@
 //             + alpha_sigma mean_h sum_i w_i (u_ih - mu'_h)^2   (per joint)
 //
 // One workgroup of 1024 threads per problem.  Weights are staged in LDS in
-// chunks; threads are laid out (row r, column (j, h)) and row r accumulates
-// the particles r, r + R, ... of its column with four independent partial
-// sums, so that each thread keeps four loads in flight.  The variance about
+// chunks.  Two wavefronts per joint stream that joint's controls u[j][*][*]
+// in contiguous rows of H floats, sixteen loads in flight per lane, and
+// accumulate per step; the partial sums are merged in a fixed order.  The variance about
 // the new mean comes from the moments about the old one,
 // sum w (d - delta)^2 = S2/S0 - 2 delta S1/S0 + delta^2, in one pass.  Every
 // sum has a fixed order (results are bitwise reproducible); no atomics on
@@ -22,6 +22,7 @@ namespace {
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / kLanes;
 constexpr int kWChunk = 8192;  // weights staged in LDS per chunk of particles
+constexpr int kUnroll = 16;    // independent loads in flight per lane
 
 __device__ __forceinline__ float wave_sum(float x)
 {
@@ -37,12 +38,17 @@ __device__ __forceinline__ float wave_min(float x)
     return x;
 }
 
+// Moment layout.  A lane owns one step h and one "slot" p of a particle
+// group: with H <= 32 a wavefront reads two particles per load (lanes 0-31
+// and 32-63, each a contiguous run of H floats of u[j][i][.]), otherwise one.
+// Work items are (joint j, group range); the 16 waves take them in order and
+// each lane keeps its own sums, merged at the end in a fixed order.
 __global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *__restrict__ mean_out,
                                                           float *__restrict__ sigma2_out, float *__restrict__ cmd,
                                                           int shift)
 {
     __shared__ float s_w[kWChunk];
-    __shared__ float s_red[2 * kThreads];
+    __shared__ float s_part[2][kWaves][kLanes];
     __shared__ float s_wave[kWaves];
     __shared__ float s_mu[kDof * kMaxH];
     __shared__ float s_v[kDof * kMaxH];
@@ -50,7 +56,6 @@ __global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *_
     const int t = threadIdx.x;
     const int lane = t & (kLanes - 1), wave = t / kLanes;
     const int N = P.N, H = P.H;
-    const int ncol = kDof * H;
     const float beta = P.beta;
     const float *__restrict__ C = P.C;
 
@@ -80,69 +85,87 @@ __global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *_
     for (int k = 0; k < kWaves; ++k) S0 += s_wave[k];
     const bool ok = !any_nonfinite && S0 > 0.0f && isfinite(S0);
 
-    // weighted first and second moments of d = u - mu per (joint, step) column
-    const int rows = kThreads / ncol;  // >= 2 for H <= 64
-    const int r = t / ncol, col = t - r * ncol;
-    const bool act = r < rows;
-    const int j = col / H, h = col - j * H;
-    const float mu = act ? P.mean[h * kDof + j] : 0.0f;
-    const float *__restrict__ U = P.u + (size_t)j * N * H + h;
-    float a1[4] = {0.0f, 0.0f, 0.0f, 0.0f}, a2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // moments of d = u - mu: two waves per joint (14 of the 16 waves), each
+    // over half of the particle groups
+    const int per = H <= 32 ? 2 : 1;        // particles per wavefront load
+    const int seg = H <= 32 ? 32 : 64;      // lanes per particle slot
+    const int slot = lane / seg, h = lane - slot * seg;
+    const bool lane_ok = h < H;
+    const int groups = (N + per - 1) / per;
+    const int j = wave >> 1, half = wave & 1;
+    const bool wave_ok = wave < 2 * kDof;
+    const int g_lo = half ? groups / 2 : 0, g_hi = half ? groups : groups / 2;
+    const float mu = (wave_ok && lane_ok) ? P.mean[h * kDof + j] : 0.0f;
+    const float *__restrict__ U = P.u + (size_t)(wave_ok ? j : 0) * N * H;
+    float s1 = 0.0f, s2 = 0.0f;
     for (int c0 = 0; c0 < N; c0 += kWChunk) {
         const int nc = min(kWChunk, N - c0);
         __syncthreads();
         for (int k = t; k < nc; k += kThreads) s_w[k] = expf(-(C[c0 + k] - cmin) / beta);
         __syncthreads();
-        if (act && ok) {
-            int k = r;
-            for (; k + 3 * rows < nc; k += 4 * rows) {
-                float d[4];
+        if (!(wave_ok && lane_ok && ok)) continue;
+        // groups whose particle lies in [c0, c0 + nc)
+        const int ga = max(g_lo, (c0 + per - 1) / per), gb = min(g_hi, (c0 + nc + per - 1) / per);
+        int g = ga;
+        for (; g + kUnroll <= gb; g += kUnroll) {
+            float uv[kUnroll];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) d[m] = U[(size_t)(c0 + k + m * rows) * H] - mu;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const float wd = s_w[k + m * rows] * d[m];
-                    a1[m] += wd;
-                    a2[m] = fmaf(wd, d[m], a2[m]);
-                }
+            for (int m = 0; m < kUnroll; ++m) {
+                const int i = (g + m) * per + slot;
+                uv[m] = i < N ? U[(size_t)i * H + h] : mu;
             }
-            for (; k < nc; k += rows) {
-                const float d = U[(size_t)(c0 + k) * H] - mu;
-                const float wd = s_w[k] * d;
-                a1[0] += wd;
-                a2[0] = fmaf(wd, d, a2[0]);
+#pragma unroll
+            for (int m = 0; m < kUnroll; ++m) {
+                const int i = (g + m) * per + slot;
+                const float d = uv[m] - mu;
+                const float wd = (i < N ? s_w[i - c0] : 0.0f) * d;
+                s1 += wd;
+                s2 = fmaf(wd, d, s2);
+            }
+        }
+        for (; g < gb; ++g) {
+            const int i = g * per + slot;
+            if (i < N) {
+                const float d = U[(size_t)i * H + h] - mu;
+                const float wd = s_w[i - c0] * d;
+                s1 += wd;
+                s2 = fmaf(wd, d, s2);
             }
         }
     }
-    s_red[t] = (a1[0] + a1[1]) + (a1[2] + a1[3]);
-    s_red[kThreads + t] = (a2[0] + a2[1]) + (a2[2] + a2[3]);
+    s_part[0][wave][lane] = s1;
+    s_part[1][wave][lane] = s2;
     __syncthreads();
-    if (t < ncol) {
-        float s1 = 0.0f, s2 = 0.0f;
-        for (int k = 0; k < rows; ++k) {
-            s1 += s_red[k * ncol + t];
-            s2 += s_red[kThreads + k * ncol + t];
-        }
-        const float muo = P.mean[h * kDof + j];
-        const float m1 = s1 / S0, m2 = s2 / S0;
+    // column (j, h): waves 2j and 2j+1, slots in order
+    for (int col = t; col < kDof * H; col += kThreads) {
+        const int jj = col / H, hh = col - jj * H;
+        float a1 = 0.0f, a2 = 0.0f;
+        for (int w = 2 * jj; w < 2 * jj + 2; ++w)
+            for (int sl = 0; sl < per; ++sl) {
+                a1 += s_part[0][w][sl * seg + hh];
+                a2 += s_part[1][w][sl * seg + hh];
+            }
+        const float muo = P.mean[hh * kDof + jj];
+        const float m1 = a1 / S0, m2 = a2 / S0;
         const float delta = P.alpha_mu * m1;
-        s_mu[t] = ok ? muo + delta : muo;
-        s_v[t] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
+        s_mu[col] = ok ? muo + delta : muo;
+        s_v[col] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
     }
     __syncthreads();
     if (t < kDof) {
         float acc = 0.0f;
         for (int k = 0; k < H; ++k) acc += s_v[t * H + k];
         const float old = P.sigma2[t];
-        float s2 = old;
-        if (ok) s2 = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
-        P.sigma2[t] = s2;
-        if (sigma2_out) sigma2_out[t] = s2;
+        float s2n = old;
+        if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
+        P.sigma2[t] = s2n;
+        if (sigma2_out) sigma2_out[t] = s2n;
         cmd[t] = s_mu[t * H];
     }
-    if (t < ncol) {
-        if (mean_out) mean_out[h * kDof + j] = s_mu[t];
-        P.mean[h * kDof + j] = shift ? (h + 1 < H ? s_mu[t + 1] : 0.0f) : s_mu[t];
+    for (int col = t; col < kDof * H; col += kThreads) {
+        const int jj = col / H, hh = col - jj * H;
+        if (mean_out) mean_out[hh * kDof + jj] = s_mu[col];
+        P.mean[hh * kDof + jj] = shift ? (hh + 1 < H ? s_mu[col + 1] : 0.0f) : s_mu[col];
     }
     if (t == 0) {
         *P.step = *P.step + 1u;

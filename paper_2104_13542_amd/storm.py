@@ -79,7 +79,7 @@ _lib = None
 EXPORTS = (
     "storm_rollout_init", "storm_rollout_step", "storm_rollout_update", "storm_rollout_destroy",
     "storm_rollout_status", "storm_rollout_get_state", "storm_rollout_set_state", "storm_fk",
-    "storm_status_str",
+    "storm_status_str", "storm_rollout_graph_create", "storm_rollout_graph_launch", "storm_rollout_graph_destroy",
 )
 
 
@@ -103,6 +103,9 @@ def lib():
         L.storm_rollout_get_state.argtypes = [vp, vp, vp, vp, vp]
         L.storm_rollout_set_state.argtypes = [vp, vp, vp, vp, vp]
         L.storm_fk.argtypes = [ctypes.POINTER(storm_robot), vp, i32, vp, vp, vp]
+        L.storm_rollout_graph_create.argtypes = [vp, vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+        L.storm_rollout_graph_launch.argtypes = [vp, vp]
+        L.storm_rollout_graph_destroy.argtypes = [vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_char_p if name == "storm_status_str" else i32
         _lib = L
@@ -254,10 +257,50 @@ class Rollout:
                                              None if st is None else ctypes.addressof(st), _stream()),
                "storm_rollout_set_state")
 
+    def graph(self, x0, goal, cmd, iterations=1, shift=True):
+        """Capture one control step (K iterations) into a HIP graph reading
+        x0 / goal and writing cmd (device tensors whose storage must outlive
+        the graph)."""
+        return StepGraph(self, x0, goal, cmd, iterations, shift)
+
     def status(self):
         f = ctypes.c_uint32()
         _check(lib().storm_rollout_status(self._h, ctypes.byref(f), _stream()), "storm_rollout_status")
         return f.value
+
+
+class StepGraph:
+    """A captured control step; launch() enqueues it on the current stream."""
+
+    def __init__(self, rollout, x0, goal, cmd, iterations, shift):
+        self.rollout = rollout
+        self._keep = (x0, goal, cmd)
+        h = ctypes.c_void_p()
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            _check(lib().storm_rollout_graph_create(rollout._h, _ptr(x0), _ptr(goal), _ptr(cmd), int(iterations),
+                                                    int(bool(shift)), _stream(), ctypes.byref(h)),
+                   "storm_rollout_graph_create")
+        torch.cuda.current_stream().wait_stream(stream)
+        self._h = h
+        self._launch = lib().storm_rollout_graph_launch
+
+    def launch(self, stream=None):
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream if stream is None else stream)
+        code = self._launch(self._h, s)
+        if code != STORM_OK:
+            raise StormError(code, "storm_rollout_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().storm_rollout_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fk(q, spheres=None):

@@ -281,3 +281,37 @@ def test_abi_errors_on_gpu():
         assert e.value.code == storm.STORM_E_STATE
     finally:
         r.close()
+
+
+@pytest.mark.parametrize("iterations", [1, 2])
+def test_graph_replays_match_eager(iterations):
+    """A captured control step (K iterations of step + update, shift on the
+    last) replayed several times, with eager work and host synchronisation
+    between the replays, equals the eager calls bit for bit at every replay."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(7, n_particles=300, horizon=30)
+    eager = storm.Rollout(prob)
+    graphed = storm.Rollout(prob)
+    try:
+        x0 = eager.x0.clone()
+        goal = torch.tensor([1, 0, 0, 0, -1, 0, 0, 0, -1, 0.45, 0.1, 0.5], dtype=torch.float32, device="cuda")
+        cmd_g = torch.zeros(7, dtype=torch.float32, device="cuda")
+        g = graphed.graph(x0, goal, cmd_g, iterations=iterations, shift=True)
+        for rep in range(4):
+            for k in range(iterations):
+                eager.step(goal, x0=x0)
+                cmd_e, _, _ = eager.update(shift=(k == iterations - 1))
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(cmd_e, cmd_g), rep
+            me, se, ste = eager.get_state()
+            mg, sg, stg = graphed.get_state()
+            assert np.array_equal(me, mg) and np.array_equal(se, sg) and ste == stg == iterations * (rep + 1)
+            # eager work on the graphed context's inputs between replays
+            x0.add_(0.001)
+            torch.cuda.synchronize()
+        g.close()
+    finally:
+        eager.close()
+        graphed.close()
