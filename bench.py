@@ -98,6 +98,98 @@ def cpu_baseline(prob, budget_s):
     }
 
 
+def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
+    """Batched form: n_problems problems of the uneven batched workload in one
+    persistent launch per control step (graph-captured), against the plain
+    form launching one captured graph per problem."""
+    import numpy as np
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    probs = [inputs.config3_problem(p) for p in range(n_problems)]
+    work = sum(pr.params.n_particles * pr.params.horizon for pr in probs)
+    qg = torch.tensor(np.stack([pr.q_goal for pr in probs]), dtype=torch.float32, device="cuda")
+    goals = storm.fk(qg)[0].contiguous()
+    b = storm.Batch(probs)
+    x0 = b.x0.clone()
+    cmd = torch.zeros((n_problems, 7), dtype=torch.float32, device="cuda")
+    best, times = b.autotune(goals, x0=x0, reps=tune_reps)
+    graph = b.graph(x0, goals, cmd, iterations=1, shift=True)
+    for _ in range(warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        graph.launch()
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    # closed loop: launch, read the commands back, apply them to the plant
+    cmd_host = torch.empty((n_problems, 7), dtype=torch.float32, pin_memory=True)
+    lat = []
+    for _ in range(latency_steps):
+        t0 = time.perf_counter()
+        graph.launch()
+        cmd_host.copy_(cmd, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        storm.plant_step(x0, cmd, 0.01)
+    lat = np.array(lat)
+    graph.close()
+    b.close()
+
+    # plain form: one captured graph per problem, launched one after another
+    plains = [storm.Rollout(pr) for pr in probs]
+    pg = []
+    x0s = [r.x0.clone() for r in plains]
+    cmds = [torch.zeros(7, dtype=torch.float32, device="cuda") for _ in plains]
+    for k, r in enumerate(plains):
+        pg.append(r.graph(x0s[k], goals[k], cmds[k], iterations=1, shift=True))
+    for _ in range(2):
+        for g in pg:
+            g.launch()
+    torch.cuda.synchronize()
+    psteps = max(5, steps // 10)
+    start.record()
+    for _ in range(psteps):
+        for g in pg:
+            g.launch()
+    end.record()
+    torch.cuda.synchronize()
+    plain_ms = start.elapsed_time(end) / psteps
+    plat = []
+    for _ in range(max(20, latency_steps // 20)):
+        t0 = time.perf_counter()
+        for g in pg:
+            g.launch()
+        torch.cuda.current_stream().synchronize()
+        plat.append((time.perf_counter() - t0) * 1e3)
+    plat = np.array(plat)
+    for g in pg:
+        g.close()
+    for r in plains:
+        r.close()
+    return {
+        "workload": "%d problems, N~U{128..1024}, H~U{20..40}, 10-50 obstacles each, all cost terms" % n_problems,
+        "rollout_steps_per_s": work * 1e3 / ms,
+        "problems_per_s": n_problems * 1e3 / ms,
+        "ms_per_step": ms,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "steps": int(len(lat)), "closed_loop": True},
+        "autotuned": best,
+        "plain_per_problem": {
+            "rollout_steps_per_s": work * 1e3 / plain_ms,
+            "problems_per_s": n_problems * 1e3 / plain_ms,
+            "ms_per_step": plain_ms,
+            "latency_ms": {"p50": float(np.percentile(plat, 50)), "p99": float(np.percentile(plat, 99)),
+                           "steps": int(len(plat))},
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +198,9 @@ def main():
     ap.add_argument("--latency-steps", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--batch-problems", type=int, default=256, help="batched workload size (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-latency-steps", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the MPC step of one problem runs on a single MI355X "
@@ -232,6 +327,9 @@ def main():
             "traffic": None,
         },
     }
+    if args.batch_problems > 0:
+        line["batched"] = batched_bench(args.batch_problems, args.batch_steps, args.batch_latency_steps,
+                                        warmup=5, tune_reps=3)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(inputs.config2(args.seed), args.cpu_budget)
     print(json.dumps(line), flush=True)

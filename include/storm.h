@@ -208,6 +208,77 @@ int32_t storm_rollout_graph_launch(storm_graph graph, void *stream);
 /* Free a captured graph (NULL is a no-op). */
 int32_t storm_rollout_graph_destroy(storm_graph graph);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent problems (not in the paper).  One
+ * persistent rollout launch covers every (problem, tile) work item of all
+ * problems through an integer work queue; one update workgroup per problem
+ * follows.  Each problem keeps its own parameters, scene, policy state and
+ * sampling counter, and computes exactly what a plain context would.
+ * ------------------------------------------------------------------------ */
+typedef struct storm_batch_s *storm_batch;
+
+/* Launch shape of the persistent rollout. */
+typedef struct storm_launch_config {
+    int32_t waves;      /* wavefronts per workgroup: 8 or 16 */
+    int32_t grid;       /* persistent workgroups, >= 1 */
+    int32_t cost_order; /* 1: work queue sorted by estimated tile cost (largest first); 0: problem order */
+} storm_launch_config;
+
+/* Create a batch of n_problems problems (params[p], scenes[p]) sharing one
+ * robot.  Every per-problem limit and validation rule of storm_rollout_init
+ * applies.  Default launch shape: 8 waves, two workgroups per compute unit,
+ * cost-ordered queue.  Synchronises `stream`.  Errors: as init, plus E_RANGE
+ * for n_problems < 1. */
+int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_params *params,
+                         const storm_robot *robot, const storm_scene *scenes, void *stream);
+
+/* Sample + roll out every problem (as storm_rollout_step per problem):
+ * d_x0 [P][3][7], d_goal [P][12].  Allocates nothing.  Errors: E_NULL,
+ * E_DEVICE. */
+int32_t storm_batch_step(storm_batch b, const float *d_x0, const float *d_goal, void *stream);
+
+/* Policy update of every problem (as storm_rollout_update): d_cmd [P][7].
+ * Errors: E_NULL, E_STATE (no step since the last update), E_DEVICE. */
+int32_t storm_batch_update(storm_batch b, float *d_cmd, int32_t shift, void *stream);
+
+/* Capture one control step of every problem (K rounds of batch step +
+ * update, shift after the last) into a HIP graph; launch it with
+ * storm_rollout_graph_launch.  Errors as storm_rollout_graph_create. */
+int32_t storm_batch_graph_create(storm_batch b, const float *d_x0, const float *d_goal, float *d_cmd,
+                                 int32_t iterations, int32_t shift, void *stream, storm_graph *out);
+
+/* Set / read the persistent launch shape (graphs capture the shape current
+ * at their creation).  Errors: E_NULL, E_RANGE (waves not 8/16, grid < 1). */
+int32_t storm_batch_set_config(storm_batch b, const storm_launch_config *cfg);
+int32_t storm_batch_get_config(storm_batch b, storm_launch_config *cfg);
+
+/* Autotuner: time the rollout of this batch for every candidate shape
+ * (waves 8, 16; grid 1-4 workgroups per compute unit; sorted or problem-order
+ * queue), `reps` launches each, with HIP events on `stream`, and keep the
+ * fastest.  Writes the chosen shape to *best (nullable); if h_times is not
+ * NULL it receives the mean time in microseconds of candidate k, k <
+ * *n_candidates (capacity in, count out).  The policies are not updated;
+ * call storm_batch_step again before the next update.  Synchronises. */
+int32_t storm_batch_autotune(storm_batch b, const float *d_x0, const float *d_goal, int32_t reps, void *stream,
+                             storm_launch_config *best, float *h_times, int32_t *n_candidates);
+
+/* Per-problem state and costs (host copies, synchronising; not for the hot
+ * loop), as the storm_rollout_* calls of a plain context. */
+int32_t storm_batch_get_state(storm_batch b, int32_t problem, float *h_mean, float *h_sigma2, uint32_t *h_step,
+                              void *stream);
+int32_t storm_batch_set_state(storm_batch b, int32_t problem, const float *h_mean, const float *h_sigma2,
+                              const uint32_t *h_step, void *stream);
+int32_t storm_batch_costs(storm_batch b, int32_t problem, float *h_C, void *stream);
+
+/* Free a batch (NULL is a no-op). */
+int32_t storm_batch_destroy(storm_batch b);
+
+/* Closed-loop plant used by the benchmarks: applies command d_cmd [n][7] to
+ * states d_x [n][3][7] for `dt` seconds with the integrator of Eq. 7
+ * (v += dt u, q += dt v, a = u).  Errors: E_NULL, E_RANGE (n < 0), E_PARAM
+ * (dt <= 0), E_DEVICE. */
+int32_t storm_plant_step(float *d_x, const float *d_cmd, int32_t n, float dt, void *stream);
+
 /* Batched forward kinematics of the robot (Sec. 3.1, Eq. 8): for n joint
  * configurations d_q [7][n], writes the flange pose d_pose [12][n] (R
  * row-major, then p) and, if d_manip is not NULL, the manipulability

@@ -10,17 +10,6 @@
 
 using namespace storm;
 
-struct storm_ctx_s {
-    int device = 0;
-    int waves = 16;
-    int32_t error = STORM_OK;  // sticky device error
-    bool pending = false;      // a step waits for its update
-    storm_params params{};
-    ProblemDev P{};
-    RobotDev R{};
-    std::vector<void *> allocs;  // every device allocation of this context
-};
-
 namespace {
 
 bool finite_f(float x) { return isfinite(x) != 0; }
@@ -124,7 +113,9 @@ void fill_robot_consts(const storm_robot *robot, RobotDev &R)
 // contiguous range [t0(s), S).  The pairs, taken s-major, are cut into
 // `waves` nearly equal parts, each written as segments (s, t_begin, t_end).
 // Returns the pair count; off[w] .. off[w + 1] are wave w's segments.
-int self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
+}  // namespace
+
+int storm::self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
 {
     const int S = robot->n_spheres;
     std::vector<int> t0(S, S);
@@ -157,6 +148,8 @@ int self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, st
     off[waves] = (int)seg.size() / 4;
     return (int)total;
 }
+
+namespace {
 
 template <typename T>
 hipError_t dalloc(storm_ctx c, T **ptr, size_t count)
@@ -238,7 +231,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
             if (is_sphere) ++n_sph_obs; else ++n_box_obs;
         }
     std::vector<int> seg, seg_off;
-    const int n_pairs = self_segments(robot, c->waves, seg, seg_off);
+    const int n_pairs = storm::self_segments(robot, c->waves, seg, seg_off);
     const int n_seg = (int)seg.size() / 4;
 
     ProblemDev &P = c->P;
@@ -477,12 +470,6 @@ int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float 
     return STORM_OK;
 }
 
-struct storm_graph_s {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    storm_ctx ctx = nullptr;
-};
-
 int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
                                    int32_t iterations, int32_t shift, void *stream, storm_graph *out)
 {
@@ -502,7 +489,7 @@ int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float
         if (own) (void)hipStreamDestroy(own);
         return STORM_E_NOMEM;
     }
-    g->ctx = ctx;
+    g->error = &ctx->error;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     StepOut none{};
     for (int k = 0; e == hipSuccess && k < iterations; ++k) {
@@ -529,9 +516,9 @@ int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float
 int32_t storm_rollout_graph_launch(storm_graph graph, void *stream)
 {
     if (!graph) return STORM_E_NULL;
-    if (graph->ctx->error != STORM_OK) return graph->ctx->error;
+    if (*graph->error != STORM_OK) return *graph->error;
     if (hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)) != hipSuccess) {
-        graph->ctx->error = STORM_E_DEVICE;
+        *graph->error = STORM_E_DEVICE;
         return STORM_E_DEVICE;
     }
     return STORM_OK;

@@ -75,13 +75,13 @@ __device__ __forceinline__ float hinge_box(float x, float lo, float hi)
     return fmaxf(lo - x, 0.0f) + fmaxf(x - hi, 0.0f);
 }
 
+// One 64-lane tile of one problem, executed by the W waves of the calling
+// workgroup; smem is the workgroup's dynamic LDS (rollout_lds_bytes).
 template <int W>
-__global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, RobotDev R,
-                                                             const float *__restrict__ x0,
-                                                             const float *__restrict__ goal,
-                                                             const float *__restrict__ noise, StepOut out)
+__device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev &R, const int tile,
+                                             const float *__restrict__ x0, const float *__restrict__ goal,
+                                             const float *__restrict__ noise, const StepOut &out, float *smem)
 {
-    extern __shared__ float smem[];
     const int S = R.n_spheres;
     float *s_eps = smem;                    // [8][64]
     float *s_q = s_eps + 8 * kLanes;        // [7][64]
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
     const int N = P.N, H = P.H;
     const int pl = lane / H;
     const int h = lane - pl * H;
-    const int i = blockIdx.x * P.ppt + pl;
+    const int i = tile * P.ppt + pl;
     const bool valid = pl < P.ppt && i < N;
     const bool live = valid && i < N - P.n_null;  // sampled (non-null) particle
     const uint32_t mask = P.cost_mask;
@@ -434,6 +434,47 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, Robot
     }
 }
 
+template <int W>
+__global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, RobotDev R,
+                                                             const float *__restrict__ x0,
+                                                             const float *__restrict__ goal,
+                                                             const float *__restrict__ noise, StepOut out)
+{
+    extern __shared__ float smem[];
+    rollout_tile<W>(P, R, blockIdx.x, x0, goal, noise, out, smem);
+}
+
+// Persistent form for many problems: each workgroup takes (problem, tile)
+// items from an integer work queue, in the order of `items` (the scheduler
+// puts the most expensive tiles first), until the queue is empty.  Every
+// workgroup draws exactly one index past the end; the one that draws the
+// last of those resets the counter for the next launch.
+template <int W>
+__global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const ProblemDev *__restrict__ probs,
+                                                                   const int2 *__restrict__ items, int n_items,
+                                                                   uint32_t *next, RobotDev R,
+                                                                   const float *__restrict__ x0s,
+                                                                   const float *__restrict__ goals)
+{
+    extern __shared__ float smem[];
+    __shared__ int s_item;
+    const STORM_CONST_AS int32_t *it = uniform_ptr(reinterpret_cast<const int32_t *>(items));
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(next, 1u);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= n_items) {
+            if (threadIdx.x == 0 && item == n_items + (int)gridDim.x - 1) atomicExch(next, 0u);
+            return;
+        }
+        const int p = it[2 * item], tile = it[2 * item + 1];
+        const ProblemDev P = load_uniform(probs + p);
+        rollout_tile<W>(P, R, tile, x0s + (size_t)p * 3 * kDof, goals + (size_t)p * 12, nullptr, StepOut{}, smem);
+        __syncthreads();
+    }
+}
+
 size_t rollout_lds_bytes(int S, int W)
 {
     return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms) * kLanes * sizeof(float);
@@ -445,11 +486,33 @@ hipError_t set_rollout_lds_limit()
 {
     const int bytes16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16);
     const int bytes8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rollout_kernel<16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes16);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&rollout_kernel<8>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes8);
+    const void *fns[4] = {reinterpret_cast<const void *>(&rollout_kernel<16>),
+                          reinterpret_cast<const void *>(&rollout_kernel<8>),
+                          reinterpret_cast<const void *>(&rollout_batch_kernel<16>),
+                          reinterpret_cast<const void *>(&rollout_batch_kernel<8>)};
+    const int bytes[4] = {bytes16, bytes8, bytes16, bytes8};
+    for (int k = 0; k < 4; ++k) {
+        const hipError_t e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[k]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int n_items, uint32_t *next,
+                                const RobotDev &R, const float *x0s, const float *goals, int waves, int grid,
+                                hipStream_t stream)
+{
+    const size_t lds = rollout_lds_bytes(R.n_spheres, waves);
+    if (waves == 16) {
+        hipLaunchKernelGGL(rollout_batch_kernel<16>, dim3((unsigned)grid), dim3(16 * kLanes), lds, stream, probs,
+                           items, n_items, next, R, x0s, goals);
+    } else if (waves == 8) {
+        hipLaunchKernelGGL(rollout_batch_kernel<8>, dim3((unsigned)grid), dim3(8 * kLanes), lds, stream, probs,
+                           items, n_items, next, R, x0s, goals);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "storm.h"
 
 namespace storm {
@@ -68,6 +70,19 @@ __device__ __forceinline__ const STORM_CONST_AS T *uniform_ptr(const T *p)
     return (const STORM_CONST_AS T *)(p);
 }
 
+// Copy a struct from device memory through wave-uniform scalar loads.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "struct of 32-bit words");
+    T v;
+    const STORM_CONST_AS uint32_t *src = uniform_ptr(reinterpret_cast<const uint32_t *>(p));
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return v;
+}
+
 // Hardware square root (v_sqrt_f32, 1 ulp) for norms and distances.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
@@ -89,6 +104,36 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
 hipError_t set_rollout_lds_limit();
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream);
+// Many problems: persistent rollout over a (problem, tile) work queue, and one
+// update workgroup per problem (descriptors in device memory).
+hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int n_items, uint32_t *next,
+                                const RobotDev &R, const float *x0s, const float *goals, int waves, int grid,
+                                hipStream_t stream);
+hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *cmd, int shift, hipStream_t stream);
 hipError_t launch_fk(const RobotDev &R, const float *q, int n, float *pose, float *manip, hipStream_t stream);
 
+// Self-collision work split of the robot's sphere pairs over `waves`
+// wavefronts: segments (s, t_begin, t_end, 0) and per-wave offsets
+// off[0..waves]; returns the pair count.
+int self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off);
+
 }  // namespace storm
+
+// One plain-form problem (the storm_ctx handle of the C ABI).
+struct storm_ctx_s {
+    int device = 0;
+    int waves = 16;
+    int32_t error = STORM_OK;  // sticky device error
+    bool pending = false;      // a step waits for its update
+    storm_params params{};
+    storm::ProblemDev P{};
+    storm::RobotDev R{};
+    std::vector<void *> allocs;  // every device allocation of this context
+};
+
+// An instantiated graph of one control step (plain or batched).
+struct storm_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t *error = nullptr;  // sticky error word of the owning context or batch
+};

@@ -43,9 +43,8 @@ __device__ __forceinline__ float wave_min(float x)
 // and 32-63, each a contiguous run of H floats of u[j][i][.]), otherwise one.
 // Work items are (joint j, group range); the 16 waves take them in order and
 // each lane keeps its own sums, merged at the end in a fixed order.
-__global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *__restrict__ mean_out,
-                                                          float *__restrict__ sigma2_out, float *__restrict__ cmd,
-                                                          int shift)
+__device__ __forceinline__ void update_problem(const ProblemDev &P, float *__restrict__ mean_out,
+                                               float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift)
 {
     __shared__ float s_w[kWChunk];
     __shared__ float s_part[2][kWaves][kLanes];
@@ -173,7 +172,29 @@ __global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *_
     }
 }
 
+__global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *__restrict__ mean_out,
+                                                          float *__restrict__ sigma2_out, float *__restrict__ cmd,
+                                                          int shift)
+{
+    update_problem(P, mean_out, sigma2_out, cmd, shift);
+}
+
+// One workgroup per problem of a batch; commands go to cmd[p][7].
+__global__ __launch_bounds__(kThreads) void update_batch_kernel(const ProblemDev *__restrict__ probs,
+                                                                float *__restrict__ cmd, int shift)
+{
+    const ProblemDev P = load_uniform(probs + blockIdx.x);
+    update_problem(P, nullptr, nullptr, cmd + (size_t)blockIdx.x * kDof, shift);
+}
+
 }  // namespace
+
+hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *cmd, int shift, hipStream_t stream)
+{
+    hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)n_problems), dim3(kThreads), 0, stream, probs, cmd,
+                       shift);
+    return hipGetLastError();
+}
 
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream)

@@ -80,7 +80,14 @@ EXPORTS = (
     "storm_rollout_init", "storm_rollout_step", "storm_rollout_update", "storm_rollout_destroy",
     "storm_rollout_status", "storm_rollout_get_state", "storm_rollout_set_state", "storm_fk",
     "storm_status_str", "storm_rollout_graph_create", "storm_rollout_graph_launch", "storm_rollout_graph_destroy",
+    "storm_batch_init", "storm_batch_step", "storm_batch_update", "storm_batch_graph_create",
+    "storm_batch_set_config", "storm_batch_get_config", "storm_batch_autotune", "storm_batch_get_state",
+    "storm_batch_set_state", "storm_batch_costs", "storm_batch_destroy", "storm_plant_step",
 )
+
+
+class storm_launch_config(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("grid", ctypes.c_int32), ("cost_order", ctypes.c_int32)]
 
 
 def lib():
@@ -106,6 +113,20 @@ def lib():
         L.storm_rollout_graph_create.argtypes = [vp, vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
         L.storm_rollout_graph_launch.argtypes = [vp, vp]
         L.storm_rollout_graph_destroy.argtypes = [vp]
+        L.storm_batch_init.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(storm_params),
+                                       ctypes.POINTER(storm_robot), ctypes.POINTER(storm_scene), vp]
+        L.storm_batch_step.argtypes = [vp, vp, vp, vp]
+        L.storm_batch_update.argtypes = [vp, vp, i32, vp]
+        L.storm_batch_graph_create.argtypes = [vp, vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+        L.storm_batch_set_config.argtypes = [vp, ctypes.POINTER(storm_launch_config)]
+        L.storm_batch_get_config.argtypes = [vp, ctypes.POINTER(storm_launch_config)]
+        L.storm_batch_autotune.argtypes = [vp, vp, vp, i32, vp, ctypes.POINTER(storm_launch_config), vp,
+                                           ctypes.POINTER(i32)]
+        L.storm_batch_get_state.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.storm_batch_set_state.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.storm_batch_costs.argtypes = [vp, i32, vp, vp]
+        L.storm_batch_destroy.argtypes = [vp]
+        L.storm_plant_step.argtypes = [vp, vp, i32, ctypes.c_float, vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_char_p if name == "storm_status_str" else i32
         _lib = L
@@ -272,15 +293,16 @@ class Rollout:
 class StepGraph:
     """A captured control step; launch() enqueues it on the current stream."""
 
-    def __init__(self, rollout, x0, goal, cmd, iterations, shift):
-        self.rollout = rollout
+    def __init__(self, owner, x0, goal, cmd, iterations, shift, create=None):
+        self.owner = owner
         self._keep = (x0, goal, cmd)
+        create = lib().storm_rollout_graph_create if create is None else create
         h = ctypes.c_void_p()
         stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(stream):
-            _check(lib().storm_rollout_graph_create(rollout._h, _ptr(x0), _ptr(goal), _ptr(cmd), int(iterations),
-                                                    int(bool(shift)), _stream(), ctypes.byref(h)),
-                   "storm_rollout_graph_create")
+            _check(create(owner._h, _ptr(x0), _ptr(goal), _ptr(cmd), int(iterations), int(bool(shift)), _stream(),
+                          ctypes.byref(h)), "graph_create")
         torch.cuda.current_stream().wait_stream(stream)
         self._h = h
         self._launch = lib().storm_rollout_graph_launch
@@ -301,6 +323,96 @@ class StepGraph:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many independent problems sharing one robot (batched form)."""
+
+    def __init__(self, problems, device=None):
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.problems = list(problems)
+        P = len(self.problems)
+        self.P = P
+        params = (storm_params * P)()
+        scenes = (storm_scene * P)()
+        self._keep = []
+        for k, pr in enumerate(self.problems):
+            sp, dt = make_params(pr.params)
+            sc, obs = make_scene(pr.obstacles)
+            params[k] = sp
+            scenes[k] = sc
+            self._keep += [dt, obs]
+        rb, sph = make_robot(self.problems[0].spheres)
+        self._keep += [rb, sph]
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().storm_batch_init(ctypes.byref(h), P, params, ctypes.byref(rb), scenes, _stream()),
+                   "storm_batch_init")
+        self._h = h
+        self.x0 = torch.tensor(np.stack([np.concatenate([pr.q0, pr.v0, pr.a0]) for pr in self.problems]),
+                               dtype=torch.float32, device=self.device).contiguous()
+        self.cmd = torch.zeros((P, DOF), dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().storm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, goals, x0=None):
+        x0 = self.x0 if x0 is None else x0
+        _check(lib().storm_batch_step(self._h, _ptr(x0), _ptr(goals), _stream()), "storm_batch_step")
+
+    def update(self, cmd=None, shift=True):
+        cmd = self.cmd if cmd is None else cmd
+        _check(lib().storm_batch_update(self._h, _ptr(cmd), int(bool(shift)), _stream()), "storm_batch_update")
+        return cmd
+
+    def graph(self, x0, goals, cmd, iterations=1, shift=True):
+        return StepGraph(self, x0, goals, cmd, iterations, shift, create=lib().storm_batch_graph_create)
+
+    def config(self):
+        c = storm_launch_config()
+        _check(lib().storm_batch_get_config(self._h, ctypes.byref(c)), "storm_batch_get_config")
+        return {"waves": c.waves, "grid": c.grid, "cost_order": c.cost_order}
+
+    def set_config(self, waves, grid, cost_order=1):
+        c = storm_launch_config(int(waves), int(grid), int(cost_order))
+        _check(lib().storm_batch_set_config(self._h, ctypes.byref(c)), "storm_batch_set_config")
+
+    def autotune(self, goals, x0=None, reps=5):
+        x0 = self.x0 if x0 is None else x0
+        best = storm_launch_config()
+        times = np.zeros(64, dtype=np.float32)
+        n = ctypes.c_int32(64)
+        _check(lib().storm_batch_autotune(self._h, _ptr(x0), _ptr(goals), int(reps), _stream(), ctypes.byref(best),
+                                          times.ctypes.data, ctypes.byref(n)), "storm_batch_autotune")
+        return {"waves": best.waves, "grid": best.grid, "cost_order": best.cost_order}, times[: n.value].copy()
+
+    def get_state(self, p):
+        pr = self.problems[p].params
+        mean = np.zeros((pr.horizon, DOF), dtype=np.float32)
+        sigma2 = np.zeros(DOF, dtype=np.float32)
+        step = ctypes.c_uint32()
+        _check(lib().storm_batch_get_state(self._h, int(p), mean.ctypes.data, sigma2.ctypes.data,
+                                           ctypes.addressof(step), _stream()), "storm_batch_get_state")
+        return mean, sigma2, step.value
+
+    def costs(self, p):
+        C = np.zeros(self.problems[p].params.n_particles, dtype=np.float32)
+        _check(lib().storm_batch_costs(self._h, int(p), C.ctypes.data, _stream()), "storm_batch_costs")
+        return C
+
+
+def plant_step(x, cmd, dt):
+    """Apply commands cmd [n][7] to states x [n][3][7] for dt seconds (Eq. 7)."""
+    n = cmd.shape[0] if cmd.dim() == 2 else 1
+    _check(lib().storm_plant_step(_ptr(x), _ptr(cmd), int(n), float(dt), _stream()), "storm_plant_step")
 
 
 def fk(q, spheres=None):

@@ -137,3 +137,25 @@ def test_call_validation_before_device(storm):
     assert L.storm_fk(None, None, 1, None, None, None) == E.STORM_E_NULL
     assert L.storm_fk(ctypes.byref(rb), None, -1, None, None, None) == E.STORM_E_RANGE
     assert L.storm_fk(ctypes.byref(rb), None, 5, None, None, None) == E.STORM_E_NULL
+
+
+def test_batch_and_plant_validation(storm):
+    L = storm.lib()
+    E = storm
+    h = ctypes.c_void_p()
+    sp, rb, sc, keep = _args(storm)
+    assert L.storm_batch_init(None, 1, ctypes.byref(sp), ctypes.byref(rb), None, None) == E.STORM_E_NULL
+    assert L.storm_batch_init(ctypes.byref(h), 0, ctypes.byref(sp), ctypes.byref(rb), None, None) == E.STORM_E_RANGE
+    sp.beta = -1.0
+    assert L.storm_batch_init(ctypes.byref(h), 1, ctypes.byref(sp), ctypes.byref(rb), None, None) == E.STORM_E_PARAM
+    assert L.storm_batch_step(None, None, None, None) == E.STORM_E_NULL
+    assert L.storm_batch_update(None, None, 1, None) == E.STORM_E_NULL
+    assert L.storm_batch_destroy(None) == E.STORM_OK
+    cfg = storm.storm_launch_config(8, 1, 1)
+    assert L.storm_batch_set_config(None, ctypes.byref(cfg)) == E.STORM_E_NULL
+    assert L.storm_plant_step(None, None, -1, ctypes.c_float(0.01), None) == E.STORM_E_RANGE
+    assert L.storm_plant_step(None, None, 3, ctypes.c_float(0.01), None) == E.STORM_E_NULL
+    assert L.storm_plant_step(None, None, 0, ctypes.c_float(0.0), None) == E.STORM_E_PARAM
+    assert L.storm_rollout_graph_create(None, None, None, None, 1, 1, None, ctypes.byref(h)) == E.STORM_E_NULL
+    assert L.storm_rollout_graph_launch(None, None) == E.STORM_E_NULL
+    assert L.storm_rollout_graph_destroy(None) == E.STORM_OK
