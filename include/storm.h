@@ -186,6 +186,30 @@ int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, u
 int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float *h_sigma2, const uint32_t *h_step,
                                 void *stream);
 
+/* Gradient of the expected horizon cost (the differentiable form; not in
+ * the paper): J(mu) = (1/N) sum_i C_i(mu + sigma * eps_i) with the standard
+ * noise eps of the last storm_rollout_step held fixed (or d_noise [7][N][H]
+ * if not NULL), sigma the current per-joint standard deviation, and C_i the
+ * horizon cost (Eq. 2) of the pose (Eq. 9), joint / velocity limit (Eq. 11)
+ * and stop (Eq. 10) terms.  Null particles add to J but not to the
+ * gradient.  Reverse mode through the costs, the kinematics (Eq. 8) and the
+ * integrator (Eq. 7), states recomputed.  d_mean [H][7] in, d_grad [H][7]
+ * and d_J [1] out (each nullable).  Errors: E_NULL (x0, goal, mean),
+ * E_UNSUPPORTED (cost mask with manipulability or collision terms),
+ * E_DEVICE. */
+int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_mean,
+                           const float *d_noise, float *d_grad, float *d_J, void *stream);
+
+/* Gradient refinement of the stored mean (the differentiable form):
+ * `iterations` Adam steps (Kingma and Ba 2015: beta1 0.9, beta2 0.999,
+ * eps 1e-8, moments restarted at each call) of learning rate lr on J above,
+ * then d_cmd [7] = refined mu_0 and, if shift != 0, the warm-start shift.
+ * Meant to follow storm_rollout_update(..., shift = 0).  Allocates nothing.
+ * Errors: E_NULL, E_RANGE (iterations < 0), E_PARAM (lr not finite or < 0),
+ * E_UNSUPPORTED, E_DEVICE. */
+int32_t storm_rollout_refine(storm_ctx ctx, const float *d_x0, const float *d_goal, int32_t iterations, float lr,
+                             float *d_cmd, int32_t shift, void *stream);
+
 /* Opaque handle of an instantiated HIP graph of one control step. */
 typedef struct storm_graph_s *storm_graph;
 
@@ -200,6 +224,12 @@ typedef struct storm_graph_s *storm_graph;
  * E_DEVICE. */
 int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
                                    int32_t iterations, int32_t shift, void *stream, storm_graph *out);
+
+/* As storm_rollout_graph_create, followed by `refine_iters` Adam steps of
+ * storm_rollout_refine (learning rate lr) before the command and shift. */
+int32_t storm_rollout_graph_create_refine(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                                          int32_t iterations, int32_t shift, int32_t refine_iters, float lr,
+                                          void *stream, storm_graph *out);
 
 /* Enqueue one captured control step on `stream`.  Allocates nothing.
  * Errors: E_NULL, E_DEVICE. */

@@ -266,7 +266,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     c->R.n_pairs = n_pairs;
 
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
-    float *self_rr2;
+    float *self_rr2, *grad_part, *cost_part, *grad, *adam;
     float4 *sph_obs, *env_sph, *sph_local;
     int32_t *sph_body, *self_off;
     int4 *self_seg;
@@ -289,6 +289,10 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &u, (size_t)STORM_DOF * N * H));
     STORM_TRY(dalloc(c, &C, (size_t)N));
     STORM_TRY(dalloc(c, &counters, (size_t)4));
+    STORM_TRY(dalloc(c, &grad_part, (size_t)P.n_tiles * STORM_DOF * storm::kMaxH));
+    STORM_TRY(dalloc(c, &cost_part, (size_t)P.n_tiles));
+    STORM_TRY(dalloc(c, &grad, (size_t)H * STORM_DOF));
+    STORM_TRY(dalloc(c, &adam, (size_t)2 * H * STORM_DOF));
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &self_rr2, (size_t)robot->n_spheres * robot->n_spheres));
@@ -330,6 +334,12 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         P.C = C;
         P.step = counters;
         P.status = counters + 1;
+        P.last_step = counters + 2;
+        P.grad_part = grad_part;
+        P.cost_part = cost_part;
+        P.grad = grad;
+        P.adam_m = adam;
+        P.adam_v = adam + (size_t)H * STORM_DOF;
         c->R.sph_local = sph_local;
         c->R.sph_body = sph_body;
         c->R.self_rr2 = self_rr2;
@@ -470,13 +480,30 @@ int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float 
     return STORM_OK;
 }
 
-int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
-                                   int32_t iterations, int32_t shift, void *stream, storm_graph *out)
+namespace {
+constexpr uint32_t kDiffMask = STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP;
+
+hipError_t enqueue_refine(storm_ctx ctx, const float *d_x0, const float *d_goal, int iterations, float lr,
+                          float *d_cmd, int shift, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int it = 1; e == hipSuccess && it <= iterations; ++it) {
+        e = storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, ctx->P.mean, nullptr, nullptr, nullptr, s);
+        if (e == hipSuccess) e = storm::launch_adam(ctx->P, it, lr, s);
+    }
+    if (e == hipSuccess) e = storm::launch_command(ctx->P, d_cmd, shift, s);
+    return e;
+}
+
+int32_t create_graph(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd, int32_t iterations,
+                     int32_t shift, int32_t refine_iters, float lr, void *stream, storm_graph *out)
 {
     if (!out) return STORM_E_NULL;
     *out = nullptr;
     if (!ctx || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
-    if (iterations < 1) return STORM_E_RANGE;
+    if (iterations < 1 || refine_iters < 0) return STORM_E_RANGE;
+    if (refine_iters > 0 && (!(lr >= 0.0f) || !isfinite(lr))) return STORM_E_PARAM;
+    if (refine_iters > 0 && (ctx->P.cost_mask & ~kDiffMask)) return STORM_E_UNSUPPORTED;
     if (ctx->error != STORM_OK) return ctx->error;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipStream_t own = nullptr;
@@ -493,10 +520,12 @@ int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     StepOut none{};
     for (int k = 0; e == hipSuccess && k < iterations; ++k) {
+        const bool last = k == iterations - 1;
         e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, nullptr, none, ctx->waves, s);
         if (e == hipSuccess)
-            e = storm::launch_update(ctx->P, nullptr, nullptr, d_cmd, (k == iterations - 1) && shift != 0, s);
+            e = storm::launch_update(ctx->P, nullptr, nullptr, d_cmd, last && shift != 0 && refine_iters == 0, s);
     }
+    if (e == hipSuccess && refine_iters > 0) e = enqueue_refine(ctx, d_x0, d_goal, refine_iters, lr, d_cmd, shift, s);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (e == hipSuccess) e = e2;
@@ -510,6 +539,50 @@ int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float
         return STORM_E_DEVICE;
     }
     *out = g;
+    return STORM_OK;
+}
+}  // namespace
+
+int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                                   int32_t iterations, int32_t shift, void *stream, storm_graph *out)
+{
+    return create_graph(ctx, d_x0, d_goal, d_cmd, iterations, shift, 0, 0.0f, stream, out);
+}
+
+int32_t storm_rollout_graph_create_refine(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                                          int32_t iterations, int32_t shift, int32_t refine_iters, float lr,
+                                          void *stream, storm_graph *out)
+{
+    return create_graph(ctx, d_x0, d_goal, d_cmd, iterations, shift, refine_iters, lr, stream, out);
+}
+
+int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_mean,
+                           const float *d_noise, float *d_grad, float *d_J, void *stream)
+{
+    if (!ctx || !d_x0 || !d_goal || !d_mean) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    if (ctx->P.cost_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
+    if (storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, d_mean, d_noise, d_grad, d_J,
+                           static_cast<hipStream_t>(stream)) != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    return STORM_OK;
+}
+
+int32_t storm_rollout_refine(storm_ctx ctx, const float *d_x0, const float *d_goal, int32_t iterations, float lr,
+                             float *d_cmd, int32_t shift, void *stream)
+{
+    if (!ctx || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
+    if (iterations < 0) return STORM_E_RANGE;
+    if (!(lr >= 0.0f) || !isfinite(lr)) return STORM_E_PARAM;
+    if (ctx->error != STORM_OK) return ctx->error;
+    if (ctx->P.cost_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
+    if (enqueue_refine(ctx, d_x0, d_goal, iterations, lr, d_cmd, shift != 0, static_cast<hipStream_t>(stream)) !=
+        hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
     return STORM_OK;
 }
 

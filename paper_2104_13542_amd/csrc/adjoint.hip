@@ -1,0 +1,335 @@
+// Kernel A: reverse-mode gradient of the expected horizon cost
+//   J(mu) = (1/N) sum_i C_i(mu + sigma * eps_i),  eps held fixed,
+// with respect to the mean control sequence mu [H][7] (not in the paper: the
+// differentiable form).  Differentiated terms: pose (Eq. 9), joint and
+// velocity limits (Eq. 11 form) and stop (Eq. 10); hinge and norm kinks take
+// subgradient 0.  States are recomputed from mu and the noise, never stored.
+//
+// Per 64-lane tile (ppt particles x H steps), eight wavefronts:
+//   A   noise, controls and the forward integrator (as kernel R)
+//   B   wave 0: forward kinematics to LDS; wave 1: limit costs and their
+//       gradients with respect to q and v
+//   C   wave 0: pose cost and dC/dq through the Jacobian columns,
+//       dp/dq_k = z_k x (p - o_k) and dR/dq_k = [z_k]x R; horizon cost
+//   D   waves 0-6: the integrator backwards, two segmented suffix sums:
+//       dC/dv_k = gv_k + dt_k sum_{h>=k} gq_h,  dC/du_m = dt_m sum_{k>=m} dC/dv_k
+//   E   per (joint, step) sum over the tile's particles -> partial gradient
+// A second kernel adds the tile partials in a fixed order; a third takes an
+// Adam step (Kingma and Ba, 2015) on mu.
+#include "kinematics.h"
+#include "sampling.h"
+
+namespace storm {
+namespace {
+
+constexpr int kAdjWaves = 8;
+constexpr int kRedThreads = 1024;
+
+__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P, RobotDev R,
+                                                                    const float *__restrict__ x0,
+                                                                    const float *__restrict__ goal,
+                                                                    const float *__restrict__ mean,
+                                                                    const float *__restrict__ noise)
+{
+    __shared__ float s_eps[8][kLanes];
+    __shared__ float s_q[kDof][kLanes];
+    __shared__ float s_v[kDof][kLanes];
+    __shared__ float s_fr[kFrames * 12][kLanes];
+    __shared__ float s_gl[kDof][kLanes];  // limit-cost gradient d c / d q
+    __shared__ float s_gv[kDof][kLanes];  // limit and stop gradient d c / d v
+    __shared__ float s_gq[kDof][kLanes];  // horizon-weighted d C / d q
+    __shared__ float s_gu[kDof][kLanes];  // d C / d u
+    __shared__ float s_cl[kLanes];        // weighted limit and stop costs
+    __shared__ float s_Cp[kLanes];        // horizon cost per particle of the tile
+
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x;
+    const int N = P.N, H = P.H;
+    const int pl = lane / H;
+    const int h = lane - pl * H;
+    const int i = tile * P.ppt + pl;
+    const bool valid = pl < P.ppt && i < N;
+    const bool live = valid && i < N - P.n_null;
+    const uint32_t mask = P.cost_mask;
+    const float *__restrict__ tab = P.tables;
+    const float dt_h = tab[kTabDt + h];
+    const float hw_h = tab[kTabHw + h];
+
+    // ---- A: noise, controls, integrator ---------------------------------------
+    if (wave < 2) {
+        float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (live) standard_noise4(P, noise, wave, i, h, *P.last_step, e);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) s_eps[4 * wave + m][lane] = e[m];
+    }
+    __syncthreads();
+    if (wave < kDof) {
+        const int j = wave;
+        float u = 0.0f;
+        if (live) u = fmaf(sqrtf(P.sigma2[j]), s_eps[j][lane], mean[h * kDof + j]);
+        const float v = x0[kDof + j] + segmented_scan(dt_h * u, h, H);
+        const float q = x0[j] + segmented_scan(dt_h * v, h, H);
+        s_q[j][lane] = q;
+        s_v[j][lane] = v;
+    }
+    __syncthreads();
+
+    // ---- B: kinematics | limit costs and their gradients -------------------
+    if (wave == 0) {
+        float r[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+        float p[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int f = 0; f < kFrames; ++f) {
+            float st = 0.0f, ct = 1.0f;
+            if (f < kDof) sincosf(s_q[f][lane], &st, &ct);
+            dh_step(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) s_fr[f * 12 + c][lane] = r[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_fr[f * 12 + 9 + c][lane] = p[c];
+        }
+    } else if (wave == 1) {
+        float ej[kDof], ev[kDof], es[kDof];
+        float nj = 0.0f, nv = 0.0f, ns = 0.0f;
+        const float vs = tab[kTabVstop + h];
+#pragma unroll
+        for (int j = 0; j < kDof; ++j) {
+            const float q = s_q[j][lane], v = s_v[j][lane];
+            // signed violations: negative below the band, positive above
+            ej[j] = fminf(q - tab[kTabJlo + j], 0.0f) + fmaxf(q - tab[kTabJhi + j], 0.0f);
+            ev[j] = fminf(v - tab[kTabVlo + j], 0.0f) + fmaxf(v - tab[kTabVhi + j], 0.0f);
+            es[j] = fmaxf(fabsf(v) - vs, 0.0f);
+            nj = fmaf(ej[j], ej[j], nj);
+            nv = fmaf(ev[j], ev[j], nv);
+            ns = fmaf(es[j], es[j], ns);
+        }
+        nj = (mask & STORM_COST_JOINT) ? fast_sqrt(nj) : 0.0f;
+        nv = (mask & STORM_COST_VEL) ? fast_sqrt(nv) : 0.0f;
+        ns = (mask & STORM_COST_STOP) ? fast_sqrt(ns) : 0.0f;
+        const float kj = nj > 0.0f ? P.a_joint / nj : 0.0f;
+        const float kv = nv > 0.0f ? P.a_vel / nv : 0.0f;
+        const float ks = ns > 0.0f ? P.a_stop / ns : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kDof; ++j) {
+            const float v = s_v[j][lane];
+            s_gl[j][lane] = kj * ej[j];
+            s_gv[j][lane] = fmaf(kv, ev[j], ks * es[j] * (v > 0.0f ? 1.0f : -1.0f));
+        }
+        s_cl[lane] = fmaf(P.a_joint, nj, fmaf(P.a_vel, nv, P.a_stop * ns));
+    }
+    __syncthreads();
+
+    // ---- C: pose cost and its gradient; horizon cost ------------------------
+    if (wave == 0) {
+        float gq[kDof];
+#pragma unroll
+        for (int k = 0; k < kDof; ++k) gq[k] = s_gl[k][lane];
+        float cost = s_cl[lane];
+        if (mask & STORM_COST_POSE) {
+            float Re[9], pe[3];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) Re[c] = s_fr[7 * 12 + c][lane];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pe[c] = s_fr[7 * 12 + 9 + c][lane];
+            // position: e = diag(a2) R_g^T (p - p_g), gradient g_p = w_pos R_g diag(a2) e / |e|
+            float e[3], pos2 = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                e[r] = P.alpha_pos[r] * fmaf(goal[0 * 3 + r], pe[0] - goal[9],
+                                             fmaf(goal[1 * 3 + r], pe[1] - goal[10], goal[2 * 3 + r] * (pe[2] - goal[11])));
+                pos2 = fmaf(e[r], e[r], pos2);
+            }
+            const float pos = fast_sqrt(pos2);
+            const float kp = pos > 0.0f ? P.w_pos / pos : 0.0f;
+            float gp[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                gp[a] = kp * fmaf(goal[a * 3 + 0], P.alpha_pos[0] * e[0],
+                                  fmaf(goal[a * 3 + 1], P.alpha_pos[1] * e[1], goal[a * 3 + 2] * P.alpha_pos[2] * e[2]));
+            // rotation: M = diag(a1)(I - R_g^T R), gradient G = -w_rot R_g diag(a1) M / |M|_F
+            float M[9], rot2 = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float m = fmaf(goal[0 * 3 + r], Re[0 * 3 + c],
+                                         fmaf(goal[1 * 3 + r], Re[1 * 3 + c], goal[2 * 3 + r] * Re[2 * 3 + c]));
+                    M[r * 3 + c] = P.alpha_rot[r] * ((r == c ? 1.0f : 0.0f) - m);
+                    rot2 = fmaf(M[r * 3 + c], M[r * 3 + c], rot2);
+                }
+            const float rot = fast_sqrt(rot2);
+            const float kr = rot > 0.0f ? -P.w_rot / rot : 0.0f;
+            float G[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    G[a * 3 + c] = kr * fmaf(goal[a * 3 + 0], P.alpha_rot[0] * M[0 * 3 + c],
+                                             fmaf(goal[a * 3 + 1], P.alpha_rot[1] * M[1 * 3 + c],
+                                                  goal[a * 3 + 2] * P.alpha_rot[2] * M[2 * 3 + c]));
+            // <G, [z]x R> = z . w with A = R G^T, w = (A12 - A21, A20 - A02, A01 - A10)
+            float A[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    A[a * 3 + b] = fmaf(Re[a * 3 + 0], G[b * 3 + 0], fmaf(Re[a * 3 + 1], G[b * 3 + 1], Re[a * 3 + 2] * G[b * 3 + 2]));
+            const float w0 = A[1 * 3 + 2] - A[2 * 3 + 1];
+            const float w1 = A[2 * 3 + 0] - A[0 * 3 + 2];
+            const float w2 = A[0 * 3 + 1] - A[1 * 3 + 0];
+#pragma unroll
+            for (int k = 0; k < kDof; ++k) {
+                const float z0 = s_fr[k * 12 + 2][lane], z1 = s_fr[k * 12 + 5][lane], z2 = s_fr[k * 12 + 8][lane];
+                const float r0 = pe[0] - s_fr[k * 12 + 9][lane];
+                const float r1 = pe[1] - s_fr[k * 12 + 10][lane];
+                const float r2 = pe[2] - s_fr[k * 12 + 11][lane];
+                // (p - o_k) x g_p
+                const float c0 = r1 * gp[2] - r2 * gp[1];
+                const float c1 = r2 * gp[0] - r0 * gp[2];
+                const float c2 = r0 * gp[1] - r1 * gp[0];
+                gq[k] += fmaf(z0, c0 + w0, fmaf(z1, c1 + w1, z2 * (c2 + w2)));
+            }
+            cost = fmaf(P.w_pos, pos, fmaf(P.w_rot, rot, cost));
+        }
+#pragma unroll
+        for (int k = 0; k < kDof; ++k) s_gq[k][lane] = hw_h * gq[k];
+        const float Ci = segmented_scan(hw_h * cost, h, H);
+        if (h == H - 1) s_Cp[pl] = valid ? Ci : 0.0f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float sum = 0.0f;
+        for (int p = 0; p < P.ppt; ++p) sum += s_Cp[p];
+        P.cost_part[tile] = sum;
+    }
+
+    // ---- D: the integrator backwards -----------------------------------------
+    if (wave < kDof) {
+        const int j = wave;
+        const float Gv = fmaf(dt_h, segmented_suffix_scan(s_gq[j][lane], h, H), hw_h * s_gv[j][lane]);
+        const float gu = dt_h * segmented_suffix_scan(Gv, h, H);
+        s_gu[j][lane] = live ? gu : 0.0f;
+    }
+    __syncthreads();
+
+    // ---- E: tile partial of dJ/dmu (sum over the tile's particles) -----------
+    for (int idx = threadIdx.x; idx < kDof * H; idx += kAdjWaves * kLanes) {
+        const int j = idx / H, hh = idx - j * H;
+        float sum = 0.0f;
+        for (int p = 0; p < P.ppt; ++p) sum += s_gu[j][p * H + hh];
+        P.grad_part[((size_t)tile * kDof + j) * kMaxH + hh] = sum;
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kLanes);
+    return x;
+}
+
+// grad[h][j] = (1/N) sum over tiles of the partials, J = (1/N) sum of the
+// tile cost sums; rows of threads take tiles r, r + R, ..., then the rows
+// are added in order.
+__global__ __launch_bounds__(kRedThreads) void grad_reduce_kernel(ProblemDev P, float *__restrict__ grad_out,
+                                                                  float *__restrict__ J_out)
+{
+    __shared__ float s_red[kRedThreads];
+    __shared__ float s_wave[kRedThreads / kLanes];
+    const int t = threadIdx.x;
+    const int H = P.H, T = P.n_tiles;
+    const int ncol = kDof * H;
+    const int rows = kRedThreads / ncol;
+    const int r = t / ncol, col = t - r * ncol;
+    const int j = col / H, h = col - j * H;
+    float acc = 0.0f;
+    if (r < rows) {
+        int k = r;
+        for (; k + 3 * rows < T; k += 4 * rows) {
+            float v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[m] = P.grad_part[((size_t)(k + m * rows) * kDof + j) * kMaxH + h];
+            acc += (v[0] + v[1]) + (v[2] + v[3]);
+        }
+        for (; k < T; k += rows) acc += P.grad_part[((size_t)k * kDof + j) * kMaxH + h];
+    }
+    s_red[t] = acc;
+    float cs = 0.0f;
+    for (int k = t; k < T; k += kRedThreads) cs += P.cost_part[k];
+    cs = wave_sum(cs);
+    if ((t & (kLanes - 1)) == 0) s_wave[t / kLanes] = cs;
+    __syncthreads();
+    const float invN = 1.0f / (float)P.N;
+    if (t < ncol) {
+        float s = 0.0f;
+        for (int k = 0; k < rows; ++k) s += s_red[k * ncol + t];
+        const float g = s * invN;
+        P.grad[h * kDof + j] = g;
+        if (grad_out) grad_out[h * kDof + j] = g;
+    }
+    if (t == 0) {
+        float J = 0.0f;
+        for (int k = 0; k < kRedThreads / kLanes; ++k) J += s_wave[k];
+        if (J_out) *J_out = J * invN;
+    }
+}
+
+// One Adam step on the stored mean (moments restart at it == 1).
+__global__ void adam_kernel(ProblemDev P, int it, float lr, float b1, float b2, float eps)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.H * kDof) return;
+    const float g = P.grad[t];
+    const float m0 = it == 1 ? 0.0f : P.adam_m[t];
+    const float v0 = it == 1 ? 0.0f : P.adam_v[t];
+    const float m = fmaf(b1, m0, (1.0f - b1) * g);
+    const float v = fmaf(b2, v0, (1.0f - b2) * g * g);
+    P.adam_m[t] = m;
+    P.adam_v[t] = v;
+    const float mh = m / (1.0f - powf(b1, (float)it));
+    const float vh = v / (1.0f - powf(b2, (float)it));
+    P.mean[t] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// cmd = mu_0, then the warm-start shift of the stored mean if requested.
+__global__ void command_kernel(ProblemDev P, float *__restrict__ cmd, int shift)
+{
+    __shared__ float s_mu[kDof * kMaxH];
+    const int t = threadIdx.x;
+    const int n = P.H * kDof;
+    for (int k = t; k < n; k += blockDim.x) s_mu[k] = P.mean[k];
+    __syncthreads();
+    if (t < kDof) cmd[t] = s_mu[t];
+    if (shift)
+        for (int k = t; k < n; k += blockDim.x) P.mean[k] = k + kDof < n ? s_mu[k + kDof] : 0.0f;
+}
+
+}  // namespace
+
+hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal, const float *mean,
+                       const float *noise, float *grad_out, float *J_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)P.n_tiles), dim3(kAdjWaves * kLanes), 0, stream, P, R, x0,
+                       goal, mean, noise);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(kRedThreads), 0, stream, P, grad_out, J_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const ProblemDev &P, int it, float lr, hipStream_t stream)
+{
+    const int n = P.H * kDof;
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, P, it, lr, 0.9f,
+                       0.999f, 1e-8f);
+    return hipGetLastError();
+}
+
+hipError_t launch_command(const ProblemDev &P, float *cmd, int shift, hipStream_t stream)
+{
+    hipLaunchKernelGGL(command_kernel, dim3(1), dim3(256), 0, stream, P, cmd, shift);
+    return hipGetLastError();
+}
+
+}  // namespace storm

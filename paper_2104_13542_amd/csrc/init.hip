@@ -38,6 +38,7 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
     if (t == 0) {
         *P.step = 0u;
         *P.status = 0u;
+        *P.last_step = 0u;
     }
 }
 

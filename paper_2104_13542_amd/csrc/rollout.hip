@@ -23,57 +23,10 @@
 // LDS array is [row][lane] (conflict-free).  Reductions run in a fixed order:
 // results are bitwise reproducible.
 #include "kinematics.h"
+#include "sampling.h"
 
 namespace storm {
 namespace {
-
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
-// products with the Weyl key schedule.
-__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
-                                              uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// Box-Muller on 24-bit uniforms u1 in (0, 1], u2 in [0, 1).
-__device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float &zc, float &zs)
-{
-    const float u1 = (float)((x0 >> 8) + 1u) * 0x1.0p-24f;
-    const float u2 = (float)(x1 >> 8) * 0x1.0p-24f;
-    const float r = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    zc = r * c;
-    zs = r * s;
-}
-
-// Inclusive prefix sum over the lanes of one particle (lanes p*H .. p*H+H-1),
-// Kogge-Stone with wavefront shuffles; h = step index of this lane.
-__device__ __forceinline__ float segmented_scan(float x, int h, int H)
-{
-    for (int off = 1; off < H; off <<= 1) {
-        const float y = __shfl_up(x, (unsigned)off, kLanes);
-        if (h >= off) x += y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ float hinge_box(float x, float lo, float hi)
-{
-    return fmaxf(lo - x, 0.0f) + fmaxf(x - hi, 0.0f);
-}
 
 // One 64-lane tile of one problem, executed by the W waves of the calling
 // workgroup; smem is the workgroup's dynamic LDS (rollout_lds_bytes).
@@ -115,24 +68,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     if (wave < 2) {
         const int j0 = wave * 4;
         float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (live) {
-            if (noise != nullptr) {
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    if (j0 + m < kDof) e[m] = noise[((size_t)(j0 + m) * N + i) * H + h];
-            } else if (i < P.n_halton) {
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    if (j0 + m < kDof) e[m] = P.halton[((size_t)(j0 + m) * P.n_halton + i) * H + h];
-            } else {
-                uint32_t c0 = (uint32_t)i, c1 = (uint32_t)h, c2 = (uint32_t)wave, c3 = *P.step;
-                philox4x32_10(c0, c1, c2, c3, P.seed_lo, P.seed_hi);
-                box_muller(c0, c1, e[0], e[1]);
-                box_muller(c2, c3, e[2], e[3]);
-            }
-        }
+        const uint32_t counter = *P.step;
+        if (live) standard_noise4(P, noise, wave, i, h, counter, e);
 #pragma unroll
         for (int m = 0; m < 4; ++m) s_eps[(j0 + m) * kLanes + lane] = e[m];
+        if (tile == 0 && threadIdx.x == 0) *P.last_step = counter;
     }
     __syncthreads();
 

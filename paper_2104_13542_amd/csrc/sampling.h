@@ -1,0 +1,92 @@
+// Device helpers shared by the rollout and adjoint kernels: counter-based
+// Gaussian noise (Sec. 3.3 sampling) and wavefront segmented scans over the
+// steps of one particle (the triangular sums of Sec. 3.1, Eq. 7).
+#pragma once
+
+#include "storm_internal.h"
+
+namespace storm {
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products with the Weyl key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                              uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Box-Muller on 24-bit uniforms u1 in (0, 1], u2 in [0, 1).
+__device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float &zc, float &zs)
+{
+    const float u1 = (float)((x0 >> 8) + 1u) * 0x1.0p-24f;
+    const float u2 = (float)(x1 >> 8) * 0x1.0p-24f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    zc = r * c;
+    zs = r * s;
+}
+
+// Inclusive prefix sum over the lanes of one particle (lanes p*H .. p*H+H-1),
+// Kogge-Stone with wavefront shuffles; h = step index of this lane.
+__device__ __forceinline__ float segmented_scan(float x, int h, int H)
+{
+    for (int off = 1; off < H; off <<= 1) {
+        const float y = __shfl_up(x, (unsigned)off, kLanes);
+        if (h >= off) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float hinge_box(float x, float lo, float hi)
+{
+    return fmaxf(lo - x, 0.0f) + fmaxf(x - hi, 0.0f);
+}
+
+// Inclusive suffix sum over the lanes of one particle (the transpose of
+// segmented_scan, used by the reverse pass).
+__device__ __forceinline__ float segmented_suffix_scan(float x, int h, int H)
+{
+    for (int off = 1; off < H; off <<= 1) {
+        const float y = __shfl_down(x, (unsigned)off, kLanes);
+        if (h + off < H) x += y;
+    }
+    return x;
+}
+
+// Standard noise of joints 4k..4k+3 for one (particle, step) point from the
+// override, the Halton table or Philox (k = 0 or 1).
+__device__ __forceinline__ void standard_noise4(const ProblemDev &P, const float *__restrict__ noise, int k, int i,
+                                                int h, uint32_t counter, float e[4])
+{
+    const int j0 = 4 * k;
+    if (noise != nullptr) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) e[m] = j0 + m < kDof ? noise[((size_t)(j0 + m) * P.N + i) * P.H + h] : 0.0f;
+    } else if (i < P.n_halton) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            e[m] = j0 + m < kDof ? P.halton[((size_t)(j0 + m) * P.n_halton + i) * P.H + h] : 0.0f;
+    } else {
+        uint32_t c0 = (uint32_t)i, c1 = (uint32_t)h, c2 = (uint32_t)k, c3 = counter;
+        philox4x32_10(c0, c1, c2, c3, P.seed_lo, P.seed_hi);
+        box_muller(c0, c1, e[0], e[1]);
+        box_muller(c2, c3, e[2], e[3]);
+    }
+}
+
+}  // namespace
+}  // namespace storm

@@ -48,6 +48,11 @@ struct ProblemDev {
     float *C;               // [N] horizon costs of the last step
     uint32_t *step;         // sampling step counter (Philox counter word 3)
     uint32_t *status;       // asynchronous status flags
+    uint32_t *last_step;    // counter value the last rollout sampled with (reused by the adjoint)
+    float *grad_part;       // [n_tiles][7][kMaxH] adjoint partial gradients per tile
+    float *cost_part;       // [n_tiles] adjoint partial horizon-cost sums per tile
+    float *grad;            // [H][7] gradient of the expected horizon cost
+    float *adam_m, *adam_v; // [H][7] Adam moments of the refinement
 };
 
 // Robot constants, passed by value (kernel-argument segment, wave-uniform).
@@ -110,6 +115,12 @@ hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int 
                                 const RobotDev &R, const float *x0s, const float *goals, int waves, int grid,
                                 hipStream_t stream);
 hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *cmd, int shift, hipStream_t stream);
+// Differentiable form: adjoint + fixed-order reduction (grad, J), Adam step on
+// the stored mean, and the command / shift of a refined mean.
+hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal, const float *mean,
+                       const float *noise, float *grad_out, float *J_out, hipStream_t stream);
+hipError_t launch_adam(const ProblemDev &P, int it, float lr, hipStream_t stream);
+hipError_t launch_command(const ProblemDev &P, float *cmd, int shift, hipStream_t stream);
 hipError_t launch_fk(const RobotDev &R, const float *q, int n, float *pose, float *manip, hipStream_t stream);
 
 // Self-collision work split of the robot's sphere pairs over `waves`

@@ -83,6 +83,7 @@ EXPORTS = (
     "storm_batch_init", "storm_batch_step", "storm_batch_update", "storm_batch_graph_create",
     "storm_batch_set_config", "storm_batch_get_config", "storm_batch_autotune", "storm_batch_get_state",
     "storm_batch_set_state", "storm_batch_costs", "storm_batch_destroy", "storm_plant_step",
+    "storm_rollout_grad", "storm_rollout_refine", "storm_rollout_graph_create_refine",
 )
 
 
@@ -127,6 +128,10 @@ def lib():
         L.storm_batch_costs.argtypes = [vp, i32, vp, vp]
         L.storm_batch_destroy.argtypes = [vp]
         L.storm_plant_step.argtypes = [vp, vp, i32, ctypes.c_float, vp]
+        L.storm_rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.storm_rollout_refine.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, i32, vp]
+        L.storm_rollout_graph_create_refine.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp,
+                                                        ctypes.POINTER(vp)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_char_p if name == "storm_status_str" else i32
         _lib = L
@@ -278,11 +283,36 @@ class Rollout:
                                              None if st is None else ctypes.addressof(st), _stream()),
                "storm_rollout_set_state")
 
-    def graph(self, x0, goal, cmd, iterations=1, shift=True):
-        """Capture one control step (K iterations) into a HIP graph reading
-        x0 / goal and writing cmd (device tensors whose storage must outlive
-        the graph)."""
+    def graph(self, x0, goal, cmd, iterations=1, shift=True, refine_iters=0, lr=0.05):
+        """Capture one control step (K iterations, then optionally Adam
+        refinement) into a HIP graph reading x0 / goal and writing cmd
+        (device tensors whose storage must outlive the graph)."""
+        if refine_iters:
+            def create(h, x0p, gp, cp, it, sh, stream, out):
+                return lib().storm_rollout_graph_create_refine(h, x0p, gp, cp, it, sh, int(refine_iters),
+                                                               float(lr), stream, out)
+
+            return StepGraph(self, x0, goal, cmd, iterations, shift, create=create)
         return StepGraph(self, x0, goal, cmd, iterations, shift)
+
+    # -- differentiable form -------------------------------------------------
+    def grad(self, mean, goal, x0=None, noise=None):
+        """(dJ/dmu [H][7], J) of the expected horizon cost at `mean` with the
+        last step's noise (or `noise` [7][N][H])."""
+        x0 = self.x0 if x0 is None else x0
+        g = torch.empty((self.H, DOF), dtype=torch.float32, device=self.device)
+        J = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().storm_rollout_grad(self._h, _ptr(x0), _ptr(goal), _ptr(mean.contiguous()), _ptr(noise),
+                                        _ptr(g), _ptr(J), _stream()), "storm_rollout_grad")
+        return g, J
+
+    def refine(self, goal, iterations=3, lr=0.05, x0=None, cmd=None, shift=True):
+        """Adam refinement of the stored mean, then command and shift."""
+        x0 = self.x0 if x0 is None else x0
+        cmd = self.cmd if cmd is None else cmd
+        _check(lib().storm_rollout_refine(self._h, _ptr(x0), _ptr(goal), int(iterations), float(lr), _ptr(cmd),
+                                          int(bool(shift)), _stream()), "storm_rollout_refine")
+        return cmd
 
     def status(self):
         f = ctypes.c_uint32()
@@ -407,6 +437,22 @@ class Batch:
         C = np.zeros(self.problems[p].params.n_particles, dtype=np.float32)
         _check(lib().storm_batch_costs(self._h, int(p), C.ctypes.data, _stream()), "storm_batch_costs")
         return C
+
+
+class ExpectedCost(torch.autograd.Function):
+    """J(mean) = (1/N) sum_i C_i(mean + sigma eps_i) with the last step's
+    noise held fixed; backward is the hand-written adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, mean, rollout, goal, x0=None, noise=None):
+        g, J = rollout.grad(mean.detach(), goal, x0=x0, noise=noise)
+        ctx.save_for_backward(g)
+        return J.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out * g, None, None, None, None
 
 
 def plant_step(x, cmd, dt):
