@@ -115,8 +115,8 @@ typedef struct storm_params {
 /* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame
  * 8 being the end-effector flange (theta = 0).  Row k of dh holds
  * (a_{k-1}, d_k, alpha_{k-1}).  Spheres rows: (body 1..8, x, y, z, r) in the
- * body frame, sorted by body; self-collision checks pairs on bodies at least
- * two apart. */
+ * body frame, sorted by body, 0 < r < 1 m; self-collision checks pairs on
+ * bodies at least two apart. */
 typedef struct storm_robot {
     float dh[STORM_NFRAMES][3];
     float q_min[STORM_DOF], q_max[STORM_DOF]; /* joint position limits */

@@ -34,7 +34,7 @@ int32_t validate_robot(const storm_robot *robot)
         if (s > 0 && r[0] < robot->spheres[5 * (s - 1)]) return STORM_E_PARAM;  // sorted by body
         for (int c = 1; c < 5; ++c)
             if (!finite_f(r[c])) return STORM_E_PARAM;
-        if (!(r[4] > 0.0f)) return STORM_E_PARAM;
+        if (!(r[4] > 0.0f && r[4] < 1.0f)) return STORM_E_PARAM;  // body spheres: 0 < r < 1 m
     }
     return STORM_OK;
 }

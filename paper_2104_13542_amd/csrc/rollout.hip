@@ -9,7 +9,8 @@
 //                  (joints 4k..4k+3); or the Halton table; or the override
 //   A1  waves 0-6  one joint each: u = mu + sigma eps, then the two
 //                  segmented prefix sums of the triple integrator (Eq. 7) as
-//                  wavefront shuffle scans over the particle's lanes
+//                  wavefront shuffle scans over the particle's lanes, and the
+//                  joint's sine and cosine
 //   B   wave 0     forward kinematics (Eq. 8), eight frames to LDS
 //       wave 1     joint / velocity / stop costs (Eq. 10-11)
 //   C   all waves  world centres of the body spheres to LDS
@@ -44,6 +45,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     float *s_penv = s_cen + 3 * S * kLanes; // [W][64]
     float *s_pself = s_penv + W * kLanes;   // [W][64]
     float *s_terms = s_pself + W * kLanes;  // [8][64]
+    float *s_sc = s_terms + 8 * kLanes;     // [7][2][64]: sin q_j, cos q_j
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -85,6 +87,10 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         const float q = q0_j + segmented_scan(dt_h * v, h, H);
         s_q[j * kLanes + lane] = q;
         s_v[j * kLanes + lane] = v;
+        float sq, cq;
+        sincosf(q, &sq, &cq);
+        s_sc[(2 * j) * kLanes + lane] = sq;
+        s_sc[(2 * j + 1) * kLanes + lane] = cq;
         if (valid) {
             const size_t o = ((size_t)j * N + i) * H + h;
             P.u[o] = u;
@@ -103,7 +109,10 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
 #pragma unroll
         for (int f = 0; f < kFrames; ++f) {
             float st = 0.0f, ct = 1.0f;
-            if (f < kDof) sincosf(s_q[f * kLanes + lane], &st, &ct);
+            if (f < kDof) {
+                st = s_sc[(2 * f) * kLanes + lane];
+                ct = s_sc[(2 * f + 1) * kLanes + lane];
+            }
             dh_step(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
 #pragma unroll
             for (int c = 0; c < 9; ++c) s_fr[(f * 12 + c) * kLanes + lane] = r[c];
@@ -163,28 +172,40 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             const float rs2 = rs * rs;
             float best = 0.0f;
             const STORM_CONST_AS float *row = esph + (size_t)4 * s * nso;
-            int o = 0;
-            for (; o + 4 <= nso; o += 4) {
+            // groups of four records, the next group's scalar loads issued
+            // before the current group is tested
+            const int ng = nso >> 2;
+            float cur[16], nxt[16];
+            if (ng > 0) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) cur[m] = row[m];
+            }
+            for (int g = 0; g < ng; ++g) {
+                if (g + 1 < ng) {
+#pragma unroll
+                    for (int m = 0; m < 16; ++m) nxt[m] = row[16 * (g + 1) + m];
+                }
                 float d2[4];
                 bool hit[4];
                 uint64_t any = 0;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const STORM_CONST_AS float *ob = row + 4 * (o + m);
-                    const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
+                    const float dx = x - cur[4 * m], dy = y - cur[4 * m + 1], dz = z - cur[4 * m + 2];
                     d2[m] = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    hit[m] = d2[m] < ob[3];
+                    hit[m] = d2[m] < cur[4 * m + 3];
                     any |= __builtin_amdgcn_ballot_w64(hit[m]);
                 }
                 if (__builtin_expect(any != 0, 0)) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const float pen = fast_sqrt(row[4 * (o + m) + 3]) - fast_sqrt(d2[m]);
+                        const float pen = fast_sqrt(cur[4 * m + 3]) - fast_sqrt(d2[m]);
                         if (hit[m]) best = fmaxf(best, pen);
                     }
                 }
+#pragma unroll
+                for (int m = 0; m < 16; ++m) cur[m] = nxt[m];
             }
-            for (; o < nso; ++o) {
+            for (int o = 4 * ng; o < nso; ++o) {
                 const STORM_CONST_AS float *ob = row + 4 * o;
                 const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
                 const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -194,45 +215,36 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                     if (hit) best = fmaxf(best, pen);
                 }
             }
-            int b = 0;
-            for (; b + 2 <= nbo; b += 2) {
-                float out2[2], qin[2];
-                bool hit[2];
-                uint64_t any = 0;
+            // cuboids one per round, the next record prefetched.  The
+            // per-axis excess max(|l| - e, 0) is also clamped at 1 m (one
+            // instruction with the clamp modifier): body spheres are smaller
+            // than 1 m, so a clamped axis can never turn a miss into a hit,
+            // and on a hit every axis is below the radius and unclamped.
+            float bc[16], bn[16];
+            if (nbo > 0) {
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    const STORM_CONST_AS float *bb = box + (size_t)(b + m) * 16;
-                    const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
-                    const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
-                    const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
-                    const float qx = fabsf(lx) - bb[12], qy = fabsf(ly) - bb[13], qz = fabsf(lz) - bb[14];
-                    const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
-                    out2[m] = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
-                    qin[m] = fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);
-                    hit[m] = out2[m] < rs2;
-                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
-                }
-                if (__builtin_expect(any != 0, 0)) {
-#pragma unroll
-                    for (int m = 0; m < 2; ++m) {
-                        const float pen = rs - (fast_sqrt(out2[m]) + qin[m]);
-                        if (hit[m]) best = fmaxf(best, pen);
-                    }
-                }
+                for (int m = 0; m < 16; ++m) bc[m] = box[m];
             }
-            for (; b < nbo; ++b) {
-                const STORM_CONST_AS float *bb = box + (size_t)b * 16;
-                const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
-                const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
-                const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
-                const float qx = fabsf(lx) - bb[12], qy = fabsf(ly) - bb[13], qz = fabsf(lz) - bb[14];
-                const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
+            for (int b = 0; b < nbo; ++b) {
+                if (b + 1 < nbo) {
+#pragma unroll
+                    for (int m = 0; m < 16; ++m) bn[m] = box[16 * (b + 1) + m];
+                }
+                const float lx = fmaf(bc[0], x, fmaf(bc[1], y, fmaf(bc[2], z, bc[9])));
+                const float ly = fmaf(bc[3], x, fmaf(bc[4], y, fmaf(bc[5], z, bc[10])));
+                const float lz = fmaf(bc[6], x, fmaf(bc[7], y, fmaf(bc[8], z, bc[11])));
+                const float ox = fminf(fmaxf(fabsf(lx) - bc[12], 0.0f), 1.0f);
+                const float oy = fminf(fmaxf(fabsf(ly) - bc[13], 0.0f), 1.0f);
+                const float oz = fminf(fmaxf(fabsf(lz) - bc[14], 0.0f), 1.0f);
                 const float out2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
                 const bool hit = out2 < rs2;
                 if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                    const float pen = rs - (fast_sqrt(out2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f));
+                    const float qm = fminf(fmaxf(fabsf(lx) - bc[12], fmaxf(fabsf(ly) - bc[13], fabsf(lz) - bc[14])), 0.0f);
+                    const float pen = rs - (fast_sqrt(out2) + qm);
                     if (hit) best = fmaxf(best, pen);
                 }
+#pragma unroll
+                for (int m = 0; m < 16; ++m) bc[m] = bn[m];
             }
             env += best;
         }
@@ -417,7 +429,7 @@ __global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const Problem
 
 size_t rollout_lds_bytes(int S, int W)
 {
-    return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms) * kLanes * sizeof(float);
+    return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms + 2 * kDof) * kLanes * sizeof(float);
 }
 
 }  // namespace

@@ -21,7 +21,6 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / kLanes;
-constexpr int kWChunk = 8192;  // weights staged in LDS per chunk of particles
 constexpr int kUnroll = 16;    // independent loads in flight per lane
 
 __device__ __forceinline__ float wave_sum(float x)
@@ -38,25 +37,37 @@ __device__ __forceinline__ float wave_min(float x)
     return x;
 }
 
-// Moment layout.  A lane owns one step h and one "slot" p of a particle
-// group: with H <= 32 a wavefront reads two particles per load (lanes 0-31
-// and 32-63, each a contiguous run of H floats of u[j][i][.]), otherwise one.
-// Work items are (joint j, group range); the 16 waves take them in order and
-// each lane keeps its own sums, merged at the end in a fixed order.
+// Two ways to form the moments, chosen by the number M of particles whose
+// weight is not exactly zero (with beta small against the spread of C, most
+// weights underflow to 0 and contribute nothing):
+//  - sparse (M <= kList): the nonzero weights and their particle indices are
+//    compacted in ascending order into LDS; thread rows of each (joint, step)
+//    column take list entries r, r + R, ... and only those rows of u are read;
+//  - dense: two wavefronts per joint stream u[j] in contiguous rows of H
+//    floats (two particles per load when H <= 32), sixteen loads in flight
+//    per lane.
+// Both add in a fixed order, so results are bitwise reproducible.
+constexpr int kList = 4096;
+
 __device__ __forceinline__ void update_problem(const ProblemDev &P, float *__restrict__ mean_out,
                                                float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift)
 {
-    __shared__ float s_w[kWChunk];
+    __shared__ float s_buf[2 * kList];  // sparse: indices then weights; dense: a chunk of weights
     __shared__ float s_part[2][kWaves][kLanes];
+    __shared__ float s_red[2 * kThreads];
     __shared__ float s_wave[kWaves];
+    __shared__ int s_count[kWaves];
     __shared__ float s_mu[kDof * kMaxH];
     __shared__ float s_v[kDof * kMaxH];
 
     const int t = threadIdx.x;
     const int lane = t & (kLanes - 1), wave = t / kLanes;
     const int N = P.N, H = P.H;
+    const int ncol = kDof * H;
     const float beta = P.beta;
     const float *__restrict__ C = P.C;
+    int *s_idx = reinterpret_cast<int *>(s_buf);
+    float *s_wl = s_buf + kList;
 
     // min C over all particles, and whether any C is not finite
     float cmin = INFINITY;
@@ -74,81 +85,151 @@ __device__ __forceinline__ void update_problem(const ProblemDev &P, float *__res
     for (int k = 1; k < kWaves; ++k) cmin = fminf(cmin, s_wave[k]);
     __syncthreads();
 
-    // weight sum: per-thread sequential, then per wave, then over waves in order
+    // weights: sum (per thread in stride order, then per wave, then waves in
+    // order) and the compacted list of the nonzero ones
     float sw = 0.0f;
-    for (int i = t; i < N; i += kThreads) sw += expf(-(C[i] - cmin) / beta);
+    int base = 0;
+    for (int c0 = 0; c0 < N; c0 += kThreads) {
+        const int i = c0 + t;
+        const float w = i < N ? expf(-(C[i] - cmin) / beta) : 0.0f;
+        sw += w;
+        const bool nz = w > 0.0f;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(nz);
+        const int before = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_count[wave] = __builtin_popcountll(bal);
+        __syncthreads();
+        int off = 0, total = 0;
+        for (int k = 0; k < kWaves; ++k) {
+            const int c = s_count[k];
+            off += k < wave ? c : 0;
+            total += c;
+        }
+        const int pos = base + off + before;
+        if (nz && pos < kList) {
+            s_idx[pos] = i;
+            s_wl[pos] = w;
+        }
+        base += total;
+        __syncthreads();
+    }
     sw = wave_sum(sw);
     if (lane == 0) s_wave[wave] = sw;
     __syncthreads();
     float S0 = 0.0f;
     for (int k = 0; k < kWaves; ++k) S0 += s_wave[k];
     const bool ok = !any_nonfinite && S0 > 0.0f && isfinite(S0);
+    const int M = base;
 
-    // moments of d = u - mu: two waves per joint (14 of the 16 waves), each
-    // over half of the particle groups
-    const int per = H <= 32 ? 2 : 1;        // particles per wavefront load
-    const int seg = H <= 32 ? 32 : 64;      // lanes per particle slot
-    const int slot = lane / seg, h = lane - slot * seg;
-    const bool lane_ok = h < H;
-    const int groups = (N + per - 1) / per;
-    const int j = wave >> 1, half = wave & 1;
-    const bool wave_ok = wave < 2 * kDof;
-    const int g_lo = half ? groups / 2 : 0, g_hi = half ? groups : groups / 2;
-    const float mu = (wave_ok && lane_ok) ? P.mean[h * kDof + j] : 0.0f;
-    const float *__restrict__ U = P.u + (size_t)(wave_ok ? j : 0) * N * H;
-    float s1 = 0.0f, s2 = 0.0f;
-    for (int c0 = 0; c0 < N; c0 += kWChunk) {
-        const int nc = min(kWChunk, N - c0);
-        __syncthreads();
-        for (int k = t; k < nc; k += kThreads) s_w[k] = expf(-(C[c0 + k] - cmin) / beta);
-        __syncthreads();
-        if (!(wave_ok && lane_ok && ok)) continue;
-        // groups whose particle lies in [c0, c0 + nc)
-        const int ga = max(g_lo, (c0 + per - 1) / per), gb = min(g_hi, (c0 + nc + per - 1) / per);
-        int g = ga;
-        for (; g + kUnroll <= gb; g += kUnroll) {
-            float uv[kUnroll];
+    if (M <= kList) {
+        // ---- sparse moments over the compacted list -------------------------
+        const int rows = kThreads / ncol;  // >= 2 for H <= 64
+        const int r = t / ncol, col = t - r * ncol;
+        float a1 = 0.0f, a2 = 0.0f;
+        if (r < rows && ok) {
+            const int j = col / H, h = col - j * H;
+            const float mu = P.mean[h * kDof + j];
+            const float *__restrict__ U = P.u + (size_t)j * N * H + h;
+            int k = r;
+            for (; k + 3 * rows < M; k += 4 * rows) {
+                float d[4];
 #pragma unroll
-            for (int m = 0; m < kUnroll; ++m) {
-                const int i = (g + m) * per + slot;
-                uv[m] = i < N ? U[(size_t)i * H + h] : mu;
+                for (int m = 0; m < 4; ++m) d[m] = U[(size_t)s_idx[k + m * rows] * H] - mu;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float wd = s_wl[k + m * rows] * d[m];
+                    a1 += wd;
+                    a2 = fmaf(wd, d[m], a2);
+                }
             }
-#pragma unroll
-            for (int m = 0; m < kUnroll; ++m) {
-                const int i = (g + m) * per + slot;
-                const float d = uv[m] - mu;
-                const float wd = (i < N ? s_w[i - c0] : 0.0f) * d;
-                s1 += wd;
-                s2 = fmaf(wd, d, s2);
+            for (; k < M; k += rows) {
+                const float d = U[(size_t)s_idx[k] * H] - mu;
+                const float wd = s_wl[k] * d;
+                a1 += wd;
+                a2 = fmaf(wd, d, a2);
             }
         }
-        for (; g < gb; ++g) {
-            const int i = g * per + slot;
-            if (i < N) {
-                const float d = U[(size_t)i * H + h] - mu;
-                const float wd = s_w[i - c0] * d;
-                s1 += wd;
-                s2 = fmaf(wd, d, s2);
+        s_red[t] = a1;
+        s_red[kThreads + t] = a2;
+        __syncthreads();
+        for (int c = t; c < ncol; c += kThreads) {
+            float x1 = 0.0f, x2 = 0.0f;
+            for (int k = 0; k < rows; ++k) {
+                x1 += s_red[k * ncol + c];
+                x2 += s_red[kThreads + k * ncol + c];
             }
+            s_red[c] = x1;  // rows were read above by this thread only for column c
+            s_v[c] = x2;
+        }
+    } else {
+        // ---- dense moments --------------------------------------------------
+        const int per = H <= 32 ? 2 : 1;
+        const int seg = H <= 32 ? 32 : 64;
+        const int slot = lane / seg, h = lane - slot * seg;
+        const bool lane_ok = h < H;
+        const int groups = (N + per - 1) / per;
+        const int j = wave >> 1, half = wave & 1;
+        const bool wave_ok = wave < 2 * kDof;
+        const int g_lo = half ? groups / 2 : 0, g_hi = half ? groups : groups / 2;
+        const float mu = (wave_ok && lane_ok) ? P.mean[h * kDof + j] : 0.0f;
+        const float *__restrict__ U = P.u + (size_t)(wave_ok ? j : 0) * N * H;
+        float s1 = 0.0f, s2 = 0.0f;
+        for (int c0 = 0; c0 < N; c0 += 2 * kList) {
+            const int nc = min(2 * kList, N - c0);
+            __syncthreads();
+            for (int k = t; k < nc; k += kThreads) s_buf[k] = expf(-(C[c0 + k] - cmin) / beta);
+            __syncthreads();
+            if (!(wave_ok && lane_ok && ok)) continue;
+            const int ga = max(g_lo, (c0 + per - 1) / per), gb = min(g_hi, (c0 + nc + per - 1) / per);
+            int g = ga;
+            for (; g + kUnroll <= gb; g += kUnroll) {
+                float uv[kUnroll];
+#pragma unroll
+                for (int m = 0; m < kUnroll; ++m) {
+                    const int i = (g + m) * per + slot;
+                    uv[m] = i < N ? U[(size_t)i * H + h] : mu;
+                }
+#pragma unroll
+                for (int m = 0; m < kUnroll; ++m) {
+                    const int i = (g + m) * per + slot;
+                    const float d = uv[m] - mu;
+                    const float wd = (i < N ? s_buf[i - c0] : 0.0f) * d;
+                    s1 += wd;
+                    s2 = fmaf(wd, d, s2);
+                }
+            }
+            for (; g < gb; ++g) {
+                const int i = g * per + slot;
+                if (i < N) {
+                    const float d = U[(size_t)i * H + h] - mu;
+                    const float wd = s_buf[i - c0] * d;
+                    s1 += wd;
+                    s2 = fmaf(wd, d, s2);
+                }
+            }
+        }
+        s_part[0][wave][lane] = s1;
+        s_part[1][wave][lane] = s2;
+        __syncthreads();
+        for (int c = t; c < ncol; c += kThreads) {
+            const int jj = c / H, hh = c - jj * H;
+            float x1 = 0.0f, x2 = 0.0f;
+            for (int w = 2 * jj; w < 2 * jj + 2; ++w)
+                for (int sl = 0; sl < per; ++sl) {
+                    x1 += s_part[0][w][sl * seg + hh];
+                    x2 += s_part[1][w][sl * seg + hh];
+                }
+            s_red[c] = x1;
+            s_v[c] = x2;
         }
     }
-    s_part[0][wave][lane] = s1;
-    s_part[1][wave][lane] = s2;
     __syncthreads();
-    // column (j, h): waves 2j and 2j+1, slots in order
-    for (int col = t; col < kDof * H; col += kThreads) {
-        const int jj = col / H, hh = col - jj * H;
-        float a1 = 0.0f, a2 = 0.0f;
-        for (int w = 2 * jj; w < 2 * jj + 2; ++w)
-            for (int sl = 0; sl < per; ++sl) {
-                a1 += s_part[0][w][sl * seg + hh];
-                a2 += s_part[1][w][sl * seg + hh];
-            }
+    for (int c = t; c < ncol; c += kThreads) {
+        const int jj = c / H, hh = c - jj * H;
         const float muo = P.mean[hh * kDof + jj];
-        const float m1 = a1 / S0, m2 = a2 / S0;
+        const float m1 = s_red[c] / S0, m2 = s_v[c] / S0;
         const float delta = P.alpha_mu * m1;
-        s_mu[col] = ok ? muo + delta : muo;
-        s_v[col] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
+        s_mu[c] = ok ? muo + delta : muo;
+        s_v[c] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
     }
     __syncthreads();
     if (t < kDof) {
@@ -161,10 +242,10 @@ __device__ __forceinline__ void update_problem(const ProblemDev &P, float *__res
         if (sigma2_out) sigma2_out[t] = s2n;
         cmd[t] = s_mu[t * H];
     }
-    for (int col = t; col < kDof * H; col += kThreads) {
-        const int jj = col / H, hh = col - jj * H;
-        if (mean_out) mean_out[hh * kDof + jj] = s_mu[col];
-        P.mean[hh * kDof + jj] = shift ? (hh + 1 < H ? s_mu[col + 1] : 0.0f) : s_mu[col];
+    for (int c = t; c < ncol; c += kThreads) {
+        const int jj = c / H, hh = c - jj * H;
+        if (mean_out) mean_out[hh * kDof + jj] = s_mu[c];
+        P.mean[hh * kDof + jj] = shift ? (hh + 1 < H ? s_mu[c + 1] : 0.0f) : s_mu[c];
     }
     if (t == 0) {
         *P.step = *P.step + 1u;

@@ -315,3 +315,21 @@ def test_graph_replays_match_eager(iterations):
     finally:
         eager.close()
         graphed.close()
+
+
+@pytest.mark.parametrize("N,H,beta", [(5000, 16, 1e6), (700, 30, 1e6), (3000, 8, 50.0)])
+def test_update_dense_and_sparse_paths(oracle_lib, N, H, beta):
+    """The update gathers only particles with nonzero weight when they fit
+    the compaction list (4096) and streams every particle otherwise; both
+    must equal the oracle's update on the same costs and controls."""
+    prob = inputs.config1(8)
+    prob.params.n_particles = N
+    prob.params.horizon = H
+    prob.params.dt = np.full(H, 0.02)
+    prob.params.beta = beta
+    prob.params.n_null = 3
+    eps = inputs.standard_normal(900 + N, (N, H, 7))
+    g, ro, up, o, _ = run_pair(prob, oracle_lib, noise_nhj=eps)
+    upd = o.update(g["C"], g["u"], np.zeros((H, 7)), f32(np.asarray(prob.params.sigma_init) ** 2))
+    assert np.max(np.abs(g["mean"] - upd["mean"])) <= TOL_MEAN
+    assert np.max(np.abs(g["sigma2"] - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"])
