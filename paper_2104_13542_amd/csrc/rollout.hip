@@ -172,40 +172,28 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             const float rs2 = rs * rs;
             float best = 0.0f;
             const STORM_CONST_AS float *row = esph + (size_t)4 * s * nso;
-            // groups of four records, the next group's scalar loads issued
-            // before the current group is tested
-            const int ng = nso >> 2;
-            float cur[16], nxt[16];
-            if (ng > 0) {
-#pragma unroll
-                for (int m = 0; m < 16; ++m) cur[m] = row[m];
-            }
-            for (int g = 0; g < ng; ++g) {
-                if (g + 1 < ng) {
-#pragma unroll
-                    for (int m = 0; m < 16; ++m) nxt[m] = row[16 * (g + 1) + m];
-                }
+            int o = 0;
+            for (; o + 4 <= nso; o += 4) {
                 float d2[4];
                 bool hit[4];
                 uint64_t any = 0;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const float dx = x - cur[4 * m], dy = y - cur[4 * m + 1], dz = z - cur[4 * m + 2];
+                    const STORM_CONST_AS float *ob = row + 4 * (o + m);
+                    const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
                     d2[m] = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    hit[m] = d2[m] < cur[4 * m + 3];
+                    hit[m] = d2[m] < ob[3];
                     any |= __builtin_amdgcn_ballot_w64(hit[m]);
                 }
                 if (__builtin_expect(any != 0, 0)) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const float pen = fast_sqrt(cur[4 * m + 3]) - fast_sqrt(d2[m]);
+                        const float pen = fast_sqrt(row[4 * (o + m) + 3]) - fast_sqrt(d2[m]);
                         if (hit[m]) best = fmaxf(best, pen);
                     }
                 }
-#pragma unroll
-                for (int m = 0; m < 16; ++m) cur[m] = nxt[m];
             }
-            for (int o = 4 * ng; o < nso; ++o) {
+            for (; o < nso; ++o) {
                 const STORM_CONST_AS float *ob = row + 4 * o;
                 const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
                 const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -215,36 +203,55 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                     if (hit) best = fmaxf(best, pen);
                 }
             }
-            // cuboids one per round, the next record prefetched.  The
-            // per-axis excess max(|l| - e, 0) is also clamped at 1 m (one
-            // instruction with the clamp modifier): body spheres are smaller
-            // than 1 m, so a clamped axis can never turn a miss into a hit,
-            // and on a hit every axis is below the radius and unclamped.
-            float bc[16], bn[16];
-            if (nbo > 0) {
+            int b = 0;
+            for (; b + 2 <= nbo; b += 2) {
+                float out2[2], lxyz[2][3];
+                bool hit[2];
+                uint64_t any = 0;
 #pragma unroll
-                for (int m = 0; m < 16; ++m) bc[m] = box[m];
-            }
-            for (int b = 0; b < nbo; ++b) {
-                if (b + 1 < nbo) {
-#pragma unroll
-                    for (int m = 0; m < 16; ++m) bn[m] = box[16 * (b + 1) + m];
+                for (int m = 0; m < 2; ++m) {
+                    const STORM_CONST_AS float *bb = box + (size_t)(b + m) * 16;
+                    const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
+                    const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
+                    const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
+                    // excess per axis, clamped to [0, 1 m]: one instruction with the
+                    // clamp modifier; body spheres are below 1 m, so clamping cannot
+                    // turn a miss into a hit and leaves every axis of a hit exact
+                    const float ox = fminf(fmaxf(fabsf(lx) - bb[12], 0.0f), 1.0f);
+                    const float oy = fminf(fmaxf(fabsf(ly) - bb[13], 0.0f), 1.0f);
+                    const float oz = fminf(fmaxf(fabsf(lz) - bb[14], 0.0f), 1.0f);
+                    out2[m] = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+                    lxyz[m][0] = lx;
+                    lxyz[m][1] = ly;
+                    lxyz[m][2] = lz;
+                    hit[m] = out2[m] < rs2;
+                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
                 }
-                const float lx = fmaf(bc[0], x, fmaf(bc[1], y, fmaf(bc[2], z, bc[9])));
-                const float ly = fmaf(bc[3], x, fmaf(bc[4], y, fmaf(bc[5], z, bc[10])));
-                const float lz = fmaf(bc[6], x, fmaf(bc[7], y, fmaf(bc[8], z, bc[11])));
-                const float ox = fminf(fmaxf(fabsf(lx) - bc[12], 0.0f), 1.0f);
-                const float oy = fminf(fmaxf(fabsf(ly) - bc[13], 0.0f), 1.0f);
-                const float oz = fminf(fmaxf(fabsf(lz) - bc[14], 0.0f), 1.0f);
+                if (__builtin_expect(any != 0, 0)) {
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) {
+                        const STORM_CONST_AS float *bb = box + (size_t)(b + m) * 16;
+                        const float qin = fminf(fmaxf(fabsf(lxyz[m][0]) - bb[12],
+                                                      fmaxf(fabsf(lxyz[m][1]) - bb[13], fabsf(lxyz[m][2]) - bb[14])),
+                                                0.0f);
+                        const float pen = rs - (fast_sqrt(out2[m]) + qin);
+                        if (hit[m]) best = fmaxf(best, pen);
+                    }
+                }
+            }
+            for (; b < nbo; ++b) {
+                const STORM_CONST_AS float *bb = box + (size_t)b * 16;
+                const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
+                const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
+                const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
+                const float qx = fabsf(lx) - bb[12], qy = fabsf(ly) - bb[13], qz = fabsf(lz) - bb[14];
+                const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
                 const float out2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
                 const bool hit = out2 < rs2;
                 if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                    const float qm = fminf(fmaxf(fabsf(lx) - bc[12], fmaxf(fabsf(ly) - bc[13], fabsf(lz) - bc[14])), 0.0f);
-                    const float pen = rs - (fast_sqrt(out2) + qm);
+                    const float pen = rs - (fast_sqrt(out2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f));
                     if (hit) best = fmaxf(best, pen);
                 }
-#pragma unroll
-                for (int m = 0; m < 16; ++m) bc[m] = bn[m];
             }
             env += best;
         }
