@@ -51,11 +51,30 @@ def flops_per_particle_step(mask, n_spheres, n_pairs, n_sph_obs, n_box_obs, gaus
     if mask & (I.COST_SELF | I.COST_ENV):
         f += 18.0 * n_spheres  # world sphere centres
     if mask & I.COST_ENV:
-        f += n_spheres * (11.0 * n_sph_obs + 30.0 * n_box_obs)
+        # sphere obstacle: |x|^2 - 2 c.x + |c|^2 test = 3 FMA + compare (+ |x|^2 once per sphere);
+        # cuboid: 9 FMA transform (18), 3 excesses |l| - e clamped (6), square sum (5), compare
+        f += n_spheres * (5.0 + 7.0 * n_sph_obs + 30.0 * n_box_obs)
     if mask & I.COST_SELF:
         f += 9.0 * n_pairs
     f += 22.0  # weighted sum (Eq. 15) and horizon weight (Eq. 2)
     return f
+
+
+def measured_traffic():
+    """HBM bytes per rollout launch from the committed rocprofv3 counter
+    summary, if it was taken on the kernel source as it is now (else None)."""
+    import hashlib
+
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "rollout_kernel_traffic.json")))
+    except (OSError, ValueError):
+        return None
+    src = b""
+    for f in ("rollout.hip", "kinematics.h", "sampling.h"):
+        src += open(os.path.join(ROOT, "paper_2104_13542_amd", "csrc", f), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def self_pair_count(spheres):
@@ -201,6 +220,8 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=256, help="batched workload size (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-latency-steps", type=int, default=1000)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the MPC step of one problem runs on a single MI355X "
@@ -246,16 +267,15 @@ def main():
     torch.cuda.synchronize()
     graph_ms = start.elapsed_time(end) / K
 
-    # the rollout kernel alone, launch after launch, timed by HIP events on
-    # the stream it runs on (its average duration prices the roofline)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    # the rollout kernel alone, K launches back to back on the stream it runs
+    # on, bracketed by HIP events (its average duration prices the roofline)
     torch.cuda.synchronize()
-    for k in range(K):
-        ev[k][0].record()
+    start.record()
+    for _ in range(K):
         r.step(goal, x0=x0, C=C)
-        ev[k][1].record()
+    end.record()
     torch.cuda.synchronize()
-    rollout_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    rollout_ms = start.elapsed_time(end) / K
     r.update(shift=True, want_mean=False, cmd=cmd)
 
     # eager (two launches per step from the host) for comparison
@@ -337,9 +357,18 @@ def main():
             "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "flops_per_launch": fpp * N * H,
             "avg_launch_us": rollout_ms * 1e3,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = n * 4
     if args.batch_problems > 0:
         line["batched"] = batched_bench(args.batch_problems, args.batch_steps, args.batch_latency_steps,
                                         warmup=5, tune_reps=3)

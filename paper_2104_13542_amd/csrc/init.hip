@@ -59,10 +59,19 @@ __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float 
         sph_obs[t] = make_float4(r[1], r[2], r[3], r[4]);
     }
     if (t < S * n_so) {
+        // test record of (body sphere s, obstacle o) for the expanded form
+        // |x|^2 - 2 c.x + |c|^2 < (r_s + r_o)^2: (-2c, (r_s + r_o)^2 - |c|^2 +
+        // slack).  The slack (2^-15 (1 + |c|)^2) exceeds the FP32 rounding of
+        // the expanded sum for any point within 2 m of the base, so the test
+        // has no false negatives; hits are resolved with the exact distance.
         const int s = t / n_so, o = t - s * n_so;
         const float *r = sph_obs_raw + o * STORM_OBSTACLE_STRIDE;
+        const double cx = r[1], cy = r[2], cz = r[3];
+        const double c2 = cx * cx + cy * cy + cz * cz;
         const double rr = (double)sph_raw[s * 5 + 4] + (double)r[4];
-        env_sph[t] = make_float4(r[1], r[2], r[3], (float)(rr * rr));
+        const double slack = ldexp((1.0 + sqrt(c2)) * (1.0 + sqrt(c2)), -15);
+        env_sph[t] = make_float4((float)(-2.0 * cx), (float)(-2.0 * cy), (float)(-2.0 * cz),
+                                 (float)(rr * rr - c2 + slack));
     }
     if (t < n_bo) {
         const float *r = box_raw + t * STORM_OBSTACLE_STRIDE;

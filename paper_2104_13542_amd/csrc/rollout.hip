@@ -172,34 +172,41 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             const float rs2 = rs * rs;
             float best = 0.0f;
             const STORM_CONST_AS float *row = esph + (size_t)4 * s * nso;
+            const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
+            // sphere obstacles, four per round: |x|^2 - 2 c.x + |c|^2 against
+            // the record's threshold (three FMAs and a compare); lanes that
+            // pass get the exact distance and penetration (r_s + r_o) - |x - c|,
+            // which a rounding near-miss leaves at or below zero
+            const float xs2 = fmaf(x, x, fmaf(y, y, z * z));
             int o = 0;
             for (; o + 4 <= nso; o += 4) {
-                float d2[4];
                 bool hit[4];
                 uint64_t any = 0;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const STORM_CONST_AS float *ob = row + 4 * (o + m);
-                    const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
-                    d2[m] = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    hit[m] = d2[m] < ob[3];
+                    const float a = fmaf(x, ob[0], fmaf(y, ob[1], fmaf(z, ob[2], xs2)));
+                    hit[m] = a < ob[3];
                     any |= __builtin_amdgcn_ballot_w64(hit[m]);
                 }
                 if (__builtin_expect(any != 0, 0)) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const float pen = fast_sqrt(row[4 * (o + m) + 3]) - fast_sqrt(d2[m]);
+                        const STORM_CONST_AS float *so = sob + 4 * (o + m);
+                        const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
+                        const float pen = (rs + so[3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
                         if (hit[m]) best = fmaxf(best, pen);
                     }
                 }
             }
             for (; o < nso; ++o) {
                 const STORM_CONST_AS float *ob = row + 4 * o;
-                const float dx = x - ob[0], dy = y - ob[1], dz = z - ob[2];
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const bool hit = d2 < ob[3];
+                const float a = fmaf(x, ob[0], fmaf(y, ob[1], fmaf(z, ob[2], xs2)));
+                const bool hit = a < ob[3];
                 if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                    const float pen = fast_sqrt(ob[3]) - fast_sqrt(d2);
+                    const STORM_CONST_AS float *so = sob + 4 * o;
+                    const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
+                    const float pen = (rs + so[3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
                     if (hit) best = fmaxf(best, pen);
                 }
             }

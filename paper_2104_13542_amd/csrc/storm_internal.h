@@ -40,7 +40,7 @@ struct ProblemDev {
     const float *tables;    // [kTabSize]
     const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
     const float4 *sph_obs;  // [n_sph_obs] centre, radius
-    const float4 *env_sph;  // [S][n_sph_obs] obstacle centre, (r_s + r_o)^2 for body sphere s
+    const float4 *env_sph;  // [S][n_sph_obs] -2 c_o, (r_s + r_o)^2 - |c_o|^2 + slack for body sphere s
     const float *box_obs;   // [n_box_obs][16]: M = R^T (9, row-major), t = -R^T c (3), half extents (3), pad
     float *mean;            // [H][7]
     float *sigma2;          // [7]
