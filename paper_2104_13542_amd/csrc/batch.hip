@@ -68,15 +68,19 @@ hipError_t robot_for_waves(storm_batch b, const storm_robot *robot, int waves, R
     return e;
 }
 
-// Estimated VALU work of one tile of problem p (the scheduler's sort key):
-// collision tests dominate, then the per-point kinematics.
+// Estimated VALU work of one tile of problem p (the scheduler's sort key),
+// in instructions per wave: the per-point kinematics, the environment broad
+// phase (wave ball per sphere, one 64-obstacle chunk per pass) plus the few
+// exact tests that survive it (about 2% of the pairs), and the sphere pairs.
 double tile_cost(const ProblemDev &P, int n_spheres, int n_pairs)
 {
-    const double points = (double)P.ppt * P.H;
-    double per_point = 1500.0;
-    if (P.cost_mask & STORM_COST_ENV) per_point += n_spheres * (7.0 * P.n_sph_obs + 19.0 * P.n_box_obs);
-    if (P.cost_mask & STORM_COST_SELF) per_point += 7.0 * n_pairs;
-    return points * per_point;
+    double per_wave = 1500.0;
+    if (P.cost_mask & STORM_COST_ENV) {
+        const int chunks = (P.n_sph_obs + P.n_box_obs + 63) / 64;
+        per_wave += n_spheres * (40.0 + 12.0 * chunks + 0.02 * (5.0 * P.n_sph_obs + 19.0 * P.n_box_obs));
+    }
+    if (P.cost_mask & STORM_COST_SELF) per_wave += 7.0 * n_pairs;
+    return per_wave;
 }
 
 int32_t launch_batch_step(storm_batch b, const float *d_x0, const float *d_goal, hipStream_t s)

@@ -50,13 +50,26 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
 //   body spheres:     (local centre, radius) and the frame index
 //   self pairs:       (r_s + r_t)^2 for every sphere pair
 __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float *box_raw, int n_bo,
-                                float4 *sph_obs, float4 *env_sph, float *box_obs, const float *sph_raw, int S,
-                                float4 *sph_local, int32_t *sph_body, float *self_rr2)
+                                float4 *sph_obs, float4 *env_sph, float *box_obs, float4 *obs_bound,
+                                const float *sph_raw, int S, float4 *sph_local, int32_t *sph_body, float *self_rr2)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_so) {
         const float *r = sph_obs_raw + t * STORM_OBSTACLE_STRIDE;
         sph_obs[t] = make_float4(r[1], r[2], r[3], r[4]);
+    }
+    if (t < n_so + n_bo) {
+        // culling record: the obstacle lies inside the ball (centre, radius);
+        // a cuboid's ball has the radius of its half-extent diagonal.  The
+        // 1e-4 m margin dwarfs the FP32 rounding of any distance the cull or
+        // the exact tests form, so no contact the exact tests would report is
+        // ever culled.
+        const bool sphere = t < n_so;
+        const float *r = sphere ? sph_obs_raw + t * STORM_OBSTACLE_STRIDE
+                                : box_raw + (t - n_so) * STORM_OBSTACLE_STRIDE;
+        const double rad = sphere ? (double)r[4]
+                                  : sqrt((double)r[4] * r[4] + (double)r[5] * r[5] + (double)r[6] * r[6]);
+        obs_bound[t] = make_float4(r[1], r[2], r[3], (float)(rad + 1e-4));
     }
     if (t < S * n_so) {
         // test record of (body sphere s, obstacle o) for the expanded form
@@ -191,7 +204,7 @@ __global__ void halton_smooth_kernel(int n_halton, int K, int H, const double *Z
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
                               int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
-                              float *d_box_obs, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
+                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
                               int32_t *d_sph_body, float *d_self_rr2, hipStream_t stream)
 {
     (void)n_obs;
@@ -203,13 +216,12 @@ hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const 
     const int S = n_spheres, n_so = P.n_sph_obs, n_bo = P.n_box_obs;
     int ng = S * S;
     if (S * n_so > ng) ng = S * n_so;
-    if (n_so > ng) ng = n_so;
-    if (n_bo > ng) ng = n_bo;
+    if (n_so + n_bo > ng) ng = n_so + n_bo;
     const int gthreads = 256;
     const int gblocks = ng > 0 ? (ng + gthreads - 1) / gthreads : 1;
     hipLaunchKernelGGL(geometry_kernel, dim3(gblocks), dim3(gthreads), 0, stream, d_obs_raw, n_so,
                        d_obs_raw + (size_t)STORM_OBSTACLE_STRIDE * n_so, n_bo, d_sph_obs, d_env_sph, d_box_obs,
-                       d_sph_raw, S, d_sph_local, d_sph_body, d_self_rr2);
+                       d_obs_bound, d_sph_raw, S, d_sph_local, d_sph_body, d_self_rr2);
     e = hipGetLastError();
     if (e != hipSuccess || P.n_halton == 0) return e;
     double *Z = nullptr;

@@ -29,6 +29,35 @@
 namespace storm {
 namespace {
 
+// Wavefront-wide maximum of a non-negative float: IEEE bit patterns of
+// non-negative floats order like unsigned integers, so the maximum runs on
+// the bits through DPP lane moves (quad permutes, half-row and row mirrors,
+// then the row broadcasts that carry each row's result into the next) and is
+// read back from lane 63, the lane every step feeds, into an SGPR.
+__device__ __forceinline__ float wave_max_nonneg(float x)
+{
+    uint32_t b = __float_as_uint(x);
+    b = max(b, (uint32_t)__builtin_amdgcn_mov_dpp((int)b, 0xb1, 0xf, 0xf, false));   // quad_perm [1, 0, 3, 2]
+    b = max(b, (uint32_t)__builtin_amdgcn_mov_dpp((int)b, 0x4e, 0xf, 0xf, false));   // quad_perm [2, 3, 0, 1]
+    b = max(b, (uint32_t)__builtin_amdgcn_mov_dpp((int)b, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    b = max(b, (uint32_t)__builtin_amdgcn_mov_dpp((int)b, 0x140, 0xf, 0xf, false));  // row_mirror
+    b = max(b, (uint32_t)__builtin_amdgcn_mov_dpp((int)b, 0x142, 0xa, 0xf, false));  // row_bcast:15, rows 1 and 3
+    b = max(b, (uint32_t)__builtin_amdgcn_mov_dpp((int)b, 0x143, 0xc, 0xf, false));  // row_bcast:31, rows 2 and 3
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)b, 63));
+}
+
+// Lane 0's value, as a wave-uniform (SGPR) float.
+__device__ __forceinline__ float uniform_lane0(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Culling record o, or one that no test can pass for o beyond the scene.
+__device__ __forceinline__ float4 load_bound(const float4 *__restrict__ b, int o, int n)
+{
+    return o < n ? b[o] : make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
+}
+
 // One 64-lane tile of one problem, executed by the W waves of the calling
 // workgroup; smem is the workgroup's dynamic LDS (rollout_lds_bytes).
 template <int W>
@@ -65,6 +94,9 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     const float sig_j = sqrtf(P.sigma2[jw]);
     const float dt_h = tab[kTabDt + h];
     const float q0_j = x0[jw], v0_j = x0[kDof + jw];
+    // culling record of obstacle `lane` (first 64 obstacles) for phase D
+    const float4 bound0 = (mask & STORM_COST_ENV) ? load_bound(P.obs_bound, lane, P.n_sph_obs + P.n_box_obs)
+                                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
     // ---- A0: standard noise ------------------------------------------------
     if (wave < 2) {
@@ -161,103 +193,75 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     float env = 0.0f, selfpen = 0.0f;
     if (mask & STORM_COST_ENV) {
         const STORM_CONST_AS float *esph = uniform_ptr(reinterpret_cast<const float *>(P.env_sph));
+        const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
         const STORM_CONST_AS float *box = uniform_ptr(P.box_obs);
         const STORM_CONST_AS float *sloc = uniform_ptr(reinterpret_cast<const float *>(R.sph_local));
-        const int nso = P.n_sph_obs, nbo = P.n_box_obs;
+        const int nso = P.n_sph_obs, nobs = P.n_sph_obs + P.n_box_obs;
         for (int s = wave; s < S; s += W) {
             const float x = s_cen[(s * 3 + 0) * kLanes + lane];
             const float y = s_cen[(s * 3 + 1) * kLanes + lane];
             const float z = s_cen[(s * 3 + 2) * kLanes + lane];
             const float rs = sloc[4 * s + 3];
             const float rs2 = rs * rs;
-            float best = 0.0f;
-            const STORM_CONST_AS float *row = esph + (size_t)4 * s * nso;
-            const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
-            // sphere obstacles, four per round: |x|^2 - 2 c.x + |c|^2 against
-            // the record's threshold (three FMAs and a compare); lanes that
-            // pass get the exact distance and penetration (r_s + r_o) - |x - c|,
-            // which a rounding near-miss leaves at or below zero
             const float xs2 = fmaf(x, x, fmaf(y, y, z * z));
-            int o = 0;
-            for (; o + 4 <= nso; o += 4) {
-                bool hit[4];
-                uint64_t any = 0;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const STORM_CONST_AS float *ob = row + 4 * (o + m);
-                    const float a = fmaf(x, ob[0], fmaf(y, ob[1], fmaf(z, ob[2], xs2)));
-                    hit[m] = a < ob[3];
-                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
-                }
-                if (__builtin_expect(any != 0, 0)) {
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const STORM_CONST_AS float *so = sob + 4 * (o + m);
-                        const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
-                        const float pen = (rs + so[3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                        if (hit[m]) best = fmaxf(best, pen);
+            // Broad phase: the wave's 64 centres of this sphere lie in the
+            // ball of radius rad about lane 0's centre; by the triangle
+            // inequality an obstacle whose bounding ball is farther than
+            // rad + r_s from that point touches the sphere at no lane.  One
+            // lane tests one obstacle, and a ballot gives the candidates.  A
+            // non-finite centre anywhere in the wave turns the culling off.
+            const float rx = uniform_lane0(x), ry = uniform_lane0(y), rz = uniform_lane0(z);
+            const float ax = x - rx, ay = y - ry, az = z - rz;
+            const float rad = fast_sqrt(wave_max_nonneg(fminf(fmaf(ax, ax, fmaf(ay, ay, az * az)), 1.0e30f)));
+            const bool cull = rad < 1.0e6f;
+            const float rad_rs = rad + rs;
+            float best = 0.0f;
+            for (int o0 = 0; o0 < nobs; o0 += kLanes) {
+                const float4 bd = o0 == 0 ? bound0 : load_bound(P.obs_bound, o0 + lane, nobs);
+                const float dx = bd.x - rx, dy = bd.y - ry, dz = bd.z - rz;
+                const float reach = bd.w + rad_rs;
+                uint64_t cand = cull ? __builtin_amdgcn_ballot_w64(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < reach * reach)
+                                     : __builtin_amdgcn_ballot_w64(o0 + lane < nobs);
+                // Narrow phase over the candidates, in increasing obstacle
+                // order (the maximum does not depend on the order).
+                while (cand != 0) {
+                    const int o = o0 + (int)__builtin_ctzll(cand);
+                    cand &= cand - 1;
+                    if (o < nso) {
+                        // |x|^2 - 2 c.x + |c|^2 against the record's threshold;
+                        // lanes that pass get the exact penetration
+                        // (r_s + r_o) - |x - c|, which a rounding near-miss
+                        // leaves at or below zero
+                        const STORM_CONST_AS float *ob = esph + (size_t)4 * (s * nso + o);
+                        const float a = fmaf(x, ob[0], fmaf(y, ob[1], fmaf(z, ob[2], xs2)));
+                        const bool hit = a < ob[3];
+                        if (__builtin_amdgcn_ballot_w64(hit) != 0) {
+                            const STORM_CONST_AS float *so = sob + 4 * o;
+                            const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
+                            const float pen = (rs + so[3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                            if (hit) best = fmaxf(best, pen);
+                        }
+                    } else {
+                        const STORM_CONST_AS float *bb = box + (size_t)(o - nso) * 16;
+                        const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
+                        const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
+                        const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
+                        // excess per axis, clamped to [0, 1 m]: one instruction
+                        // with the clamp modifier; body spheres are below 1 m, so
+                        // clamping cannot turn a miss into a hit and leaves every
+                        // axis of a hit exact
+                        const float ox = fminf(fmaxf(fabsf(lx) - bb[12], 0.0f), 1.0f);
+                        const float oy = fminf(fmaxf(fabsf(ly) - bb[13], 0.0f), 1.0f);
+                        const float oz = fminf(fmaxf(fabsf(lz) - bb[14], 0.0f), 1.0f);
+                        const float out2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+                        const bool hit = out2 < rs2;
+                        if (__builtin_amdgcn_ballot_w64(hit) != 0) {
+                            const float qin =
+                                fminf(fmaxf(fabsf(lx) - bb[12], fmaxf(fabsf(ly) - bb[13], fabsf(lz) - bb[14])), 0.0f);
+                            const float pen = rs - (fast_sqrt(out2) + qin);
+                            if (hit) best = fmaxf(best, pen);
+                        }
                     }
-                }
-            }
-            for (; o < nso; ++o) {
-                const STORM_CONST_AS float *ob = row + 4 * o;
-                const float a = fmaf(x, ob[0], fmaf(y, ob[1], fmaf(z, ob[2], xs2)));
-                const bool hit = a < ob[3];
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                    const STORM_CONST_AS float *so = sob + 4 * o;
-                    const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
-                    const float pen = (rs + so[3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                    if (hit) best = fmaxf(best, pen);
-                }
-            }
-            int b = 0;
-            for (; b + 2 <= nbo; b += 2) {
-                float out2[2], lxyz[2][3];
-                bool hit[2];
-                uint64_t any = 0;
-#pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    const STORM_CONST_AS float *bb = box + (size_t)(b + m) * 16;
-                    const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
-                    const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
-                    const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
-                    // excess per axis, clamped to [0, 1 m]: one instruction with the
-                    // clamp modifier; body spheres are below 1 m, so clamping cannot
-                    // turn a miss into a hit and leaves every axis of a hit exact
-                    const float ox = fminf(fmaxf(fabsf(lx) - bb[12], 0.0f), 1.0f);
-                    const float oy = fminf(fmaxf(fabsf(ly) - bb[13], 0.0f), 1.0f);
-                    const float oz = fminf(fmaxf(fabsf(lz) - bb[14], 0.0f), 1.0f);
-                    out2[m] = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
-                    lxyz[m][0] = lx;
-                    lxyz[m][1] = ly;
-                    lxyz[m][2] = lz;
-                    hit[m] = out2[m] < rs2;
-                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
-                }
-                if (__builtin_expect(any != 0, 0)) {
-#pragma unroll
-                    for (int m = 0; m < 2; ++m) {
-                        const STORM_CONST_AS float *bb = box + (size_t)(b + m) * 16;
-                        const float qin = fminf(fmaxf(fabsf(lxyz[m][0]) - bb[12],
-                                                      fmaxf(fabsf(lxyz[m][1]) - bb[13], fabsf(lxyz[m][2]) - bb[14])),
-                                                0.0f);
-                        const float pen = rs - (fast_sqrt(out2[m]) + qin);
-                        if (hit[m]) best = fmaxf(best, pen);
-                    }
-                }
-            }
-            for (; b < nbo; ++b) {
-                const STORM_CONST_AS float *bb = box + (size_t)b * 16;
-                const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));
-                const float ly = fmaf(bb[3], x, fmaf(bb[4], y, fmaf(bb[5], z, bb[10])));
-                const float lz = fmaf(bb[6], x, fmaf(bb[7], y, fmaf(bb[8], z, bb[11])));
-                const float qx = fabsf(lx) - bb[12], qy = fabsf(ly) - bb[13], qz = fabsf(lz) - bb[14];
-                const float ox = fmaxf(qx, 0.0f), oy = fmaxf(qy, 0.0f), oz = fmaxf(qz, 0.0f);
-                const float out2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
-                const bool hit = out2 < rs2;
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                    const float pen = rs - (fast_sqrt(out2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f));
-                    if (hit) best = fmaxf(best, pen);
                 }
             }
             env += best;
