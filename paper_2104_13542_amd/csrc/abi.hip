@@ -108,45 +108,94 @@ void fill_robot_consts(const storm_robot *robot, RobotDev &R)
     R.n_spheres = robot->n_spheres;
 }
 
-// Self-collision work split.  With spheres sorted by body, the partners t > s
-// of sphere s on bodies at least two further along the chain form one
-// contiguous range [t0(s), S).  The pairs, taken s-major, are cut into
-// `waves` nearly equal parts, each written as segments (s, t_begin, t_end).
-// Returns the pair count; off[w] .. off[w + 1] are wave w's segments.
+// Upper bound of the distance from the base of any body-sphere centre: the
+// frame origins move along a chain whose links have lengths at most
+// |a_k| + |d_k|, and a sphere sits |local centre| from its frame origin.
+double reach_bound(const storm_robot *robot)
+{
+    double r = 0.0, loc = 0.0;
+    for (int k = 0; k < STORM_NFRAMES; ++k) r += fabs((double)robot->dh[k][0]) + fabs((double)robot->dh[k][1]);
+    for (int s = 0; s < robot->n_spheres; ++s) {
+        const float *q = robot->spheres + 5 * s;
+        loc = fmax(loc, sqrt((double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]));
+    }
+    return r + loc;
+}
+
 }  // namespace
 
-int storm::self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
+std::vector<storm::SelfGroup> storm::self_groups(const storm_robot *robot)
 {
     const int S = robot->n_spheres;
-    std::vector<int> t0(S, S);
-    for (int s = 0; s < S; ++s)
-        for (int t = s + 1; t < S; ++t)
-            if ((int)robot->spheres[5 * t] - (int)robot->spheres[5 * s] >= 2) {
-                t0[s] = t;
-                break;
-            }
+    std::vector<SelfGroup> g;
+    for (int t = 0; t < S;) {
+        const int body = (int)robot->spheres[5 * t];
+        int n = 1;
+        while (t + n < S && n < 4 && (int)robot->spheres[5 * (t + n)] == body) ++n;
+        int s_end = 0;  // spheres are sorted by body
+        while (s_end < S && (int)robot->spheres[5 * s_end] <= body - 2) ++s_end;
+        g.push_back(SelfGroup{t, n, s_end});
+        t += n;
+    }
+    return g;
+}
+
+// Self-collision work split: the pairs (s, t) of every group, taken
+// group-major and s-major within a group (count pairs per s), are cut into
+// `waves` nearly equal parts at whole partners s; each part is written as
+// items (t_first | count << 8, group, s_begin, s_end).  Returns the pair
+// count; off[w] .. off[w + 1] are wave w's items.
+int storm::self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
+{
+    const std::vector<SelfGroup> groups = self_groups(robot);
     long long total = 0;
-    for (int s = 0; s < S; ++s) total += S - t0[s];
+    for (const SelfGroup &g : groups) total += (long long)g.count * g.s_end;
     seg.clear();
     off.assign(waves + 1, 0);
     for (int w = 0; w < waves; ++w) {
         off[w] = (int)seg.size() / 4;
         const long long k0 = total * w / waves, k1 = total * (w + 1) / waves;
         long long base = 0;
-        for (int s = 0; s < S; ++s) {
-            const long long n = S - t0[s];
-            const long long a = k0 > base ? k0 : base, b = k1 < base + n ? k1 : base + n;
+        for (int gi = 0; gi < (int)groups.size(); ++gi) {
+            const SelfGroup &g = groups[gi];
+            // partner s belongs to the wave whose range holds pair base + s * count
+            const long long c = g.count;
+            const long long sa = k0 > base ? (k0 - base + c - 1) / c : 0;
+            const long long sb = k1 > base ? (k1 - base + c - 1) / c : 0;
+            const int a = (int)(sa < g.s_end ? sa : g.s_end), b = (int)(sb < g.s_end ? sb : g.s_end);
             if (a < b) {
-                seg.push_back(s);
-                seg.push_back(t0[s] + (int)(a - base));
-                seg.push_back(t0[s] + (int)(b - base));
-                seg.push_back(0);
+                seg.push_back(g.t_first | (g.count << 8));
+                seg.push_back(gi);
+                seg.push_back(a);
+                seg.push_back(b);
             }
-            base += n;
+            base += c * g.s_end;
         }
     }
     off[waves] = (int)seg.size() / 4;
     return (int)total;
+}
+
+// Thresholds of the expanded pair test |c_s|^2 - 2 c_s.c_t + |c_t|^2 <
+// (r_s + r_t)^2 + slack, [group][s][k] for group sphere t_first + k:
+// the FP32 evaluation errs by less than 2^-24 * 10 (|c_s| + |c_t|)^2, and the
+// slack, 2^-18 (2 reach + r_s + r_t)^2, is over six times that with both
+// centres within the robot's reach.  Slots past a group's count, and
+// partners s outside its range, hold -1e30 (never a hit).
+std::vector<float> storm::self_thresholds(const storm_robot *robot, double reach)
+{
+    const int S = robot->n_spheres;
+    const std::vector<SelfGroup> groups = self_groups(robot);
+    std::vector<float> thr(groups.size() * (size_t)S * 4, -1.0e30f);
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (int s = 0; s < groups[gi].s_end; ++s)
+            for (int k = 0; k < groups[gi].count; ++k) {
+                const int t = groups[gi].t_first + k;
+                const double rs = (double)robot->spheres[5 * s + 4] + (double)robot->spheres[5 * t + 4];
+                const double span = 2.0 * reach + rs;
+                thr[(gi * S + s) * 4 + k] = (float)(rs * rs + ldexp(span * span, -18));
+            }
+    return thr;
 }
 
 namespace {
@@ -232,6 +281,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         }
     std::vector<int> seg, seg_off;
     const int n_pairs = storm::self_segments(robot, c->waves, seg, seg_off);
+    const std::vector<float> thr = storm::self_thresholds(robot, reach_bound(robot));
     const int n_seg = (int)seg.size() / 4;
 
     ProblemDev &P = c->P;
@@ -266,7 +316,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     c->R.n_pairs = n_pairs;
 
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
-    float *self_rr2, *grad_part, *cost_part, *grad, *adam;
+    float *self_thr, *grad_part, *cost_part, *grad, *adam;
     float4 *sph_obs, *env_sph, *obs_bound, *sph_local;
     int32_t *sph_body, *self_off;
     int4 *self_seg;
@@ -296,7 +346,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &adam, (size_t)2 * H * STORM_DOF));
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
-    STORM_TRY(dalloc(c, &self_rr2, (size_t)robot->n_spheres * robot->n_spheres));
+    STORM_TRY(dalloc(c, &self_thr, thr.size()));
     STORM_TRY(dalloc(c, &self_seg, (size_t)n_seg));
     STORM_TRY(dalloc(c, &self_off, seg_off.size()));
     // staging copies of the host inputs (freed at destroy with the rest)
@@ -324,6 +374,8 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         if (n_seg > 0)
             STORM_TRY(hipMemcpyAsync(self_seg, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice, s));
         STORM_TRY(hipMemcpyAsync(self_off, seg_off.data(), sizeof(int) * seg_off.size(), hipMemcpyHostToDevice, s));
+        if (!thr.empty())
+            STORM_TRY(hipMemcpyAsync(self_thr, thr.data(), sizeof(float) * thr.size(), hipMemcpyHostToDevice, s));
         P.tables = tables;
         P.halton = halton;
         P.sph_obs = sph_obs;
@@ -344,13 +396,13 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         P.adam_v = adam + (size_t)H * STORM_DOF;
         c->R.sph_local = sph_local;
         c->R.sph_body = sph_body;
-        c->R.self_rr2 = self_rr2;
+        c->R.self_thr = self_thr;
         c->R.self_seg = self_seg;
         c->R.self_off = self_off;
         STORM_TRY(storm::launch_init_tables(P, dt_raw, lim_raw, params->acc_stop, params->gamma, params->w_term,
                                             params->k_jl, params->k_vl, sig_raw, params->n_knots, obs_raw, n_obs,
-                                            sph_obs, env_sph, box_obs, obs_bound, sph_raw_d, robot->n_spheres, sph_local,
-                                            sph_body, self_rr2, s));
+                                            sph_obs, env_sph, box_obs, obs_bound, sph_raw_d, robot->n_spheres,
+                                            reach_bound(robot), sph_local, sph_body, s));
         STORM_TRY(hipStreamSynchronize(s));
     }
 #undef STORM_TRY

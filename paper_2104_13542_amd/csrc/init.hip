@@ -51,7 +51,7 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
 //   self pairs:       (r_s + r_t)^2 for every sphere pair
 __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float *box_raw, int n_bo,
                                 float4 *sph_obs, float4 *env_sph, float *box_obs, float4 *obs_bound,
-                                const float *sph_raw, int S, float4 *sph_local, int32_t *sph_body, float *self_rr2)
+                                const float *sph_raw, int S, double reach, float4 *sph_local, int32_t *sph_body)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_so) {
@@ -74,15 +74,18 @@ __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float 
     if (t < S * n_so) {
         // test record of (body sphere s, obstacle o) for the expanded form
         // |x|^2 - 2 c.x + |c|^2 < (r_s + r_o)^2: (-2c, (r_s + r_o)^2 - |c|^2 +
-        // slack).  The slack (2^-15 (1 + |c|)^2) exceeds the FP32 rounding of
-        // the expanded sum for any point within 2 m of the base, so the test
-        // has no false negatives; hits are resolved with the exact distance.
+        // slack).  The FP32 evaluation (two three-term FMA chains and the
+        // rounded record) errs by less than 2^-21 (|x| + |c| + r_s + r_o)^2;
+        // the slack is eight times that with |x| bounded by the robot's
+        // reach, so the test has no false negatives.  Hits are resolved with
+        // the exact distance.
         const int s = t / n_so, o = t - s * n_so;
         const float *r = sph_obs_raw + o * STORM_OBSTACLE_STRIDE;
         const double cx = r[1], cy = r[2], cz = r[3];
         const double c2 = cx * cx + cy * cy + cz * cz;
         const double rr = (double)sph_raw[s * 5 + 4] + (double)r[4];
-        const double slack = ldexp((1.0 + sqrt(c2)) * (1.0 + sqrt(c2)), -15);
+        const double span = reach + sqrt(c2) + rr;
+        const double slack = ldexp(span * span, -18);
         env_sph[t] = make_float4((float)(-2.0 * cx), (float)(-2.0 * cy), (float)(-2.0 * cz),
                                  (float)(rr * rr - c2 + slack));
     }
@@ -105,11 +108,6 @@ __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float 
         const float *q = sph_raw + t * 5;
         sph_local[t] = make_float4(q[1], q[2], q[3], q[4]);
         sph_body[t] = (int32_t)q[0] - 1;
-    }
-    if (t < S * S) {
-        const int a = t / S, b = t - a * S;
-        const double rs = (double)sph_raw[a * 5 + 4] + (double)sph_raw[b * 5 + 4];
-        self_rr2[t] = (float)(rs * rs);
     }
 }
 
@@ -204,8 +202,9 @@ __global__ void halton_smooth_kernel(int n_halton, int K, int H, const double *Z
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
                               int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
-                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
-                              int32_t *d_sph_body, float *d_self_rr2, hipStream_t stream)
+                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres,
+                              double reach, float4 *d_sph_local,
+                              int32_t *d_sph_body, hipStream_t stream)
 {
     (void)n_obs;
     hipLaunchKernelGGL(tables_kernel, dim3(1), dim3(kMaxH), 0, stream, P, const_cast<float *>(P.tables), d_dt_raw,
@@ -214,14 +213,14 @@ hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const 
     if (e != hipSuccess) return e;
     // d_obs_raw holds the sphere records first, then the cuboid records
     const int S = n_spheres, n_so = P.n_sph_obs, n_bo = P.n_box_obs;
-    int ng = S * S;
+    int ng = S;
     if (S * n_so > ng) ng = S * n_so;
     if (n_so + n_bo > ng) ng = n_so + n_bo;
     const int gthreads = 256;
     const int gblocks = ng > 0 ? (ng + gthreads - 1) / gthreads : 1;
     hipLaunchKernelGGL(geometry_kernel, dim3(gblocks), dim3(gthreads), 0, stream, d_obs_raw, n_so,
                        d_obs_raw + (size_t)STORM_OBSTACLE_STRIDE * n_so, n_bo, d_sph_obs, d_env_sph, d_box_obs,
-                       d_obs_bound, d_sph_raw, S, d_sph_local, d_sph_body, d_self_rr2);
+                       d_obs_bound, d_sph_raw, S, reach, d_sph_local, d_sph_body);
     e = hipGetLastError();
     if (e != hipSuccess || P.n_halton == 0) return e;
     double *Z = nullptr;

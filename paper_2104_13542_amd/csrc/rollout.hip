@@ -75,6 +75,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     float *s_pself = s_penv + W * kLanes;   // [W][64]
     float *s_terms = s_pself + W * kLanes;  // [8][64]
     float *s_sc = s_terms + 8 * kLanes;     // [7][2][64]: sin q_j, cos q_j
+    float *s_cn = s_sc + 14 * kLanes;       // [S][64]: |c|^2 of the sphere centres
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -170,22 +171,75 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     }
     __syncthreads();
 
-    // ---- C: world centres of the body spheres --------------------------------
-    const bool need_centres = (mask & (STORM_COST_SELF | STORM_COST_ENV)) != 0;
-    if (need_centres) {
-        for (int s = wave; s < S; s += W) {
-            const STORM_CONST_AS float *sl = uniform_ptr(reinterpret_cast<const float *>(R.sph_local)) + 4 * s;
-            const float *F = s_fr + uniform_ptr(R.sph_body)[s] * 12 * kLanes + lane;
+    // ---- C: world centres of the body spheres | pose | manipulability --------
+    // The last two waves evaluate the pose (Eq. 9) and manipulability
+    // (Eq. 12) terms from the frames while the others place the spheres, so
+    // that the collision phase is spread evenly over all waves.
+    constexpr int WC = W - kPoseWaves;
+    if (wave < WC) {
+        if (mask & (STORM_COST_SELF | STORM_COST_ENV)) {
+            for (int s = wave; s < S; s += WC) {
+                const STORM_CONST_AS float *sl = uniform_ptr(reinterpret_cast<const float *>(R.sph_local)) + 4 * s;
+                const float *F = s_fr + uniform_ptr(R.sph_body)[s] * 12 * kLanes + lane;
+                float cc[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                s_cen[(s * 3 + c) * kLanes + lane] =
-                    fmaf(F[(c * 3 + 0) * kLanes], sl[0],
-                         fmaf(F[(c * 3 + 1) * kLanes], sl[1], fmaf(F[(c * 3 + 2) * kLanes], sl[2], F[(9 + c) * kLanes])));
+                for (int c = 0; c < 3; ++c) {
+                    cc[c] = fmaf(F[(c * 3 + 0) * kLanes], sl[0],
+                                 fmaf(F[(c * 3 + 1) * kLanes], sl[1], fmaf(F[(c * 3 + 2) * kLanes], sl[2], F[(9 + c) * kLanes])));
+                    s_cen[(s * 3 + c) * kLanes + lane] = cc[c];
+                }
+                s_cn[s * kLanes + lane] = fmaf(cc[0], cc[0], fmaf(cc[1], cc[1], cc[2] * cc[2]));
+            }
         }
-        __syncthreads();
+    } else if (wave == W - 1) {
+        if (mask & STORM_COST_POSE) {
+            // Eq. 9: rotation error |diag(alpha_rot)(I - R_g^T R)|_F and position
+            // error |diag(alpha_pos) R_g^T (p - p_g)|.
+            const float *E = s_fr + 7 * 12 * kLanes + lane;
+            float Re[9], pe[3];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) Re[c] = E[c * kLanes];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pe[c] = E[(9 + c) * kLanes];
+            float rot2 = 0.0f, pos2 = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float m = fmaf(goal[0 * 3 + r], Re[0 * 3 + c],
+                                         fmaf(goal[1 * 3 + r], Re[1 * 3 + c], goal[2 * 3 + r] * Re[2 * 3 + c]));
+                    const float e = P.alpha_rot[r] * ((r == c ? 1.0f : 0.0f) - m);
+                    rot2 = fmaf(e, e, rot2);
+                }
+                const float l = fmaf(goal[0 * 3 + r], pe[0] - goal[9],
+                                     fmaf(goal[1 * 3 + r], pe[1] - goal[10], goal[2 * 3 + r] * (pe[2] - goal[11])));
+                const float e = P.alpha_pos[r] * l;
+                pos2 = fmaf(e, e, pos2);
+            }
+            s_terms[0 * kLanes + lane] = fast_sqrt(pos2);
+            s_terms[1 * kLanes + lane] = fast_sqrt(rot2);
+        }
+    } else {
+        if (mask & STORM_COST_MANIP) {
+            float z[kDof][3], o[kDof][3], pe[3];
+#pragma unroll
+            for (int k = 0; k < kDof; ++k) {
+                const float *F = s_fr + k * 12 * kLanes + lane;
+                z[k][0] = F[2 * kLanes];
+                z[k][1] = F[5 * kLanes];
+                z[k][2] = F[8 * kLanes];
+                o[k][0] = F[9 * kLanes];
+                o[k][1] = F[10 * kLanes];
+                o[k][2] = F[11 * kLanes];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pe[c] = s_fr[(7 * 12 + 9 + c) * kLanes + lane];
+            s_terms[5 * kLanes + lane] = manipulability(z, o, pe);
+        }
     }
+    __syncthreads();
 
-    // ---- D: collision terms, pose, manipulability -----------------------------
+    // ---- D: collision terms ---------------------------------------------------
     // Both collision loops test four records per round: the squared distance
     // of each is compared with its squared contact distance, the four lane
     // masks are OR-ed in SGPRs and the square roots (penetration depths) run
@@ -268,47 +322,55 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         }
     }
     if (mask & STORM_COST_SELF) {
+        // Pairs by groups of up to four spheres t of one body, held in
+        // registers as (-2 c_t, |c_t|^2), against their partners s streamed
+        // from LDS: per s four LDS reads, one scalar load of the four
+        // thresholds and, per pair, the expanded test |c_t|^2 - 2 c_s.c_t <
+        // threshold - |c_s|^2 (three FMAs, a subtraction, a compare).  Lanes
+        // that pass get the exact penetration (r_s + r_t) - |c_s - c_t|, at or
+        // below zero for a rounding near-miss; unused slots of a short group
+        // repeat its last sphere against a threshold no pair passes.
         const STORM_CONST_AS int32_t *segs = uniform_ptr(reinterpret_cast<const int32_t *>(R.self_seg));
         const STORM_CONST_AS int32_t *off = uniform_ptr(R.self_off);
-        const STORM_CONST_AS float *rr2 = uniform_ptr(R.self_rr2);
+        const STORM_CONST_AS float *thr = uniform_ptr(R.self_thr);
+        const STORM_CONST_AS float *sloc = uniform_ptr(reinterpret_cast<const float *>(R.sph_local));
         const int g1 = off[wave + 1];
         for (int g = off[wave]; g < g1; ++g) {
-            const int ss = segs[4 * g], t_end = segs[4 * g + 2];
-            const float cx = s_cen[(ss * 3 + 0) * kLanes + lane];
-            const float cy = s_cen[(ss * 3 + 1) * kLanes + lane];
-            const float cz = s_cen[(ss * 3 + 2) * kLanes + lane];
-            const STORM_CONST_AS float *row = rr2 + (size_t)ss * S;
-            int t = segs[4 * g + 1];
-            for (; t + 4 <= t_end; t += 4) {
-                float d2[4];
+            const int code = segs[4 * g], grp = segs[4 * g + 1], s_end = segs[4 * g + 3];
+            const int t_first = code & 255, count = code >> 8;
+            float mx[4], my[4], mz[4], nt[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int t = t_first + (k < count ? k : count - 1);
+                mx[k] = -2.0f * s_cen[(t * 3 + 0) * kLanes + lane];
+                my[k] = -2.0f * s_cen[(t * 3 + 1) * kLanes + lane];
+                mz[k] = -2.0f * s_cen[(t * 3 + 2) * kLanes + lane];
+                nt[k] = s_cn[t * kLanes + lane];
+            }
+            const STORM_CONST_AS float *tg = thr + (size_t)grp * S * 4;
+            for (int sp = segs[4 * g + 2]; sp < s_end; ++sp) {
+                const float cx = s_cen[(sp * 3 + 0) * kLanes + lane];
+                const float cy = s_cen[(sp * 3 + 1) * kLanes + lane];
+                const float cz = s_cen[(sp * 3 + 2) * kLanes + lane];
+                const float ns = s_cn[sp * kLanes + lane];
+                const STORM_CONST_AS float *th = tg + 4 * sp;
                 bool hit[4];
                 uint64_t any = 0;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const float dx = cx - s_cen[((t + m) * 3 + 0) * kLanes + lane];
-                    const float dy = cy - s_cen[((t + m) * 3 + 1) * kLanes + lane];
-                    const float dz = cz - s_cen[((t + m) * 3 + 2) * kLanes + lane];
-                    d2[m] = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    hit[m] = d2[m] < row[t + m];
-                    any |= __builtin_amdgcn_ballot_w64(hit[m]);
+                for (int k = 0; k < 4; ++k) {
+                    const float a = fmaf(cx, mx[k], fmaf(cy, my[k], fmaf(cz, mz[k], nt[k])));
+                    hit[k] = a < th[k] - ns;
+                    any |= __builtin_amdgcn_ballot_w64(hit[k]);
                 }
                 if (__builtin_expect(any != 0, 0)) {
+                    const float rs = sloc[4 * sp + 3];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const float pen = fast_sqrt(row[t + m]) - fast_sqrt(d2[m]);
-                        if (hit[m]) selfpen = fmaxf(selfpen, pen);
+                    for (int k = 0; k < 4; ++k) {
+                        const int t = t_first + (k < count ? k : count - 1);
+                        const float dx = fmaf(0.5f, mx[k], cx), dy = fmaf(0.5f, my[k], cy), dz = fmaf(0.5f, mz[k], cz);
+                        const float pen = (rs + sloc[4 * t + 3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                        if (hit[k]) selfpen = fmaxf(selfpen, pen);
                     }
-                }
-            }
-            for (; t < t_end; ++t) {
-                const float dx = cx - s_cen[(t * 3 + 0) * kLanes + lane];
-                const float dy = cy - s_cen[(t * 3 + 1) * kLanes + lane];
-                const float dz = cz - s_cen[(t * 3 + 2) * kLanes + lane];
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const bool hit = d2 < row[t];
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                    const float pen = fast_sqrt(row[t]) - fast_sqrt(d2);
-                    if (hit) selfpen = fmaxf(selfpen, pen);
                 }
             }
         }
@@ -316,49 +378,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     s_penv[wave * kLanes + lane] = env;
     s_pself[wave * kLanes + lane] = selfpen;
 
-    if (wave == W - 1 && (mask & STORM_COST_POSE)) {
-        // Eq. 9: rotation error |diag(alpha_rot)(I - R_g^T R)|_F and position
-        // error |diag(alpha_pos) R_g^T (p - p_g)|.
-        const float *E = s_fr + 7 * 12 * kLanes + lane;
-        float Re[9], pe[3];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) Re[c] = E[c * kLanes];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) pe[c] = E[(9 + c) * kLanes];
-        float rot2 = 0.0f, pos2 = 0.0f;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float m = fmaf(goal[0 * 3 + r], Re[0 * 3 + c],
-                                     fmaf(goal[1 * 3 + r], Re[1 * 3 + c], goal[2 * 3 + r] * Re[2 * 3 + c]));
-                const float e = P.alpha_rot[r] * ((r == c ? 1.0f : 0.0f) - m);
-                rot2 = fmaf(e, e, rot2);
-            }
-            const float l = fmaf(goal[0 * 3 + r], pe[0] - goal[9],
-                                 fmaf(goal[1 * 3 + r], pe[1] - goal[10], goal[2 * 3 + r] * (pe[2] - goal[11])));
-            const float e = P.alpha_pos[r] * l;
-            pos2 = fmaf(e, e, pos2);
-        }
-        s_terms[0 * kLanes + lane] = fast_sqrt(pos2);
-        s_terms[1 * kLanes + lane] = fast_sqrt(rot2);
-    }
-    if (wave == W - 2 && (mask & STORM_COST_MANIP)) {
-        float z[kDof][3], o[kDof][3], pe[3];
-#pragma unroll
-        for (int k = 0; k < kDof; ++k) {
-            const float *F = s_fr + k * 12 * kLanes + lane;
-            z[k][0] = F[2 * kLanes];
-            z[k][1] = F[5 * kLanes];
-            z[k][2] = F[8 * kLanes];
-            o[k][0] = F[9 * kLanes];
-            o[k][1] = F[10 * kLanes];
-            o[k][2] = F[11 * kLanes];
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) pe[c] = s_fr[(7 * 12 + 9 + c) * kLanes + lane];
-        s_terms[5 * kLanes + lane] = manipulability(z, o, pe);
-    }
     __syncthreads();
 
     // ---- E: running cost (Eq. 15) and horizon cost (Eq. 2) ------------------
@@ -447,7 +466,7 @@ __global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const Problem
 
 size_t rollout_lds_bytes(int S, int W)
 {
-    return (size_t)(8 + 2 * kDof + 96 + 3 * S + 2 * W + kTerms + 2 * kDof) * kLanes * sizeof(float);
+    return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof) * kLanes * sizeof(float);
 }
 
 }  // namespace

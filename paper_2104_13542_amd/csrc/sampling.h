@@ -40,14 +40,42 @@ __device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float &zc, 
     zs = r * s;
 }
 
-// Inclusive prefix sum over the lanes of one particle (lanes p*H .. p*H+H-1),
-// Kogge-Stone with wavefront shuffles; h = step index of this lane.
+// Lane move through DPP: lane l receives x from the lane that `kCtrl` names
+// (row shifts, row broadcasts); lanes whose source is outside the row, or
+// in a row that kRowMask leaves out, receive 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_or_zero(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, kRowMask, 0xf, true));
+}
+
+// Inclusive prefix sum over the lanes of one particle (lanes p*H .. p*H+H-1;
+// h = step index of this lane), without LDS traffic: a Kogge-Stone scan
+// inside each 16-lane row (DPP row shifts by 1, 2, 4, 8, each term taken
+// only from the lane's own segment and row), then the two row broadcasts
+// that carry the sums of rows 0 and 2 into rows 1 and 3, and of rows 0-1
+// into rows 2-3, each taken only by lanes whose particle began before the
+// source lane.  Segments of the padding lanes past the last particle are
+// scanned the same way.
 __device__ __forceinline__ float segmented_scan(float x, int h, int H)
 {
-    for (int off = 1; off < H; off <<= 1) {
-        const float y = __shfl_up(x, (unsigned)off, kLanes);
-        if (h >= off) x += y;
-    }
+    (void)H;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int in_row = lane & 15;
+    const int reach = h < in_row ? h : in_row;  // lanes back to the row or segment start
+    float y;
+    y = dpp_or_zero<0x111, 0xf>(x);  // row_shr:1
+    x += reach >= 1 ? y : 0.0f;
+    y = dpp_or_zero<0x112, 0xf>(x);  // row_shr:2
+    x += reach >= 2 ? y : 0.0f;
+    y = dpp_or_zero<0x114, 0xf>(x);  // row_shr:4
+    x += reach >= 4 ? y : 0.0f;
+    y = dpp_or_zero<0x118, 0xf>(x);  // row_shr:8
+    x += reach >= 8 ? y : 0.0f;
+    y = dpp_or_zero<0x142, 0xa>(x);  // row_bcast:15 -> rows 1, 3
+    x += h > in_row ? y : 0.0f;
+    y = dpp_or_zero<0x143, 0xc>(x);  // row_bcast:31 -> rows 2, 3
+    x += (lane >= 32 && h > lane - 32) ? y : 0.0f;
     return x;
 }
 

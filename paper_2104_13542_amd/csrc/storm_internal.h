@@ -15,6 +15,9 @@ constexpr int kDof = STORM_DOF;
 constexpr int kFrames = STORM_NFRAMES;
 constexpr int kTerms = STORM_NTERMS;
 constexpr int kLanes = 64;  // CDNA wavefront width
+// waves at the end of a rollout workgroup that evaluate the pose and
+// manipulability terms while the others place the body spheres
+constexpr int kPoseWaves = 2;
 constexpr int kMaxH = STORM_MAX_HORIZON;
 
 // Offsets (in floats) inside the per-problem table block built at init.
@@ -62,8 +65,8 @@ struct RobotDev {
     int32_t n_spheres, n_pairs, pad0, pad1;
     const float4 *sph_local;  // [S] body-frame centre (x, y, z), radius
     const int32_t *sph_body;  // [S] frame index 0..7 the sphere is attached to
-    const float *self_rr2;    // [S][S] (r_s + r_t)^2
-    const int4 *self_seg;     // self-collision segments (s, t_begin, t_end, 0): pairs (s, t), bodies >= 2 apart
+    const float *self_thr;    // [groups][S][4] threshold of the expanded pair test (group spheres x partner s)
+    const int4 *self_seg;     // self-collision items (t_first | count << 8, group, s_begin, s_end)
     const int32_t *self_off;  // [W + 1] segment range of each wave of the rollout workgroup
 };
 
@@ -101,8 +104,9 @@ struct StepOut {
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
                               int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
-                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
-                              int32_t *d_sph_body, float *d_self_rr2, hipStream_t stream);
+                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres,
+                              double reach, float4 *d_sph_local,
+                              int32_t *d_sph_body, hipStream_t stream);
 hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,
                           const float *noise, const StepOut &out, int waves, hipStream_t stream);
 // Raise the dynamic-LDS limit of the rollout kernels to what the largest
@@ -127,7 +131,15 @@ hipError_t launch_fk(const RobotDev &R, const float *q, int n, float *pose, floa
 // Self-collision work split of the robot's sphere pairs over `waves`
 // wavefronts: segments (s, t_begin, t_end, 0) and per-wave offsets
 // off[0..waves]; returns the pair count.
+// Self-collision groups: the spheres of one body in runs of up to four,
+// (t_first, count), whose partners are the spheres s < s_end on bodies at
+// least two earlier in the chain.
+struct SelfGroup {
+    int t_first, count, s_end;
+};
+std::vector<SelfGroup> self_groups(const storm_robot *robot);
 int self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off);
+std::vector<float> self_thresholds(const storm_robot *robot, double reach);
 
 }  // namespace storm
 

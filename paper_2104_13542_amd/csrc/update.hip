@@ -11,13 +11,20 @@
 // seven joints need no synchronisation with each other; every workgroup
 // recomputes min C and the weights of all particles (N exponentials).  The
 // joint's H columns are read by rows of threads, row r taking particles r,
-// r + R, ... with eight loads in flight per thread.  When few weights are not
-// exactly zero (beta small against the spread of C) only those particles are
-// gathered, from a list compacted in ascending order.  The variance about the
-// new mean comes from the moments about the old one,
-// sum w (d - delta)^2 = S2/S0 - 2 delta S1/S0 + delta^2, in one pass.  Every
-// sum has a fixed order, so results are bitwise reproducible; there is no
-// floating-point atomic and no synchronisation between workgroups.
+// r + R, ...  Three ways to gather them:
+//   registers  (N <= 32 R): every thread loads its up to 32 controls at the
+//              start, together with the costs, so the only global-memory
+//              latency on the path is the first one;
+//   list       (at most 4096 weights not exactly zero, beta small against the
+//              spread of C): only those particles, from a list compacted in
+//              ascending order;
+//   dense      otherwise: all particles, weights staged in LDS by chunks,
+//              eight loads in flight per thread.
+// The variance about the new mean comes from the moments about the old one,
+// sum w (d - delta)^2 = S2/S0 - 2 delta S1/S0 + delta^2, in one pass.  Wave
+// reductions use DPP lane moves; every sum has a fixed order, so results are
+// bitwise reproducible; there is no floating-point atomic and no
+// synchronisation between workgroups.
 #include "storm_internal.h"
 
 namespace storm {
@@ -28,186 +35,307 @@ constexpr int kWaves = kThreads / kLanes;
 constexpr int kList = 4096;   // capacity of the nonzero-weight list
 constexpr int kChunk = 8192;  // weights staged in LDS per chunk (dense path)
 constexpr int kUnroll = 8;    // independent loads in flight per thread
+constexpr int kRegU = 32;     // controls per thread held in registers (register path)
+
+// Full-wave reductions through DPP lane moves (quad permutes, half-row and
+// row mirrors, then the row broadcasts that carry each row's result into the
+// next); lane 63, which every step feeds, holds the result, read back into
+// an SGPR.  The order of the operations is fixed.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_move(int x)
+{
+    return __builtin_amdgcn_mov_dpp(x, kCtrl, kRowMask, 0xf, false);
+}
+
+// Two wave sums at once (the two DPP chains interleave).
+__device__ __forceinline__ void wave_sum2(float &x, float &y)
+{
+    x += __int_as_float(dpp_move<0xb1, 0xf>(__float_as_int(x)));
+    y += __int_as_float(dpp_move<0xb1, 0xf>(__float_as_int(y)));
+    x += __int_as_float(dpp_move<0x4e, 0xf>(__float_as_int(x)));
+    y += __int_as_float(dpp_move<0x4e, 0xf>(__float_as_int(y)));
+    x += __int_as_float(dpp_move<0x141, 0xf>(__float_as_int(x)));
+    y += __int_as_float(dpp_move<0x141, 0xf>(__float_as_int(y)));
+    x += __int_as_float(dpp_move<0x140, 0xf>(__float_as_int(x)));
+    y += __int_as_float(dpp_move<0x140, 0xf>(__float_as_int(y)));
+    x += __int_as_float(dpp_move<0x142, 0xa>(__float_as_int(x)));
+    y += __int_as_float(dpp_move<0x142, 0xa>(__float_as_int(y)));
+    x += __int_as_float(dpp_move<0x143, 0xc>(__float_as_int(x)));
+    y += __int_as_float(dpp_move<0x143, 0xc>(__float_as_int(y)));
+    x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 63));
+}
 
 __device__ __forceinline__ float wave_sum(float x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kLanes);
-    return x;
+    x += __int_as_float(dpp_move<0xb1, 0xf>(__float_as_int(x)));
+    x += __int_as_float(dpp_move<0x4e, 0xf>(__float_as_int(x)));
+    x += __int_as_float(dpp_move<0x141, 0xf>(__float_as_int(x)));
+    x += __int_as_float(dpp_move<0x140, 0xf>(__float_as_int(x)));
+    x += __int_as_float(dpp_move<0x142, 0xa>(__float_as_int(x)));
+    x += __int_as_float(dpp_move<0x143, 0xc>(__float_as_int(x)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
+
+// IEEE bits mapped so that signed-integer order is float order (negative
+// values have their magnitude bits flipped); the map is its own inverse.
+__device__ __forceinline__ int ordered(int b) { return b ^ (int)((uint32_t)(b >> 31) >> 1); }
 
 __device__ __forceinline__ float wave_min(float x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off, kLanes));
-    return x;
+    int b = ordered(__float_as_int(x));
+    b = min(b, dpp_move<0xb1, 0xf>(b));
+    b = min(b, dpp_move<0x4e, 0xf>(b));
+    b = min(b, dpp_move<0x141, 0xf>(b));
+    b = min(b, dpp_move<0x140, 0xf>(b));
+    b = min(b, dpp_move<0x142, 0xa>(b));
+    b = min(b, dpp_move<0x143, 0xc>(b));
+    return __int_as_float(ordered(__builtin_amdgcn_readlane(b, 63)));
+}
+
+// Minimum of v over the workgroup (all threads get it).
+__device__ __forceinline__ float block_min(float v, float *s_wave, int lane, int wave)
+{
+    v = wave_min(v);
+    if (lane == 0) s_wave[wave] = v;
+    __syncthreads();
+    float m = s_wave[0];
+    for (int k = 1; k < kWaves; ++k) m = fminf(m, s_wave[k]);
+    __syncthreads();
+    return m;
 }
 
 __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, float *__restrict__ mean_out,
                                              float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift)
 {
-    __shared__ float s_buf[kChunk];  // sparse: indices, then weights; dense: a chunk of weights
+    __shared__ float s_buf[kChunk];  // register path: weights; list: indices, then weights; dense: a chunk
     __shared__ float s_red[2 * kThreads];
     __shared__ float s_wave[kWaves];
+    __shared__ float s_wsum[kWaves];
     __shared__ int s_count[kWaves];
     __shared__ float s_mu[kMaxH];
     __shared__ float s_var[kMaxH];
+    __shared__ float s_mold[kMaxH];
 
     const int t = threadIdx.x;
-    const int lane = t & (kLanes - 1), wave = t / kLanes;
+    const int lane = t & (kLanes - 1), wave = __builtin_amdgcn_readfirstlane(t / kLanes);
     const int N = P.N, H = P.H;
     const float beta = P.beta;
     const float *__restrict__ C = P.C;
     int *s_idx = reinterpret_cast<int *>(s_buf);
     float *s_wl = s_buf + kList;
 
-    // min C over all particles, and whether any C is not finite
-    float cmin = INFINITY;
-    int nonfinite = 0;
-    for (int i = t; i < N; i += kThreads) {
-        const float c = C[i];
-        nonfinite |= !isfinite(c);
-        cmin = fminf(cmin, c);
-    }
-    cmin = wave_min(cmin);
-    const int any_nonfinite = __syncthreads_or(nonfinite);
-    if (lane == 0) s_wave[wave] = cmin;
-    __syncthreads();
-    cmin = s_wave[0];
-    for (int k = 1; k < kWaves; ++k) cmin = fminf(cmin, s_wave[k]);
-    __syncthreads();
-
-    // weight sum (per thread in stride order, per wave, waves in order) and
-    // the list of nonzero weights in ascending particle order
-    float sw = 0.0f;
-    int base = 0;
-    for (int c0 = 0; c0 < N; c0 += kThreads) {
-        const int i = c0 + t;
-        const float w = i < N ? expf(-(C[i] - cmin) / beta) : 0.0f;
-        sw += w;
-        const bool nz = w > 0.0f;
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(nz);
-        const int before = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) s_count[wave] = __builtin_popcountll(bal);
-        __syncthreads();
-        int off = 0, total = 0;
-        for (int k = 0; k < kWaves; ++k) {
-            const int c = s_count[k];
-            off += k < wave ? c : 0;
-            total += c;
-        }
-        const int pos = base + off + before;
-        if (nz && pos < kList) {
-            s_idx[pos] = i;
-            s_wl[pos] = w;
-        }
-        base += total;
-        __syncthreads();
-    }
-    sw = wave_sum(sw);
-    if (lane == 0) s_wave[wave] = sw;
-    __syncthreads();
-    float S0 = 0.0f;
-    for (int k = 0; k < kWaves; ++k) S0 += s_wave[k];
-    const bool ok = !any_nonfinite && S0 > 0.0f && isfinite(S0);
-    const int M = base;
-
-    // moments of d = u - mu over the particles, per step h of joint j
+    // thread (r, h): step h of particles r, r + rows, ...
     const int rows = kThreads / H;
     const int r = t / H, h = t - r * H;
-    const bool act = r < rows && ok;
-    const float mu = r < rows ? P.mean[h * kDof + j] : 0.0f;
+    const bool in_rows = r < rows;
     const float *__restrict__ U = P.u + (size_t)j * N * H + h;
-    float a1[kUnroll], a2[kUnroll];
+    const bool regs = N <= kRegU * rows && N <= 2 * kThreads;
+
+    // register path: the costs, then every control load, all in flight at
+    // once (indices clamped into the array; the surplus values are unused)
+    float c0 = INFINITY, c1 = INFINITY;
+    float uu[kRegU];
+    if (regs) {
+        if (t < N) c0 = C[t];
+        if (t + kThreads < N) c1 = C[t + kThreads];
 #pragma unroll
-    for (int m = 0; m < kUnroll; ++m) a1[m] = a2[m] = 0.0f;
-    if (M <= kList) {
-        if (act) {
-            int k = r;
-            for (; k + (kUnroll - 1) * rows < M; k += kUnroll * rows) {
-                float d[kUnroll];
+        for (int k = 0; k < kRegU; ++k) uu[k] = U[(size_t)min(r + k * rows, N - 1) * H];
+    }
+    if (t < H) s_mold[t] = P.mean[t * kDof + j];
+    const float mu = in_rows ? P.mean[h * kDof + j] : 0.0f;
+
+    float S0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    int any_nonfinite = 0;
+    bool ok = false;
+    if (regs) {
+        // min C and the non-finite flag in one exchange, then the weights
+        // and their sum in a second (separate LDS slots: no third barrier)
+        const bool bad = (t < N && !isfinite(c0)) || (t + kThreads < N && !isfinite(c1));
+        const uint64_t bad_lanes = __builtin_amdgcn_ballot_w64(bad);
+        const float wmin = wave_min(fminf(c0, c1));
+        if (lane == 0) {
+            s_wave[wave] = wmin;
+            s_count[wave] = bad_lanes != 0;
+        }
+        __syncthreads();
+        float cmin = s_wave[0];
+        any_nonfinite = s_count[0];
+        for (int k = 1; k < kWaves; ++k) {
+            cmin = fminf(cmin, s_wave[k]);
+            any_nonfinite |= s_count[k];
+        }
+        const float w0 = t < N ? expf(-(c0 - cmin) / beta) : 0.0f;
+        const float w1 = t + kThreads < N ? expf(-(c1 - cmin) / beta) : 0.0f;
+        s_buf[t] = w0;
+        s_buf[t + kThreads] = w1;
+        const float sw = wave_sum(w0 + w1);
+        if (lane == 0) s_wsum[wave] = sw;
+        __syncthreads();
+        for (int k = 0; k < kWaves; ++k) S0 += s_wsum[k];
+        ok = !any_nonfinite && S0 > 0.0f && isfinite(S0);
+        // straight-line over the 32 slots (weight 0 past the last particle)
+        // so that every LDS read is in flight before the first use
+        float a1[4] = {0.0f, 0.0f, 0.0f, 0.0f}, a2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (in_rows && ok) {
 #pragma unroll
-                for (int m = 0; m < kUnroll; ++m) d[m] = U[(size_t)s_idx[k + m * rows] * H] - mu;
-#pragma unroll
-                for (int m = 0; m < kUnroll; ++m) {
-                    const float wd = s_wl[k + m * rows] * d[m];
-                    a1[m] += wd;
-                    a2[m] = fmaf(wd, d[m], a2[m]);
-                }
-            }
-            for (; k < M; k += rows) {
-                const float d = U[(size_t)s_idx[k] * H] - mu;
-                const float wd = s_wl[k] * d;
-                a1[0] += wd;
-                a2[0] = fmaf(wd, d, a2[0]);
+            for (int k = 0; k < kRegU; ++k) {
+                const int i = r + k * rows;
+                const float w = s_buf[min(i, N - 1)];
+                const float d = uu[k] - mu;
+                const float wd = i < N ? w * d : 0.0f;
+                a1[k & 3] += wd;
+                a2[k & 3] = fmaf(wd, d, a2[k & 3]);
             }
         }
+        x1 = (a1[0] + a1[1]) + (a1[2] + a1[3]);
+        x2 = (a2[0] + a2[1]) + (a2[2] + a2[3]);
     } else {
-        for (int c0 = 0; c0 < N; c0 += kChunk) {
-            const int nc = min(kChunk, N - c0);
+        // min C over all particles, and whether any C is not finite
+        float cmin = INFINITY;
+        int nonfinite = 0;
+        for (int i = t; i < N; i += kThreads) {
+            const float c = C[i];
+            nonfinite |= !isfinite(c);
+            cmin = fminf(cmin, c);
+        }
+        any_nonfinite = __syncthreads_or(nonfinite);
+        cmin = block_min(cmin, s_wave, lane, wave);
+
+        // weight sum (per thread in stride order, per wave, waves in order)
+        // and the list of nonzero weights in ascending particle order
+        float sw = 0.0f;
+        int base = 0;
+        for (int c0 = 0; c0 < N; c0 += kThreads) {
+            const int i = c0 + t;
+            const float w = i < N ? expf(-(C[i] - cmin) / beta) : 0.0f;
+            sw += w;
+            const bool nz = w > 0.0f;
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(nz);
+            const int before = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) s_count[wave] = __builtin_popcountll(bal);
             __syncthreads();
-            for (int k = t; k < nc; k += kThreads) s_buf[k] = expf(-(C[c0 + k] - cmin) / beta);
+            int off = 0, total = 0;
+            for (int k = 0; k < kWaves; ++k) {
+                const int c = s_count[k];
+                off += k < wave ? c : 0;
+                total += c;
+            }
+            const int pos = base + off + before;
+            if (nz && pos < kList) {
+                s_idx[pos] = i;
+                s_wl[pos] = w;
+            }
+            base += total;
             __syncthreads();
-            if (!act) continue;
-            int k = r;
-            for (; k + (kUnroll - 1) * rows < nc; k += kUnroll * rows) {
-                float d[kUnroll];
+        }
+        sw = wave_sum(sw);
+        if (lane == 0) s_wave[wave] = sw;
+        __syncthreads();
+        for (int k = 0; k < kWaves; ++k) S0 += s_wave[k];
+        ok = !any_nonfinite && S0 > 0.0f && isfinite(S0);
+        const int M = base;
+
+        // moments of d = u - mu over the particles, per step h of joint j
+        const bool act = in_rows && ok;
+        float a1[kUnroll], a2[kUnroll];
 #pragma unroll
-                for (int m = 0; m < kUnroll; ++m) d[m] = U[(size_t)(c0 + k + m * rows) * H] - mu;
+        for (int m = 0; m < kUnroll; ++m) a1[m] = a2[m] = 0.0f;
+        if (M <= kList) {
+            if (act) {
+                int k = r;
+                for (; k + (kUnroll - 1) * rows < M; k += kUnroll * rows) {
+                    float d[kUnroll];
 #pragma unroll
-                for (int m = 0; m < kUnroll; ++m) {
-                    const float wd = s_buf[k + m * rows] * d[m];
-                    a1[m] += wd;
-                    a2[m] = fmaf(wd, d[m], a2[m]);
+                    for (int m = 0; m < kUnroll; ++m) d[m] = U[(size_t)s_idx[k + m * rows] * H] - mu;
+#pragma unroll
+                    for (int m = 0; m < kUnroll; ++m) {
+                        const float wd = s_wl[k + m * rows] * d[m];
+                        a1[m] += wd;
+                        a2[m] = fmaf(wd, d[m], a2[m]);
+                    }
+                }
+                for (; k < M; k += rows) {
+                    const float d = U[(size_t)s_idx[k] * H] - mu;
+                    const float wd = s_wl[k] * d;
+                    a1[0] += wd;
+                    a2[0] = fmaf(wd, d, a2[0]);
                 }
             }
-            for (; k < nc; k += rows) {
-                const float d = U[(size_t)(c0 + k) * H] - mu;
-                const float wd = s_buf[k] * d;
-                a1[0] += wd;
-                a2[0] = fmaf(wd, d, a2[0]);
+        } else {
+            for (int c0 = 0; c0 < N; c0 += kChunk) {
+                const int nc = min(kChunk, N - c0);
+                __syncthreads();
+                for (int k = t; k < nc; k += kThreads) s_buf[k] = expf(-(C[c0 + k] - cmin) / beta);
+                __syncthreads();
+                if (!act) continue;
+                int k = r;
+                for (; k + (kUnroll - 1) * rows < nc; k += kUnroll * rows) {
+                    float d[kUnroll];
+#pragma unroll
+                    for (int m = 0; m < kUnroll; ++m) d[m] = U[(size_t)(c0 + k + m * rows) * H] - mu;
+#pragma unroll
+                    for (int m = 0; m < kUnroll; ++m) {
+                        const float wd = s_buf[k + m * rows] * d[m];
+                        a1[m] += wd;
+                        a2[m] = fmaf(wd, d[m], a2[m]);
+                    }
+                }
+                for (; k < nc; k += rows) {
+                    const float d = U[(size_t)(c0 + k) * H] - mu;
+                    const float wd = s_buf[k] * d;
+                    a1[0] += wd;
+                    a2[0] = fmaf(wd, d, a2[0]);
+                }
             }
         }
-    }
-    float x1 = 0.0f, x2 = 0.0f;
 #pragma unroll
-    for (int m = 0; m < kUnroll; ++m) {
-        x1 += a1[m];
-        x2 += a2[m];
+        for (int m = 0; m < kUnroll; ++m) {
+            x1 += a1[m];
+            x2 += a2[m];
+        }
     }
+
+    // per step h: S1, S2 over the rows (one wave per step, lanes over rows,
+    // then a wave sum), the new mean and the variance about it
     s_red[t] = x1;
     s_red[kThreads + t] = x2;
     __syncthreads();
-    if (t < H) {
+    const float inv_S0 = 1.0f / S0;
+    for (int hh = wave; hh < H; hh += kWaves) {
         float s1 = 0.0f, s2 = 0.0f;
-        for (int k = 0; k < rows; ++k) {
-            s1 += s_red[k * H + t];
-            s2 += s_red[kThreads + k * H + t];
+        for (int l = lane; l < rows; l += kLanes) {
+            s1 += s_red[l * H + hh];
+            s2 += s_red[kThreads + l * H + hh];
         }
-        const float muo = P.mean[t * kDof + j];
-        const float m1 = s1 / S0, m2 = s2 / S0;
-        const float delta = P.alpha_mu * m1;
-        s_mu[t] = ok ? muo + delta : muo;
-        s_var[t] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
+        wave_sum2(s1, s2);
+        if (lane == 0) {
+            const float muo = s_mold[hh];
+            const float m1 = s1 * inv_S0, m2 = s2 * inv_S0;
+            const float delta = P.alpha_mu * m1;
+            s_mu[hh] = ok ? muo + delta : muo;
+            s_var[hh] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
+        }
     }
     __syncthreads();
-    if (t == 0) {
-        float acc = 0.0f;
-        for (int k = 0; k < H; ++k) acc += s_var[k];
-        const float old = P.sigma2[j];
-        float s2n = old;
-        if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
-        P.sigma2[j] = s2n;
-        if (sigma2_out) sigma2_out[j] = s2n;
-        cmd[j] = s_mu[0];
-        if (j == 0) {
-            *P.step = *P.step + 1u;
-            if (!ok) atomicOr(P.status, any_nonfinite ? STORM_FLAG_NONFINITE_COST : STORM_FLAG_ZERO_WEIGHT);
+    if (wave == 0) {
+        const float acc = wave_sum(lane < H ? s_var[lane] : 0.0f);
+        if (lane == 0) {
+            const float old = P.sigma2[j];
+            float s2n = old;
+            if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
+            P.sigma2[j] = s2n;
+            if (sigma2_out) sigma2_out[j] = s2n;
+            cmd[j] = s_mu[0];
+            if (j == 0) {
+                *P.step = *P.step + 1u;
+                if (!ok) atomicOr(P.status, any_nonfinite ? STORM_FLAG_NONFINITE_COST : STORM_FLAG_ZERO_WEIGHT);
+            }
         }
-    }
-    if (t < H) {
-        if (mean_out) mean_out[t * kDof + j] = s_mu[t];
-        P.mean[t * kDof + j] = shift ? (t + 1 < H ? s_mu[t + 1] : 0.0f) : s_mu[t];
+        if (lane < H) {
+            if (mean_out) mean_out[lane * kDof + j] = s_mu[lane];
+            P.mean[lane * kDof + j] = shift ? (lane + 1 < H ? s_mu[lane + 1] : 0.0f) : s_mu[lane];
+        }
     }
 }
 

@@ -317,10 +317,13 @@ def test_graph_replays_match_eager(iterations):
         graphed.close()
 
 
-@pytest.mark.parametrize("N,H,beta", [(5000, 16, 1e6), (700, 30, 1e6), (3000, 8, 50.0)])
+@pytest.mark.parametrize("N,H,beta", [(5000, 16, 1e6), (700, 30, 1e6), (3000, 8, 50.0), (2500, 30, 0.1),
+                                      (1088, 30, 1e6), (512, 64, 0.1), (2048, 16, 1e6)])
 def test_update_dense_and_sparse_paths(oracle_lib, N, H, beta):
-    """The update gathers only particles with nonzero weight when they fit
-    the compaction list (4096) and streams every particle otherwise; both
+    """The update holds the controls in registers when every thread needs at
+    most 32 of them (N <= 32 floor(1024 / H), N <= 2048: the last three cases
+    sit on that edge), else gathers only particles with nonzero weight when
+    they fit the compaction list (4096), else streams every particle; each
     must equal the oracle's update on the same costs and controls."""
     prob = inputs.config1(8)
     prob.params.n_particles = N
