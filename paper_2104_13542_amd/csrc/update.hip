@@ -136,13 +136,13 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     // once (indices clamped into the array; the surplus values are unused)
     float c0 = INFINITY, c1 = INFINITY;
     float uu[kRegU];
+    const int nk = (N + rows - 1) / rows;  // slots in use, <= kRegU on this path
     if (regs) {
         if (t < N) c0 = C[t];
         if (t + kThreads < N) c1 = C[t + kThreads];
 #pragma unroll
         for (int k = 0; k < kRegU; ++k) uu[k] = U[(size_t)min(r + k * rows, N - 1) * H];
     }
-    if (t < H) s_mold[t] = P.mean[t * kDof + j];
     const float mu = in_rows ? P.mean[h * kDof + j] : 0.0f;
 
     float S0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
@@ -300,6 +300,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     // then a wave sum), the new mean and the variance about it
     s_red[t] = x1;
     s_red[kThreads + t] = x2;
+    if (r == 0) s_mold[h] = mu;  // stored late: an early store would wait for every load in flight
     __syncthreads();
     const float inv_S0 = 1.0f / S0;
     for (int hh = wave; hh < H; hh += kWaves) {
