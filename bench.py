@@ -209,6 +209,199 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
     }
 
 
+def differentiable_bench(steps, latency_steps, warmup):
+    """Differentiable form on the N=1024, H=30 workload (pose + joint-limit
+    costs): a control step with 3 Adam refinement steps of the mean (one
+    captured graph) against the plain MPPI step, and the adjoint gradient
+    against the same gradient by central differences through plain rollout
+    launches (2 H 7 of them)."""
+    import numpy as np
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    prob = inputs.config4(0)
+    p = prob.params
+    N, H = p.n_particles, p.horizon
+    r = storm.Rollout(prob)
+    qg = torch.tensor(prob.q_goal, dtype=torch.float32, device="cuda").reshape(1, 7)
+    goal = storm.fk(qg)[0][0].contiguous()
+    x0 = r.x0.clone()
+    cmd = torch.zeros(7, dtype=torch.float32, device="cuda")
+    g_plain = r.graph(x0, goal, cmd, iterations=1, shift=True)
+    g_ref = r.graph(x0, goal, cmd, iterations=1, shift=True, refine_iters=3, lr=0.05)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    cmd_host = torch.empty(7, dtype=torch.float32, pin_memory=True)
+
+    def timed(g):
+        for _ in range(warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            g.launch()
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / steps
+        lat = []
+        for _ in range(latency_steps):
+            t0 = time.perf_counter()
+            g.launch()
+            cmd_host.copy_(cmd, non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        return ms, np.array(lat)
+
+    plain_ms, plain_lat = timed(g_plain)
+    ref_ms, ref_lat = timed(g_ref)
+    g_plain.close()
+    g_ref.close()
+
+    # the gradient alone: adjoint launch + reduction, against central
+    # differences with one plain rollout launch per perturbed mean
+    r.step(goal, x0=x0)
+    mean = torch.zeros((H, 7), dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        r.grad(mean, goal, x0=x0)
+    torch.cuda.synchronize()
+    K = max(20, steps // 5)
+    start.record()
+    for _ in range(K):
+        r.grad(mean, goal, x0=x0)
+    end.record()
+    torch.cuda.synchronize()
+    grad_us = start.elapsed_time(end) / K * 1e3
+    n_fd = 2 * H * 7
+    start.record()
+    for _ in range(n_fd):
+        r.step(goal, x0=x0)
+    end.record()
+    torch.cuda.synchronize()
+    fd_ms = start.elapsed_time(end)
+    r.close()
+    return {
+        "workload": "N=%d, H=%d, pose + joint-limit costs, dt 0.02; refinement: 3 Adam steps, lr 0.05" % (N, H),
+        "refine_step": {"ms_per_step": ref_ms, "rollout_steps_per_s": N * H * 1e3 / ref_ms,
+                        "latency_ms": {"p50": float(np.percentile(ref_lat, 50)),
+                                       "p99": float(np.percentile(ref_lat, 99)), "steps": int(len(ref_lat))}},
+        "plain_step": {"ms_per_step": plain_ms, "rollout_steps_per_s": N * H * 1e3 / plain_ms,
+                       "latency_ms": {"p50": float(np.percentile(plain_lat, 50)),
+                                      "p99": float(np.percentile(plain_lat, 99)), "steps": int(len(plain_lat))}},
+        "gradient_us": {"adjoint": grad_us, "central_differences_by_plain_rollouts": fd_ms * 1e3,
+                        "rollouts_for_central_differences": n_fd},
+    }
+
+
+def large_bench(n_problems, steps, latency_steps, warmup, plain_steps):
+    """Large workload: n_problems problems of N=4096, H=64 with 100 obstacles
+    (every cost term for MPPI, pose + joint-limit terms refined by 3 Adam
+    steps of the batched adjoint), in closed loop against a goal moving along
+    y (0.3 m amplitude, 0.2 Hz), 0.01 s per control step; against one
+    captured graph per problem."""
+    import numpy as np
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    probs = [inputs.config5_problem(p) for p in range(n_problems)]
+    for pr in probs:
+        pr.params.grad_mask = inputs.COST_POSE | inputs.COST_JOINT
+    work = sum(pr.params.n_particles * pr.params.horizon for pr in probs)
+    qg = torch.tensor(np.stack([pr.q_goal for pr in probs]), dtype=torch.float32, device="cuda")
+    base = storm.fk(qg)[0].contiguous()
+    goals = base.clone()
+    b = storm.Batch(probs)
+    x0 = b.x0.clone()
+    cmd = torch.zeros((n_problems, 7), dtype=torch.float32, device="cuda")
+    best, _ = b.autotune(goals, x0=x0, reps=2)
+    graph = b.graph(x0, goals, cmd, iterations=1, shift=True, refine_iters=3, lr=0.05)
+    dt = 0.01
+
+    def set_goal(k):
+        # p_g(t) = p_0 + 0.3 sin(2 pi 0.2 t) e_y, orientation fixed
+        goals[:, 10] = base[:, 10] + 0.3 * float(np.sin(2.0 * np.pi * 0.2 * k * dt))
+
+    for k in range(warmup):
+        set_goal(k)
+        graph.launch()
+        storm.plant_step(x0, cmd, dt)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for k in range(steps):
+        set_goal(warmup + k)
+        graph.launch()
+        storm.plant_step(x0, cmd, dt)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    cmd_host = torch.empty((n_problems, 7), dtype=torch.float32, pin_memory=True)
+    lat = []
+    k0 = warmup + steps
+    for k in range(latency_steps):
+        set_goal(k0 + k)
+        t0 = time.perf_counter()
+        graph.launch()
+        cmd_host.copy_(cmd, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        storm.plant_step(x0, cmd, dt)
+    lat = np.array(lat)
+    pose = storm.fk(x0[:, :7].contiguous())[0]
+    err = torch.linalg.norm(pose[:, 9:12] - goals[:, 9:12], dim=1).cpu().numpy()
+    graph.close()
+    b.close()
+
+    plains = [storm.Rollout(pr) for pr in probs]
+    x0s = [r.x0.clone() for r in plains]
+    cmds = [torch.zeros(7, dtype=torch.float32, device="cuda") for _ in plains]
+    pg = [r.graph(x0s[k], goals[k], cmds[k], iterations=1, shift=True, refine_iters=3, lr=0.05)
+          for k, r in enumerate(plains)]
+    for g in pg:
+        g.launch()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(plain_steps):
+        for g in pg:
+            g.launch()
+    end.record()
+    torch.cuda.synchronize()
+    plain_ms = start.elapsed_time(end) / plain_steps
+    plat = []
+    for _ in range(plain_steps):
+        t0 = time.perf_counter()
+        for g in pg:
+            g.launch()
+        torch.cuda.current_stream().synchronize()
+        plat.append((time.perf_counter() - t0) * 1e3)
+    plat = np.array(plat)
+    for g in pg:
+        g.close()
+    for r in plains:
+        r.close()
+    return {
+        "workload": "%d problems, N=4096, H=64, 100 obstacles (50 spheres, 50 cuboids), all cost terms; "
+                    "3 Adam steps (lr 0.05) on pose + joint-limit gradients; goal moving along y, 0.3 m, 0.2 Hz"
+                    % n_problems,
+        "ms_per_step": ms,
+        "rollout_steps_per_s": work * 1e3 / ms,
+        "problems_per_s": n_problems * 1e3 / ms,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "steps": int(len(lat)), "closed_loop": True},
+        "closed_loop_steps": warmup + steps + latency_steps,
+        "position_error_m": {"median": float(np.median(err)), "max": float(np.max(err))},
+        "autotuned": best,
+        "plain_per_problem": {
+            "ms_per_step": plain_ms,
+            "problems_per_s": n_problems * 1e3 / plain_ms,
+            "latency_ms": {"p50": float(np.percentile(plat, 50)), "p99": float(np.percentile(plat, 99)),
+                           "steps": int(len(plat))},
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +413,9 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=256, help="batched workload size (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-latency-steps", type=int, default=1000)
+    ap.add_argument("--diff-steps", type=int, default=200, help="differentiable-form steps (0 = skip)")
+    ap.add_argument("--large-problems", type=int, default=64, help="large workload size (0 = skip)")
+    ap.add_argument("--large-steps", type=int, default=100)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (hardware-counter calibration)")
     args = ap.parse_args()
@@ -372,6 +568,11 @@ def main():
     if args.batch_problems > 0:
         line["batched"] = batched_bench(args.batch_problems, args.batch_steps, args.batch_latency_steps,
                                         warmup=5, tune_reps=3)
+    if args.diff_steps > 0:
+        line["differentiable"] = differentiable_bench(args.diff_steps, args.diff_steps, warmup=10)
+    if args.large_problems > 0:
+        line["large"] = large_bench(args.large_problems, args.large_steps, args.large_steps, warmup=5,
+                                    plain_steps=5)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(inputs.config2(args.seed), args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -110,6 +110,8 @@ typedef struct storm_params {
     float alpha_pos[3];  /* goal-frame axis weights of the position error (Eq. 9 alpha_2) */
     float alpha_rot[3];  /* row weights of the rotation error (Eq. 9 alpha_1) */
     float a_stop, a_joint, a_vel, a_manip, a_coll; /* Eq. 15 weights */
+    uint32_t grad_mask;  /* terms of the differentiable form (storm_rollout_grad / refine): a subset of
+                            POSE | JOINT | VEL | STOP; 0 = cost_mask, which must then be such a subset */
 } storm_params;
 
 /* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame
@@ -155,7 +157,8 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
  * d_x0 [3][7] and d_goal [12] are read on the device.  d_noise (nullable)
  * replaces the sampled standard noise of every non-null particle.  d_C
  * (nullable) receives a copy of C [N].  dbg (nullable) selects extra
- * outputs.  Errors: E_NULL, E_STATE (a step is pending its update), E_DEVICE. */
+ * outputs.  A second step before the update replaces the first one's
+ * controls and costs.  Errors: E_NULL, E_DEVICE. */
 int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_noise,
                            const storm_debug *dbg, float *d_C, void *stream);
 
@@ -190,13 +193,13 @@ int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float 
  * the paper): J(mu) = (1/N) sum_i C_i(mu + sigma * eps_i) with the standard
  * noise eps of the last storm_rollout_step held fixed (or d_noise [7][N][H]
  * if not NULL), sigma the current per-joint standard deviation, and C_i the
- * horizon cost (Eq. 2) of the pose (Eq. 9), joint / velocity limit (Eq. 11)
- * and stop (Eq. 10) terms.  Null particles add to J but not to the
- * gradient.  Reverse mode through the costs, the kinematics (Eq. 8) and the
- * integrator (Eq. 7), states recomputed.  d_mean [H][7] in, d_grad [H][7]
- * and d_J [1] out (each nullable).  Errors: E_NULL (x0, goal, mean),
- * E_UNSUPPORTED (cost mask with manipulability or collision terms),
- * E_DEVICE. */
+ * horizon cost (Eq. 2) of the terms in params.grad_mask (else cost_mask)
+ * among pose (Eq. 9), joint / velocity limit (Eq. 11) and stop (Eq. 10).
+ * Null particles add to J but not to the gradient.  Reverse mode through
+ * the costs, the kinematics (Eq. 8) and the integrator (Eq. 7), states
+ * recomputed.  d_mean [H][7] in, d_grad [H][7] and d_J [1] out (each
+ * nullable).  Errors: E_NULL (x0, goal, mean), E_UNSUPPORTED (grad_mask 0
+ * and a cost mask with manipulability or collision terms), E_DEVICE. */
 int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_mean,
                            const float *d_noise, float *d_grad, float *d_J, void *stream);
 
@@ -276,6 +279,26 @@ int32_t storm_batch_update(storm_batch b, float *d_cmd, int32_t shift, void *str
  * storm_rollout_graph_launch.  Errors as storm_rollout_graph_create. */
 int32_t storm_batch_graph_create(storm_batch b, const float *d_x0, const float *d_goal, float *d_cmd,
                                  int32_t iterations, int32_t shift, void *stream, storm_graph *out);
+
+/* As storm_batch_graph_create, followed by `refine_iters` batched Adam steps
+ * (storm_batch_refine, learning rate lr) before the commands and the shift.
+ * Errors as storm_batch_graph_create, plus E_PARAM (lr) and E_UNSUPPORTED
+ * (a problem whose gradient terms are not differentiable). */
+int32_t storm_batch_graph_create_refine(storm_batch b, const float *d_x0, const float *d_goal, float *d_cmd,
+                                        int32_t iterations, int32_t shift, int32_t refine_iters, float lr,
+                                        void *stream, storm_graph *out);
+
+/* Batched gradient refinement (the differentiable form of
+ * storm_rollout_refine for every problem at once): `iterations` Adam steps
+ * of learning rate lr on each problem's stored mean, with the gradient of its
+ * expected horizon cost over the noise of its last step (terms of its
+ * grad_mask), computed for all problems by one adjoint launch per step; then
+ * d_cmd [P][7] = each refined mu_0 and, if shift != 0, the warm-start shift.
+ * Meant to follow storm_batch_update(..., shift = 0).  Allocates nothing.
+ * d_x0 [P][3][7], d_goal [P][12].  Errors: E_NULL, E_RANGE (iterations < 0),
+ * E_PARAM (lr not finite or < 0), E_UNSUPPORTED, E_DEVICE. */
+int32_t storm_batch_refine(storm_batch b, const float *d_x0, const float *d_goal, int32_t iterations, float lr,
+                           float *d_cmd, int32_t shift, void *stream);
 
 /* Set / read the persistent launch shape (graphs capture the shape current
  * at their creation).  Errors: E_NULL, E_RANGE (waves not 8/16, grid < 1). */

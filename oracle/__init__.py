@@ -331,6 +331,17 @@ class Oracle:
                 "bad": bool(bad)}
 
     # -- gradient ----------------------------------------------------------
+    def _grad_params(self):
+        """The parameters with the cost mask of the differentiable form
+        (params.grad_mask when it is set)."""
+        gm = getattr(self.problem.params, "grad_mask", 0)
+        if not gm:
+            return self.params
+        p = OracleParams()
+        ctypes.pointer(p)[0] = self.params
+        p.cost_mask = gm
+        return p
+
     def grad(self, mean, sigma, eps, goal=None, x0=None):
         H = self.H
         mean, sigma, eps = _f64(mean), _f64(sigma), _f64(eps)
@@ -338,7 +349,7 @@ class Oracle:
         x0 = self.x0 if x0 is None else _f64(x0)
         g = np.zeros((H, DOF))
         J = ctypes.c_double()
-        rc = lib().oracle_grad(ctypes.byref(self.params), ctypes.byref(self.model), _d(self.dt), _d(x0),
+        rc = lib().oracle_grad(ctypes.byref(self._grad_params()), ctypes.byref(self.model), _d(self.dt), _d(x0),
                                _d(goal), _d(mean), _d(sigma), _d(eps), _d(g), ctypes.byref(J))
         if rc != 0:
             raise RuntimeError("oracle_grad failed (%d)" % rc)
@@ -349,7 +360,8 @@ class Oracle:
         goal = self.goal if goal is None else _f64(goal)
         x0 = self.x0 if x0 is None else _f64(x0)
         J = ctypes.c_double()
-        rc = lib().oracle_expected_cost(ctypes.byref(self.params), ctypes.byref(self.model), _d(self.dt), _d(x0),
+        rc = lib().oracle_expected_cost(ctypes.byref(self._grad_params()), ctypes.byref(self.model), _d(self.dt),
+                                        _d(x0),
                                         _d(goal), _d(mean), _d(sigma), _d(eps), ctypes.byref(J))
         if rc != 0:
             raise RuntimeError("oracle_expected_cost failed")

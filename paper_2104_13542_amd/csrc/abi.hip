@@ -68,6 +68,7 @@ int32_t validate_params(const storm_params *p)
     if (p->n_halton < 0 || p->n_halton > p->n_particles - p->n_null) return STORM_E_RANGE;
     if (p->n_halton > 0 && (p->n_knots < 4 || p->n_knots > 32)) return STORM_E_RANGE;
     if (p->cost_mask & ~STORM_COST_ALL) return STORM_E_PARAM;
+    if (p->grad_mask & ~(STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP)) return STORM_E_PARAM;
     if (!p->dt) return STORM_E_NULL;
     for (int h = 0; h < p->horizon; ++h)
         if (!finite_f(p->dt[h]) || !(p->dt[h] > 0.0f)) return STORM_E_PARAM;
@@ -294,6 +295,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     P.ppt = storm::kLanes / H;
     P.n_tiles = (N + P.ppt - 1) / P.ppt;
     P.cost_mask = params->cost_mask;
+    P.grad_mask = params->grad_mask != 0 ? params->grad_mask : params->cost_mask;
     P.seed_lo = (uint32_t)params->seed;
     P.seed_hi = (uint32_t)(params->seed >> 32);
     P.beta = params->beta;
@@ -340,8 +342,11 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &u, (size_t)STORM_DOF * N * H));
     STORM_TRY(dalloc(c, &C, (size_t)N));
     STORM_TRY(dalloc(c, &counters, (size_t)4));
-    STORM_TRY(dalloc(c, &grad_part, (size_t)P.n_tiles * STORM_DOF * storm::kMaxH));
-    STORM_TRY(dalloc(c, &cost_part, (size_t)P.n_tiles));
+    {
+        const int chunks = P.n_tiles < storm::kAdjChunks ? P.n_tiles : storm::kAdjChunks;
+        STORM_TRY(dalloc(c, &grad_part, (size_t)chunks * STORM_DOF * storm::kMaxH));
+        STORM_TRY(dalloc(c, &cost_part, (size_t)chunks));
+    }
     STORM_TRY(dalloc(c, &grad, (size_t)H * STORM_DOF));
     STORM_TRY(dalloc(c, &adam, (size_t)2 * H * STORM_DOF));
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
@@ -557,7 +562,7 @@ int32_t create_graph(storm_ctx ctx, const float *d_x0, const float *d_goal, floa
     if (!ctx || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
     if (iterations < 1 || refine_iters < 0) return STORM_E_RANGE;
     if (refine_iters > 0 && (!(lr >= 0.0f) || !isfinite(lr))) return STORM_E_PARAM;
-    if (refine_iters > 0 && (ctx->P.cost_mask & ~kDiffMask)) return STORM_E_UNSUPPORTED;
+    if (refine_iters > 0 && (ctx->P.grad_mask & ~kDiffMask)) return STORM_E_UNSUPPORTED;
     if (ctx->error != STORM_OK) return ctx->error;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipStream_t own = nullptr;
@@ -615,7 +620,7 @@ int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal
 {
     if (!ctx || !d_x0 || !d_goal || !d_mean) return STORM_E_NULL;
     if (ctx->error != STORM_OK) return ctx->error;
-    if (ctx->P.cost_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
+    if (ctx->P.grad_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
     if (storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, d_mean, d_noise, d_grad, d_J,
                            static_cast<hipStream_t>(stream)) != hipSuccess) {
         ctx->error = STORM_E_DEVICE;
@@ -631,7 +636,7 @@ int32_t storm_rollout_refine(storm_ctx ctx, const float *d_x0, const float *d_go
     if (iterations < 0) return STORM_E_RANGE;
     if (!(lr >= 0.0f) || !isfinite(lr)) return STORM_E_PARAM;
     if (ctx->error != STORM_OK) return ctx->error;
-    if (ctx->P.cost_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
+    if (ctx->P.grad_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
     if (enqueue_refine(ctx, d_x0, d_goal, iterations, lr, d_cmd, shift != 0, static_cast<hipStream_t>(stream)) !=
         hipSuccess) {
         ctx->error = STORM_E_DEVICE;

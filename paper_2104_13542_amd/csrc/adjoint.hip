@@ -25,11 +25,13 @@ namespace {
 constexpr int kAdjWaves = 8;
 constexpr int kRedThreads = 1024;
 
-__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P, RobotDev R,
-                                                                    const float *__restrict__ x0,
-                                                                    const float *__restrict__ goal,
-                                                                    const float *__restrict__ mean,
-                                                                    const float *__restrict__ noise)
+// Phases A-D for one tile, then the tile's share of the chunk partials:
+// acc (thread t < 7H: joint t / H, step t % H) gains the sum over the tile's
+// particles of dC/du, cacc (thread 0) the tile's horizon-cost sum.
+__device__ __forceinline__ void adjoint_tile(const ProblemDev &P, const RobotDev &R, const int tile,
+                                             const float *__restrict__ x0, const float *__restrict__ goal,
+                                             const float *__restrict__ mean, const float *__restrict__ noise,
+                                             float &acc, float &cacc)
 {
     __shared__ float s_eps[8][kLanes];
     __shared__ float s_q[kDof][kLanes];
@@ -44,14 +46,13 @@ __global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = blockIdx.x;
     const int N = P.N, H = P.H;
     const int pl = lane / H;
     const int h = lane - pl * H;
     const int i = tile * P.ppt + pl;
     const bool valid = pl < P.ppt && i < N;
     const bool live = valid && i < N - P.n_null;
-    const uint32_t mask = P.cost_mask;
+    const uint32_t mask = P.grad_mask;
     const float *__restrict__ tab = P.tables;
     const float dt_h = tab[kTabDt + h];
     const float hw_h = tab[kTabHw + h];
@@ -198,11 +199,8 @@ __global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P
         if (h == H - 1) s_Cp[pl] = valid ? Ci : 0.0f;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float sum = 0.0f;
-        for (int p = 0; p < P.ppt; ++p) sum += s_Cp[p];
-        P.cost_part[tile] = sum;
-    }
+    if (threadIdx.x == 0)
+        for (int p = 0; p < P.ppt; ++p) cacc += s_Cp[p];
 
     // ---- D: the integrator backwards -----------------------------------------
     if (wave < kDof) {
@@ -213,13 +211,52 @@ __global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P
     }
     __syncthreads();
 
-    // ---- E: tile partial of dJ/dmu (sum over the tile's particles) -----------
-    for (int idx = threadIdx.x; idx < kDof * H; idx += kAdjWaves * kLanes) {
-        const int j = idx / H, hh = idx - j * H;
-        float sum = 0.0f;
-        for (int p = 0; p < P.ppt; ++p) sum += s_gu[j][p * H + hh];
-        P.grad_part[((size_t)tile * kDof + j) * kMaxH + hh] = sum;
+    // ---- E: the tile's partial of dJ/dmu (sum over the tile's particles) -----
+    if ((int)threadIdx.x < kDof * H) {
+        const int j = threadIdx.x / H, hh = threadIdx.x - j * H;
+        for (int p = 0; p < P.ppt; ++p) acc += s_gu[j][p * H + hh];
     }
+    __syncthreads();  // LDS is reused by the next tile of the chunk
+}
+
+// Chunks of tiles of one problem: min(n_tiles, kAdjChunks), chunk c covering
+// tiles [c T / n, (c + 1) T / n); one workgroup per chunk, tiles in order.
+__device__ __forceinline__ int adj_chunks(const ProblemDev &P) { return min(P.n_tiles, kAdjChunks); }
+
+__device__ __forceinline__ void adjoint_chunk(const ProblemDev &P, const RobotDev &R, const int c,
+                                              const float *__restrict__ x0, const float *__restrict__ goal,
+                                              const float *__restrict__ mean, const float *__restrict__ noise)
+{
+    const int n = adj_chunks(P), T = P.n_tiles;
+    const int t0 = (int)((long long)c * T / n), t1 = (int)((long long)(c + 1) * T / n);
+    float acc = 0.0f, cacc = 0.0f;
+    for (int tile = t0; tile < t1; ++tile) adjoint_tile(P, R, tile, x0, goal, mean, noise, acc, cacc);
+    if ((int)threadIdx.x < kDof * P.H) {
+        const int j = threadIdx.x / P.H, hh = threadIdx.x - j * P.H;
+        P.grad_part[((size_t)c * kDof + j) * kMaxH + hh] = acc;
+    }
+    if (threadIdx.x == 0) P.cost_part[c] = cacc;
+}
+
+__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P, RobotDev R,
+                                                                    const float *__restrict__ x0,
+                                                                    const float *__restrict__ goal,
+                                                                    const float *__restrict__ mean,
+                                                                    const float *__restrict__ noise)
+{
+    adjoint_chunk(P, R, blockIdx.x, x0, goal, mean, noise);
+}
+
+// Batched form: workgroup k takes chunk items[k] = (problem, chunk).
+__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_batch_kernel(const ProblemDev *__restrict__ probs,
+                                                                          const int2 *__restrict__ items,
+                                                                          RobotDev R, const float *__restrict__ x0s,
+                                                                          const float *__restrict__ goals)
+{
+    const STORM_CONST_AS int32_t *it = uniform_ptr(reinterpret_cast<const int32_t *>(items));
+    const int p = it[2 * blockIdx.x], c = it[2 * blockIdx.x + 1];
+    const ProblemDev P = load_uniform(probs + p);
+    adjoint_chunk(P, R, c, x0s + (size_t)p * 3 * kDof, goals + (size_t)p * 12, P.mean, nullptr);
 }
 
 __device__ __forceinline__ float wave_sum(float x)
@@ -229,16 +266,16 @@ __device__ __forceinline__ float wave_sum(float x)
     return x;
 }
 
-// grad[h][j] = (1/N) sum over tiles of the partials, J = (1/N) sum of the
-// tile cost sums; rows of threads take tiles r, r + R, ..., then the rows
+// grad[h][j] = (1/N) sum over chunks of the partials, J = (1/N) sum of the
+// chunk cost sums; rows of threads take chunks r, r + R, ..., then the rows
 // are added in order.
-__global__ __launch_bounds__(kRedThreads) void grad_reduce_kernel(ProblemDev P, float *__restrict__ grad_out,
-                                                                  float *__restrict__ J_out)
+__device__ __forceinline__ void grad_reduce(const ProblemDev &P, float *__restrict__ grad_out,
+                                            float *__restrict__ J_out)
 {
     __shared__ float s_red[kRedThreads];
     __shared__ float s_wave[kRedThreads / kLanes];
     const int t = threadIdx.x;
-    const int H = P.H, T = P.n_tiles;
+    const int H = P.H, T = min(P.n_tiles, kAdjChunks);
     const int ncol = kDof * H;
     const int rows = kRedThreads / ncol;
     const int r = t / ncol, col = t - r * ncol;
@@ -275,11 +312,9 @@ __global__ __launch_bounds__(kRedThreads) void grad_reduce_kernel(ProblemDev P, 
     }
 }
 
-// One Adam step on the stored mean (moments restart at it == 1).
-__global__ void adam_kernel(ProblemDev P, int it, float lr, float b1, float b2, float eps)
+// One Adam step on the stored mean, element t (moments restart at it == 1).
+__device__ __forceinline__ void adam_step(const ProblemDev &P, int t, int it, float lr, float b1, float b2, float eps)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P.H * kDof) return;
     const float g = P.grad[t];
     const float m0 = it == 1 ? 0.0f : P.adam_m[t];
     const float v0 = it == 1 ? 0.0f : P.adam_v[t];
@@ -293,7 +328,7 @@ __global__ void adam_kernel(ProblemDev P, int it, float lr, float b1, float b2, 
 }
 
 // cmd = mu_0, then the warm-start shift of the stored mean if requested.
-__global__ void command_kernel(ProblemDev P, float *__restrict__ cmd, int shift)
+__device__ __forceinline__ void command(const ProblemDev &P, float *__restrict__ cmd, int shift)
 {
     __shared__ float s_mu[kDof * kMaxH];
     const int t = threadIdx.x;
@@ -305,13 +340,48 @@ __global__ void command_kernel(ProblemDev P, float *__restrict__ cmd, int shift)
         for (int k = t; k < n; k += blockDim.x) P.mean[k] = k + kDof < n ? s_mu[k + kDof] : 0.0f;
 }
 
+__global__ __launch_bounds__(kRedThreads) void grad_reduce_kernel(ProblemDev P, float *__restrict__ grad_out,
+                                                                  float *__restrict__ J_out)
+{
+    grad_reduce(P, grad_out, J_out);
+}
+
+__global__ void adam_kernel(ProblemDev P, int it, float lr, float b1, float b2, float eps)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < P.H * kDof) adam_step(P, t, it, lr, b1, b2, eps);
+}
+
+__global__ void command_kernel(ProblemDev P, float *__restrict__ cmd, int shift) { command(P, cmd, shift); }
+
+// Batched forms: workgroup p serves problem p.
+__global__ __launch_bounds__(kRedThreads) void grad_reduce_batch_kernel(const ProblemDev *__restrict__ probs)
+{
+    const ProblemDev P = load_uniform(probs + blockIdx.x);
+    grad_reduce(P, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(kDof *kMaxH) void adam_batch_kernel(const ProblemDev *__restrict__ probs, int it,
+                                                                 float lr, float b1, float b2, float eps)
+{
+    const ProblemDev P = load_uniform(probs + blockIdx.x);
+    if ((int)threadIdx.x < P.H * kDof) adam_step(P, threadIdx.x, it, lr, b1, b2, eps);
+}
+
+__global__ void command_batch_kernel(const ProblemDev *__restrict__ probs, float *__restrict__ cmd, int shift)
+{
+    const ProblemDev P = load_uniform(probs + blockIdx.x);
+    command(P, cmd + (size_t)blockIdx.x * kDof, shift);
+}
+
 }  // namespace
 
 hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal, const float *mean,
                        const float *noise, float *grad_out, float *J_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)P.n_tiles), dim3(kAdjWaves * kLanes), 0, stream, P, R, x0,
-                       goal, mean, noise);
+    const int chunks = P.n_tiles < kAdjChunks ? P.n_tiles : kAdjChunks;
+    hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)chunks), dim3(kAdjWaves * kLanes), 0, stream, P, R, x0, goal,
+                       mean, noise);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(kRedThreads), 0, stream, P, grad_out, J_out);
@@ -330,6 +400,31 @@ hipError_t launch_command(const ProblemDev &P, float *cmd, int shift, hipStream_
 {
     hipLaunchKernelGGL(command_kernel, dim3(1), dim3(256), 0, stream, P, cmd, shift);
     return hipGetLastError();
+}
+
+hipError_t launch_refine_batch(const ProblemDev *probs, int n_problems, const int2 *items, int n_items,
+                               const RobotDev &R, const float *x0s, const float *goals, int iterations, float lr,
+                               float *cmd, int shift, hipStream_t stream)
+{
+    hipError_t e = hipSuccess;
+    for (int it = 1; e == hipSuccess && it <= iterations; ++it) {
+        hipLaunchKernelGGL(adjoint_batch_kernel, dim3((unsigned)n_items), dim3(kAdjWaves * kLanes), 0, stream,
+                           probs, items, R, x0s, goals);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(grad_reduce_batch_kernel, dim3((unsigned)n_problems), dim3(kRedThreads), 0, stream,
+                           probs);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(adam_batch_kernel, dim3((unsigned)n_problems), dim3(kDof * kMaxH), 0, stream, probs, it,
+                           lr, 0.9f, 0.999f, 1e-8f);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(command_batch_kernel, dim3((unsigned)n_problems), dim3(256), 0, stream, probs, cmd, shift);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace storm

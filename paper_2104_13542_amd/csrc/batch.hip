@@ -25,6 +25,9 @@ struct storm_batch_s {
     int2 *d_items_plain = nullptr; // work queue in problem order
     int n_items = 0;
     uint32_t *d_next = nullptr;    // queue head (0 between launches)
+    int2 *d_adj_items = nullptr;   // (problem, tile chunk) items of the batched adjoint
+    int n_adj_items = 0;
+    bool differentiable = true;    // every problem's gradient terms are differentiable
     storm_launch_config cfg{8, 0, 1};
     std::vector<void *> allocs;
 };
@@ -92,6 +95,56 @@ int32_t launch_batch_step(storm_batch b, const float *d_x0, const float *d_goal,
     return e == hipSuccess ? STORM_OK : STORM_E_DEVICE;
 }
 
+// One captured control step of the whole batch: K rounds of step + update
+// (shift after the last round unless refinement follows), then
+// `refine_iters` batched Adam steps, the commands and the shift.
+int32_t batch_graph(storm_batch b, const float *d_x0, const float *d_goal, float *d_cmd, int32_t iterations,
+                    int32_t shift, int32_t refine_iters, float lr, void *stream, storm_graph *out)
+{
+    if (!out) return STORM_E_NULL;
+    *out = nullptr;
+    if (!b || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
+    if (iterations < 1 || refine_iters < 0) return STORM_E_RANGE;
+    if (refine_iters > 0 && (!(lr >= 0.0f) || !isfinite(lr))) return STORM_E_PARAM;
+    if (refine_iters > 0 && !b->differentiable) return STORM_E_UNSUPPORTED;
+    if (b->error != STORM_OK) return b->error;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStream_t own = nullptr;
+    if (s == nullptr) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return STORM_E_DEVICE;
+        s = own;
+    }
+    storm_graph g = new (std::nothrow) storm_graph_s();
+    if (!g) {
+        if (own) (void)hipStreamDestroy(own);
+        return STORM_E_NOMEM;
+    }
+    g->error = &b->error;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; e == hipSuccess && k < iterations; ++k) {
+        if (launch_batch_step(b, d_x0, d_goal, s) != STORM_OK) e = hipErrorLaunchFailure;
+        const bool last_shift = (k == iterations - 1) && shift != 0 && refine_iters == 0;
+        if (e == hipSuccess) e = launch_update_batch(b->d_probs, b->n_problems, d_cmd, last_shift, s);
+    }
+    if (e == hipSuccess && refine_iters > 0)
+        e = launch_refine_batch(b->d_probs, b->n_problems, b->d_adj_items, b->n_adj_items, b->R16, d_x0, d_goal,
+                                refine_iters, lr, d_cmd, shift != 0, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    g->graph = graph;
+    if (own) (void)hipStreamDestroy(own);
+    if (e != hipSuccess) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return STORM_E_DEVICE;
+    }
+    *out = g;
+    return STORM_OK;
+}
+
 __global__ void plant_kernel(float *__restrict__ x, const float *__restrict__ cmd, int n, float dt)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,6 +207,14 @@ int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_param
         }
     }
     b->n_items = (int)plain.size();
+    std::vector<int2> adj;
+    for (int p = 0; p < n_problems; ++p) {
+        const int chunks = probs[p].n_tiles < kAdjChunks ? probs[p].n_tiles : kAdjChunks;
+        for (int c = 0; c < chunks; ++c) adj.push_back(make_int2(p, c));
+        if (probs[p].grad_mask & ~(STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP))
+            b->differentiable = false;
+    }
+    b->n_adj_items = (int)adj.size();
     std::vector<int> order(plain.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
@@ -163,6 +224,9 @@ int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_param
     if (e == hipSuccess) e = balloc(b, &b->d_items_cost, plain.size());
     if (e == hipSuccess) e = balloc(b, &b->d_items_plain, plain.size());
     if (e == hipSuccess) e = balloc(b, &b->d_next, (size_t)1);
+    if (e == hipSuccess) e = balloc(b, &b->d_adj_items, adj.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_adj_items, adj.data(), sizeof(int2) * adj.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_probs, probs.data(), sizeof(ProblemDev) * probs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -210,42 +274,29 @@ int32_t storm_batch_update(storm_batch b, float *d_cmd, int32_t shift, void *str
 int32_t storm_batch_graph_create(storm_batch b, const float *d_x0, const float *d_goal, float *d_cmd,
                                  int32_t iterations, int32_t shift, void *stream, storm_graph *out)
 {
-    if (!out) return STORM_E_NULL;
-    *out = nullptr;
+    return batch_graph(b, d_x0, d_goal, d_cmd, iterations, shift, 0, 0.0f, stream, out);
+}
+
+int32_t storm_batch_graph_create_refine(storm_batch b, const float *d_x0, const float *d_goal, float *d_cmd,
+                                        int32_t iterations, int32_t shift, int32_t refine_iters, float lr,
+                                        void *stream, storm_graph *out)
+{
+    return batch_graph(b, d_x0, d_goal, d_cmd, iterations, shift, refine_iters, lr, stream, out);
+}
+
+int32_t storm_batch_refine(storm_batch b, const float *d_x0, const float *d_goal, int32_t iterations, float lr,
+                           float *d_cmd, int32_t shift, void *stream)
+{
     if (!b || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
-    if (iterations < 1) return STORM_E_RANGE;
+    if (iterations < 0) return STORM_E_RANGE;
+    if (!(lr >= 0.0f) || !isfinite(lr)) return STORM_E_PARAM;
     if (b->error != STORM_OK) return b->error;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipStream_t own = nullptr;
-    if (s == nullptr) {
-        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return STORM_E_DEVICE;
-        s = own;
-    }
-    storm_graph g = new (std::nothrow) storm_graph_s();
-    if (!g) {
-        if (own) (void)hipStreamDestroy(own);
-        return STORM_E_NOMEM;
-    }
-    g->error = &b->error;
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; e == hipSuccess && k < iterations; ++k) {
-        if (launch_batch_step(b, d_x0, d_goal, s) != STORM_OK) e = hipErrorLaunchFailure;
-        if (e == hipSuccess)
-            e = launch_update_batch(b->d_probs, b->n_problems, d_cmd, (k == iterations - 1) && shift != 0, s);
-    }
-    hipGraph_t graph = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(s, &graph);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
-    g->graph = graph;
-    if (own) (void)hipStreamDestroy(own);
-    if (e != hipSuccess) {
-        if (g->exec) (void)hipGraphExecDestroy(g->exec);
-        if (g->graph) (void)hipGraphDestroy(g->graph);
-        delete g;
+    if (!b->differentiable) return STORM_E_UNSUPPORTED;
+    if (launch_refine_batch(b->d_probs, b->n_problems, b->d_adj_items, b->n_adj_items, b->R16, d_x0, d_goal,
+                            iterations, lr, d_cmd, shift != 0, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        b->error = STORM_E_DEVICE;
         return STORM_E_DEVICE;
     }
-    *out = g;
     return STORM_OK;
 }
 

@@ -19,6 +19,7 @@ constexpr int kLanes = 64;  // CDNA wavefront width
 // manipulability terms while the others place the body spheres
 constexpr int kPoseWaves = 2;
 constexpr int kMaxH = STORM_MAX_HORIZON;
+constexpr int kAdjChunks = 512;  // adjoint workgroups (tile chunks) per problem, at most
 
 // Offsets (in floats) inside the per-problem table block built at init.
 constexpr int kTabDt = 0;           // dt[H]
@@ -35,7 +36,7 @@ constexpr int kTabSize = 224;
 struct ProblemDev {
     int32_t N, H, n_halton, n_null;
     int32_t n_sph_obs, n_box_obs, ppt, n_tiles;  // ppt = particles per 64-lane tile
-    uint32_t cost_mask, seed_lo, seed_hi, pad0;
+    uint32_t cost_mask, seed_lo, seed_hi, grad_mask;  // grad_mask: terms of the differentiable form
     float beta, alpha_mu, alpha_sigma, sigma2_min;
     float k_m, w_pos, w_rot, a_stop;
     float a_joint, a_vel, a_manip, a_coll;
@@ -53,8 +54,8 @@ struct ProblemDev {
     uint32_t *step;         // sampling step counter (Philox counter word 3)
     uint32_t *status;       // asynchronous status flags
     uint32_t *last_step;    // counter value the last rollout sampled with (reused by the adjoint)
-    float *grad_part;       // [n_tiles][7][kMaxH] adjoint partial gradients per tile
-    float *cost_part;       // [n_tiles] adjoint partial horizon-cost sums per tile
+    float *grad_part;       // [chunks][7][kMaxH] adjoint partial gradients per tile chunk
+    float *cost_part;       // [chunks] adjoint partial horizon-cost sums per tile chunk
     float *grad;            // [H][7] gradient of the expected horizon cost
     float *adam_m, *adam_v; // [H][7] Adam moments of the refinement
 };
@@ -126,6 +127,12 @@ hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, 
                        const float *noise, float *grad_out, float *J_out, hipStream_t stream);
 hipError_t launch_adam(const ProblemDev &P, int it, float lr, hipStream_t stream);
 hipError_t launch_command(const ProblemDev &P, float *cmd, int shift, hipStream_t stream);
+// Batched refinement: `iterations` Adam steps on the gradient of every
+// problem (adjoint over the (problem, chunk) items, per-problem reduce and
+// Adam), then the commands cmd [P][7] and the shift.
+hipError_t launch_refine_batch(const ProblemDev *probs, int n_problems, const int2 *items, int n_items,
+                               const RobotDev &R, const float *x0s, const float *goals, int iterations, float lr,
+                               float *cmd, int shift, hipStream_t stream);
 hipError_t launch_fk(const RobotDev &R, const float *q, int n, float *pose, float *manip, hipStream_t stream);
 
 // Self-collision work split of the robot's sphere pairs over `waves`

@@ -136,7 +136,6 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     // once (indices clamped into the array; the surplus values are unused)
     float c0 = INFINITY, c1 = INFINITY;
     float uu[kRegU];
-    const int nk = (N + rows - 1) / rows;  // slots in use, <= kRegU on this path
     if (regs) {
         if (t < N) c0 = C[t];
         if (t + kThreads < N) c1 = C[t + kThreads];

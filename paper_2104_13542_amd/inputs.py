@@ -130,6 +130,7 @@ class Params:
     a_manip: float = 30.0
     a_coll: float = 1000.0
     cost_mask: int = COST_POSE | COST_JOINT
+    grad_mask: int = 0  # terms of the differentiable form; 0 = cost_mask
 
 
 @dataclasses.dataclass

@@ -53,7 +53,7 @@ class storm_params(ctypes.Structure):
         ("w_pos", ctypes.c_float), ("w_rot", ctypes.c_float),
         ("alpha_pos", ctypes.c_float * 3), ("alpha_rot", ctypes.c_float * 3),
         ("a_stop", ctypes.c_float), ("a_joint", ctypes.c_float), ("a_vel", ctypes.c_float),
-        ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float),
+        ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float), ("grad_mask", ctypes.c_uint32),
     ]
 
 
@@ -84,6 +84,7 @@ EXPORTS = (
     "storm_batch_set_config", "storm_batch_get_config", "storm_batch_autotune", "storm_batch_get_state",
     "storm_batch_set_state", "storm_batch_costs", "storm_batch_destroy", "storm_plant_step",
     "storm_rollout_grad", "storm_rollout_refine", "storm_rollout_graph_create_refine",
+    "storm_batch_refine", "storm_batch_graph_create_refine",
 )
 
 
@@ -132,6 +133,9 @@ def lib():
         L.storm_rollout_refine.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, i32, vp]
         L.storm_rollout_graph_create_refine.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp,
                                                         ctypes.POINTER(vp)]
+        L.storm_batch_refine.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, i32, vp]
+        L.storm_batch_graph_create_refine.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp,
+                                                      ctypes.POINTER(vp)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_char_p if name == "storm_status_str" else i32
         _lib = L
@@ -161,6 +165,7 @@ def make_params(p: "inputs.Params"):
     sp.n_particles, sp.horizon = p.n_particles, p.horizon
     sp.n_halton, sp.n_null, sp.n_knots = p.n_halton, p.n_null, p.n_knots
     sp.cost_mask, sp.seed = p.cost_mask, p.seed
+    sp.grad_mask = getattr(p, "grad_mask", 0)
     dt = np.ascontiguousarray(p.dt, dtype=np.float32)
     sp.dt = dt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     for j in range(DOF):
@@ -403,8 +408,25 @@ class Batch:
         _check(lib().storm_batch_update(self._h, _ptr(cmd), int(bool(shift)), _stream()), "storm_batch_update")
         return cmd
 
-    def graph(self, x0, goals, cmd, iterations=1, shift=True):
+    def graph(self, x0, goals, cmd, iterations=1, shift=True, refine_iters=0, lr=0.05):
+        """Capture one control step of every problem (K iterations, then
+        optionally batched Adam refinement) into a HIP graph."""
+        if refine_iters:
+            def create(h, x0p, gp, cp, it, sh, stream, out):
+                return lib().storm_batch_graph_create_refine(h, x0p, gp, cp, it, sh, int(refine_iters), float(lr),
+                                                             stream, out)
+
+            return StepGraph(self, x0, goals, cmd, iterations, shift, create=create)
         return StepGraph(self, x0, goals, cmd, iterations, shift, create=lib().storm_batch_graph_create)
+
+    def refine(self, goals, iterations=3, lr=0.05, x0=None, cmd=None, shift=True):
+        """Batched Adam refinement of every problem's stored mean (after
+        update(shift=False)); returns the commands [P][7]."""
+        x0 = self.x0 if x0 is None else x0
+        cmd = self.cmd if cmd is None else cmd
+        _check(lib().storm_batch_refine(self._h, _ptr(x0), _ptr(goals), int(iterations), float(lr), _ptr(cmd),
+                                        int(bool(shift)), _stream()), "storm_batch_refine")
+        return cmd
 
     def config(self):
         c = storm_launch_config()

@@ -76,6 +76,7 @@ def test_init_validation(storm):
         ("alpha_mu", -0.1, E.STORM_E_PARAM), ("alpha_sigma", 2.0, E.STORM_E_PARAM),
         ("k_jl", 0.5, E.STORM_E_PARAM), ("sigma2_min", -1.0, E.STORM_E_PARAM),
         ("cost_mask", 0x80, E.STORM_E_PARAM), ("w_pos", float("inf"), E.STORM_E_PARAM),
+        ("grad_mask", 0x40, E.STORM_E_PARAM), ("grad_mask", 0x10, E.STORM_E_PARAM),
     ]
     for field, val, want in cases:
         sp2, rb2, sc2, keep2 = _args(storm)
@@ -158,4 +159,7 @@ def test_batch_and_plant_validation(storm):
     assert L.storm_plant_step(None, None, 0, ctypes.c_float(0.0), None) == E.STORM_E_PARAM
     assert L.storm_rollout_graph_create(None, None, None, None, 1, 1, None, ctypes.byref(h)) == E.STORM_E_NULL
     assert L.storm_rollout_graph_launch(None, None) == E.STORM_E_NULL
+    assert L.storm_batch_refine(None, None, None, 3, ctypes.c_float(0.05), None, 1, None) == E.STORM_E_NULL
+    assert L.storm_batch_graph_create_refine(None, None, None, None, 1, 1, 3, ctypes.c_float(0.05), None,
+                                             ctypes.byref(h)) == E.STORM_E_NULL
     assert L.storm_rollout_graph_destroy(None) == E.STORM_OK

@@ -55,7 +55,8 @@ def _dev(a):
 
 @pytest.mark.parametrize("mask", [inputs.COST_POSE | inputs.COST_JOINT,
                                   inputs.COST_POSE | inputs.COST_JOINT | inputs.COST_VEL | inputs.COST_STOP])
-@pytest.mark.parametrize("N,H,n_null", [(128, 30, 0), (67, 21, 3), (5, 64, 1), (1024, 30, 0)])
+@pytest.mark.parametrize("N,H,n_null", [(128, 30, 0), (67, 21, 3), (5, 64, 1), (1024, 30, 0), (2000, 30, 2),
+                                        (700, 64, 0)])
 def test_grad_matches_oracle(oracle_lib, mask, N, H, n_null):
     from paper_2104_13542_amd import storm
 
@@ -245,3 +246,38 @@ def test_grad_rejects_collision_costs():
         assert e.value.code == storm.STORM_E_UNSUPPORTED
     finally:
         r.close()
+
+
+def test_grad_mask_on_a_problem_with_every_cost(oracle_lib):
+    """grad_mask selects the differentiable terms of a problem whose MPPI cost
+    has every term (collisions and manipulability included); the gradient
+    and J are those of the selected terms alone, as the oracle computes them
+    with that mask."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(9, n_particles=300, horizon=30)
+    prob.params.grad_mask = inputs.COST_POSE | inputs.COST_JOINT | inputs.COST_STOP
+    o = _oracle(oracle_lib, prob)
+    N, H = 300, 30
+    eps = f32(inputs.standard_normal(77, (N, H, 7)))
+    mean = f32(np.random.default_rng(4).normal(size=(H, 7)) * 0.5)
+    r = storm.Rollout(prob)
+    try:
+        g, J = r.grad(_dev(mean), _dev(o.goal), noise=_dev(eps.transpose(2, 0, 1)))
+        torch.cuda.synchronize()
+        sig = np.sqrt(f32(np.asarray(prob.params.sigma_init) ** 2))
+        g_ref, J_ref = o.grad(mean, sig, eps)
+        assert abs(J.item() - J_ref) <= 1e-4 * abs(J_ref)
+        assert np.linalg.norm(g.cpu().double().numpy() - g_ref) <= 1e-3 * np.linalg.norm(g_ref)
+    finally:
+        r.close()
+
+
+def test_grad_mask_rejects_non_differentiable_terms():
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(0, n_particles=32, horizon=10)
+    prob.params.grad_mask = inputs.COST_POSE | inputs.COST_ENV
+    with pytest.raises(storm.StormError) as e:
+        storm.Rollout(prob)
+    assert e.value.code == storm.STORM_E_PARAM

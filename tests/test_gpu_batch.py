@@ -140,3 +140,83 @@ def test_plant_step_closed_form():
     np.testing.assert_allclose(got[:, 1], v, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(got[:, 0], x[:, 0] + 0.01 * v, rtol=1e-6, atol=1e-7)
     np.testing.assert_array_equal(got[:, 2], u)
+
+
+def _refine_problems(n):
+    probs = _problems(n, seed0=20)
+    for pr in probs:
+        pr.params.grad_mask = inputs.COST_POSE | inputs.COST_JOINT
+    return probs
+
+
+def test_batch_refine_matches_plain():
+    """One batched adjoint launch per Adam step gives every problem the
+    refinement its plain context computes (bit for bit at 16 waves)."""
+    from paper_2104_13542_amd import storm
+
+    probs = _refine_problems(5)
+    goals = _goals(probs)
+    b = storm.Batch(probs)
+    b.set_config(16, 64, 1)
+    plains = [storm.Rollout(pr) for pr in probs]
+    try:
+        for step in range(2):
+            b.step(goals)
+            b.update(shift=False)
+            cmd_b = b.refine(goals, iterations=3, lr=0.05, shift=True).clone()
+            cmds = []
+            for k, r in enumerate(plains):
+                r.step(goals[k])
+                r.update(shift=False)
+                cmds.append(r.refine(goals[k], iterations=3, lr=0.05, shift=True).clone())
+            torch.cuda.synchronize()
+            for k in range(len(probs)):
+                mb, sb, _ = b.get_state(k)
+                mp, sp, _ = plains[k].get_state()
+                assert np.array_equal(mb, mp) and np.array_equal(sb, sp), (step, k)
+                assert torch.equal(cmd_b[k], cmds[k]), (step, k)
+    finally:
+        b.close()
+        for r in plains:
+            r.close()
+
+
+def test_batch_refine_graph_replays_match_eager():
+    from paper_2104_13542_amd import storm
+
+    probs = _refine_problems(4)
+    goals = _goals(probs)
+    eager = storm.Batch(probs)
+    graphed = storm.Batch(probs)
+    try:
+        eager.set_config(16, 64, 1)
+        graphed.set_config(16, 64, 1)
+        cmd_g = torch.zeros((len(probs), 7), device="cuda")
+        x0 = graphed.x0.clone()
+        g = graphed.graph(x0, goals, cmd_g, iterations=1, shift=True, refine_iters=3, lr=0.05)
+        for rep in range(3):
+            eager.step(goals)
+            eager.update(shift=False)
+            cmd_e = eager.refine(goals, iterations=3, lr=0.05, shift=True).clone()
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(cmd_e, cmd_g), rep
+            for k in range(len(probs)):
+                assert np.array_equal(eager.get_state(k)[0], graphed.get_state(k)[0]), (rep, k)
+        g.close()
+    finally:
+        eager.close()
+        graphed.close()
+
+
+def test_batch_refine_rejects_collision_gradients():
+    from paper_2104_13542_amd import storm
+
+    probs = _problems(2)  # every cost term, grad_mask 0
+    b = storm.Batch(probs)
+    try:
+        with pytest.raises(storm.StormError) as e:
+            b.refine(_goals(probs))
+        assert e.value.code == storm.STORM_E_UNSUPPORTED
+    finally:
+        b.close()
