@@ -419,6 +419,7 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (hardware-counter calibration)")
     args = ap.parse_args()
+    t_start = time.perf_counter()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the MPC step of one problem runs on a single MI355X "
               "(multi-GPU sharding is not built); run with --gpus 1", file=sys.stderr)
@@ -565,14 +566,22 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = n * 4
+
+    def progress(msg):
+        print("[bench] %s (%.0f s)" % (msg, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+
+    progress("plain step done")
     if args.batch_problems > 0:
         line["batched"] = batched_bench(args.batch_problems, args.batch_steps, args.batch_latency_steps,
                                         warmup=5, tune_reps=3)
+        progress("batched workload done")
     if args.diff_steps > 0:
         line["differentiable"] = differentiable_bench(args.diff_steps, args.diff_steps, warmup=10)
+        progress("differentiable workload done")
     if args.large_problems > 0:
-        line["large"] = large_bench(args.large_problems, args.large_steps, args.large_steps, warmup=5,
+        line["large"] = large_bench(args.large_problems, args.large_steps, args.large_steps, warmup=20,
                                     plain_steps=5)
+        progress("large workload done")
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(inputs.config2(args.seed), args.cpu_budget)
     print(json.dumps(line), flush=True)
