@@ -32,31 +32,33 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6  # one FP32 op per lane per cycle (256 CU x 4 S
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_particle_step(mask, n_spheres, n_pairs, n_sph_obs, n_box_obs, gaussian_fraction):
+def flops_per_particle_step(mask, n_spheres, n_pairs, n_sph_obs, n_box_obs):
     """Algorithmic FP32 FLOPs of one (particle, step) point of the rollout
-    kernel (FMA = 2, add/mul/min/max/compare = 1, sqrt/sin/cos/log = 1)."""
+    kernel, per term (FMA = 2; add, mul, min, max and compare = 1; sin and
+    cos = 1), with the collision terms counted as brute force: every sphere
+    pair and every sphere-obstacle pair tested with the direct squared
+    distance (9 FLOP) or the cuboid transform and excess (30 FLOP).  The
+    kernel's broad phase skips most of those tests, so this is
+    brute-force-equivalent work.  Philox and Box-Muller are integer and
+    transcendental work and are not counted."""
     from paper_2104_13542_amd import inputs as I
 
-    f = 0.0
-    f += 28.0 * gaussian_fraction  # Box-Muller, 7 normals (Philox is integer work)
-    f += 14.0  # u = mu + sigma eps
-    f += 42.0  # integrator: two prefix sums and the dt products, 7 joints
-    f += 398.0  # forward kinematics: 8 DH transforms (48 each) + 7 sin + 7 cos
-    if mask & (I.COST_JOINT | I.COST_VEL | I.COST_STOP):
-        f += 129.0  # joint / velocity / stop hinges (7 joints) + 3 norms
+    f = 42.0  # u = mu + sigma eps and the two prefix sums of the triple integrator (7 joints)
+    f += 240.0 + 14.0  # forward kinematics: 8 DH transforms, 7 sin + 7 cos
     if mask & I.COST_POSE:
-        f += 110.0  # R_g^T R, position in goal frame, two weighted norms
+        f += 120.0  # rotation and goal-frame position errors, two weighted norms
+    if mask & I.COST_JOINT:
+        f += 42.0  # joint-limit hinges and norm
+    if mask & (I.COST_VEL | I.COST_STOP):
+        f += 80.0  # velocity-limit and stop hinges and norms
     if mask & I.COST_MANIP:
-        f += 450.0  # Jacobian (84), J J^T (294), LDL^T determinant, sqrt
+        f += 105.0 + 430.0  # Jacobian; J J^T and its 6x6 L D L^T, sqrt
     if mask & (I.COST_SELF | I.COST_ENV):
         f += 18.0 * n_spheres  # world sphere centres
-    if mask & I.COST_ENV:
-        # sphere obstacle: |x|^2 - 2 c.x + |c|^2 test = 3 FMA + compare (+ |x|^2 once per sphere);
-        # cuboid: 9 FMA transform (18), 3 excesses |l| - e clamped (6), square sum (5), compare
-        f += n_spheres * (5.0 + 7.0 * n_sph_obs + 30.0 * n_box_obs)
     if mask & I.COST_SELF:
         f += 9.0 * n_pairs
-    f += 22.0  # weighted sum (Eq. 15) and horizon weight (Eq. 2)
+    if mask & I.COST_ENV:
+        f += n_spheres * (9.0 * n_sph_obs + 30.0 * n_box_obs)
     return f
 
 
@@ -514,8 +516,7 @@ def main():
     n_so = int(np.sum(kinds == inputs.OBS_SPHERE))
     n_bo = int(np.sum(kinds == inputs.OBS_CUBOID))
     n_pairs = self_pair_count(prob.spheres)
-    gfrac = (N - p.n_halton - p.n_null) / N
-    fpp = flops_per_particle_step(p.cost_mask, n_sph, n_pairs, n_so, n_bo, gfrac)
+    fpp = flops_per_particle_step(p.cost_mask, n_sph, n_pairs, n_so, n_bo)
     achieved = fpp * N * H / (rollout_ms * 1e-3) / 1e12
 
     line = {

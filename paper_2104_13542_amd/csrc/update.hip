@@ -47,25 +47,6 @@ __device__ __forceinline__ int dpp_move(int x)
     return __builtin_amdgcn_mov_dpp(x, kCtrl, kRowMask, 0xf, false);
 }
 
-// Two wave sums at once (the two DPP chains interleave).
-__device__ __forceinline__ void wave_sum2(float &x, float &y)
-{
-    x += __int_as_float(dpp_move<0xb1, 0xf>(__float_as_int(x)));
-    y += __int_as_float(dpp_move<0xb1, 0xf>(__float_as_int(y)));
-    x += __int_as_float(dpp_move<0x4e, 0xf>(__float_as_int(x)));
-    y += __int_as_float(dpp_move<0x4e, 0xf>(__float_as_int(y)));
-    x += __int_as_float(dpp_move<0x141, 0xf>(__float_as_int(x)));
-    y += __int_as_float(dpp_move<0x141, 0xf>(__float_as_int(y)));
-    x += __int_as_float(dpp_move<0x140, 0xf>(__float_as_int(x)));
-    y += __int_as_float(dpp_move<0x140, 0xf>(__float_as_int(y)));
-    x += __int_as_float(dpp_move<0x142, 0xa>(__float_as_int(x)));
-    y += __int_as_float(dpp_move<0x142, 0xa>(__float_as_int(y)));
-    x += __int_as_float(dpp_move<0x143, 0xc>(__float_as_int(x)));
-    y += __int_as_float(dpp_move<0x143, 0xc>(__float_as_int(y)));
-    x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
-    y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 63));
-}
-
 __device__ __forceinline__ float wave_sum(float x)
 {
     x += __int_as_float(dpp_move<0xb1, 0xf>(__float_as_int(x)));
@@ -113,8 +94,6 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     __shared__ float s_wave[kWaves];
     __shared__ float s_wsum[kWaves];
     __shared__ int s_count[kWaves];
-    __shared__ float s_mu[kMaxH];
-    __shared__ float s_var[kMaxH];
     __shared__ float s_mold[kMaxH];
 
     const int t = threadIdx.x;
@@ -130,17 +109,24 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     const int r = t / H, h = t - r * H;
     const bool in_rows = r < rows;
     const float *__restrict__ U = P.u + (size_t)j * N * H + h;
-    const bool regs = N <= kRegU * rows && N <= 2 * kThreads;
+    const bool regs = N <= kRegU * rows && N <= 2 * kThreads && kRegU * rows <= kChunk;
+    const float nib = -1.0f / beta;
 
     // register path: the costs, then every control load, all in flight at
-    // once (indices clamped into the array; the surplus values are unused)
+    // once.  The controls come through a buffer resource bounded by the
+    // joint's N H values: slots past the last particle read 0 and cost no
+    // address arithmetic (the load returns the raw 32 bits).
     float c0 = INFINITY, c1 = INFINITY;
     float uu[kRegU];
     if (regs) {
         if (t < N) c0 = C[t];
         if (t + kThreads < N) c1 = C[t + kThreads];
+        const __amdgpu_buffer_rsrc_t ub = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(P.u + (size_t)j * N * H), (short)0, N * H * (int)sizeof(float), 0x00020000);
+        const int stride = rows * H * (int)sizeof(float);
 #pragma unroll
-        for (int k = 0; k < kRegU; ++k) uu[k] = U[(size_t)min(r + k * rows, N - 1) * H];
+        for (int k = 0; k < kRegU; ++k)
+            uu[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ub, t * 4 + k * stride, 0, 0));
     }
     const float mu = in_rows ? P.mean[h * kDof + j] : 0.0f;
 
@@ -164,25 +150,24 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             cmin = fminf(cmin, s_wave[k]);
             any_nonfinite |= s_count[k];
         }
-        const float w0 = t < N ? expf(-(c0 - cmin) / beta) : 0.0f;
-        const float w1 = t + kThreads < N ? expf(-(c1 - cmin) / beta) : 0.0f;
+        const float w0 = t < N ? expf((c0 - cmin) * nib) : 0.0f;
+        const float w1 = t + kThreads < N ? expf((c1 - cmin) * nib) : 0.0f;
         s_buf[t] = w0;
         s_buf[t + kThreads] = w1;
+        for (int i = 2 * kThreads + t; i < kRegU * rows; i += kThreads) s_buf[i] = 0.0f;  // slots past N
         const float sw = wave_sum(w0 + w1);
         if (lane == 0) s_wsum[wave] = sw;
         __syncthreads();
         for (int k = 0; k < kWaves; ++k) S0 += s_wsum[k];
         ok = !any_nonfinite && S0 > 0.0f && isfinite(S0);
-        // straight-line over the 32 slots (weight 0 past the last particle)
-        // so that every LDS read is in flight before the first use
+        // straight-line over the 32 slots (weight 0 and control 0 past the
+        // last particle) so that every LDS read is in flight before the first use
         float a1[4] = {0.0f, 0.0f, 0.0f, 0.0f}, a2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (in_rows && ok) {
 #pragma unroll
             for (int k = 0; k < kRegU; ++k) {
-                const int i = r + k * rows;
-                const float w = s_buf[min(i, N - 1)];
                 const float d = uu[k] - mu;
-                const float wd = i < N ? w * d : 0.0f;
+                const float wd = s_buf[r + k * rows] * d;
                 a1[k & 3] += wd;
                 a2[k & 3] = fmaf(wd, d, a2[k & 3]);
             }
@@ -207,7 +192,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
         int base = 0;
         for (int c0 = 0; c0 < N; c0 += kThreads) {
             const int i = c0 + t;
-            const float w = i < N ? expf(-(C[i] - cmin) / beta) : 0.0f;
+            const float w = i < N ? expf((C[i] - cmin) * nib) : 0.0f;
             sw += w;
             const bool nz = w > 0.0f;
             const uint64_t bal = __builtin_amdgcn_ballot_w64(nz);
@@ -265,7 +250,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             for (int c0 = 0; c0 < N; c0 += kChunk) {
                 const int nc = min(kChunk, N - c0);
                 __syncthreads();
-                for (int k = t; k < nc; k += kThreads) s_buf[k] = expf(-(C[c0 + k] - cmin) / beta);
+                for (int k = t; k < nc; k += kThreads) s_buf[k] = expf((C[c0 + k] - cmin) * nib);
                 __syncthreads();
                 if (!act) continue;
                 int k = r;
@@ -295,46 +280,46 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
         }
     }
 
-    // per step h: S1, S2 over the rows (one wave per step, lanes over rows,
-    // then a wave sum), the new mean and the variance about it
+    // Wave 0 finishes alone: lane h adds the rows of step h in order (S1, S2),
+    // forms the new mean and the variance about it, then one wave sum gives
+    // the variance over the horizon; no further workgroup barrier.
     s_red[t] = x1;
     s_red[kThreads + t] = x2;
     if (r == 0) s_mold[h] = mu;  // stored late: an early store would wait for every load in flight
     __syncthreads();
-    const float inv_S0 = 1.0f / S0;
-    for (int hh = wave; hh < H; hh += kWaves) {
-        float s1 = 0.0f, s2 = 0.0f;
-        for (int l = lane; l < rows; l += kLanes) {
-            s1 += s_red[l * H + hh];
-            s2 += s_red[kThreads + l * H + hh];
-        }
-        wave_sum2(s1, s2);
-        if (lane == 0) {
-            const float muo = s_mold[hh];
-            const float m1 = s1 * inv_S0, m2 = s2 * inv_S0;
-            const float delta = P.alpha_mu * m1;
-            s_mu[hh] = ok ? muo + delta : muo;
-            s_var[hh] = fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f);  // weighted variance about mu'
-        }
-    }
-    __syncthreads();
     if (wave == 0) {
-        const float acc = wave_sum(lane < H ? s_var[lane] : 0.0f);
+        const float inv_S0 = 1.0f / S0;
+        float s1 = 0.0f, s2 = 0.0f, muo = 0.0f;
+        if (lane < H) {
+            for (int k = 0; k < rows; ++k) {
+                s1 += s_red[k * H + lane];
+                s2 += s_red[kThreads + k * H + lane];
+            }
+            muo = s_mold[lane];
+        }
+        const float m1 = s1 * inv_S0, m2 = s2 * inv_S0;
+        const float delta = P.alpha_mu * m1;
+        const float mu_new = ok ? muo + delta : muo;
+        const float var = lane < H ? fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f) : 0.0f;  // about mu'
+        const float acc = wave_sum(var);
+        // the new mean of step h + 1 (the shifted warm start), 0 past the end
+        const float mu_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(mu_new), 0x130, 0xf, 0xf,
+                                                                         true));  // wave_shl:1
         if (lane == 0) {
             const float old = P.sigma2[j];
             float s2n = old;
             if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
             P.sigma2[j] = s2n;
             if (sigma2_out) sigma2_out[j] = s2n;
-            cmd[j] = s_mu[0];
+            cmd[j] = mu_new;
             if (j == 0) {
                 *P.step = *P.step + 1u;
                 if (!ok) atomicOr(P.status, any_nonfinite ? STORM_FLAG_NONFINITE_COST : STORM_FLAG_ZERO_WEIGHT);
             }
         }
         if (lane < H) {
-            if (mean_out) mean_out[lane * kDof + j] = s_mu[lane];
-            P.mean[lane * kDof + j] = shift ? (lane + 1 < H ? s_mu[lane + 1] : 0.0f) : s_mu[lane];
+            if (mean_out) mean_out[lane * kDof + j] = mu_new;
+            P.mean[lane * kDof + j] = shift ? (lane + 1 < H ? mu_next : 0.0f) : mu_new;
         }
     }
 }
