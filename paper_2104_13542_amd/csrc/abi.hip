@@ -141,60 +141,69 @@ std::vector<storm::SelfGroup> storm::self_groups(const storm_robot *robot)
     return g;
 }
 
-// Self-collision work split: the pairs (s, t) of every group, taken
-// group-major and s-major within a group (count pairs per s), are cut into
-// `waves` nearly equal parts at whole partners s; each part is written as
-// items (t_first | count << 8, group, s_begin, s_end).  Returns the pair
-// count; off[w] .. off[w + 1] are wave w's items.
+// Self-collision work split.  The kernel tests a group against two partners
+// s per round at the same cost whatever the group's count, so the rounds
+// (ceil(s_end / 2) per group, group-major) are cut into `waves` nearly equal
+// parts at whole rounds; each part is written as items (t_first | count << 8,
+// group, s_begin, s_end) with s_begin even.  Returns the pair count; off[w] ..
+// off[w + 1] are wave w's items.
 int storm::self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
 {
     const std::vector<SelfGroup> groups = self_groups(robot);
-    long long total = 0;
-    for (const SelfGroup &g : groups) total += (long long)g.count * g.s_end;
+    long long rounds = 0, pairs = 0;
+    for (const SelfGroup &g : groups) {
+        rounds += (g.s_end + 1) / 2;
+        pairs += (long long)g.count * g.s_end;
+    }
     seg.clear();
     off.assign(waves + 1, 0);
     for (int w = 0; w < waves; ++w) {
         off[w] = (int)seg.size() / 4;
-        const long long k0 = total * w / waves, k1 = total * (w + 1) / waves;
+        const long long k0 = rounds * w / waves, k1 = rounds * (w + 1) / waves;
         long long base = 0;
         for (int gi = 0; gi < (int)groups.size(); ++gi) {
             const SelfGroup &g = groups[gi];
-            // partner s belongs to the wave whose range holds pair base + s * count
-            const long long c = g.count;
-            const long long sa = k0 > base ? (k0 - base + c - 1) / c : 0;
-            const long long sb = k1 > base ? (k1 - base + c - 1) / c : 0;
-            const int a = (int)(sa < g.s_end ? sa : g.s_end), b = (int)(sb < g.s_end ? sb : g.s_end);
-            if (a < b) {
+            const long long r = (g.s_end + 1) / 2;
+            // rounds base .. base + r - 1 are this group's; take those in [k0, k1)
+            const long long ra = k0 > base ? (k0 - base < r ? k0 - base : r) : 0;
+            const long long rb = k1 > base ? (k1 - base < r ? k1 - base : r) : 0;
+            if (ra < rb) {
                 seg.push_back(g.t_first | (g.count << 8));
                 seg.push_back(gi);
-                seg.push_back(a);
-                seg.push_back(b);
+                seg.push_back((int)(2 * ra));
+                seg.push_back((int)(2 * rb < g.s_end ? 2 * rb : g.s_end));
             }
-            base += c * g.s_end;
+            base += r;
         }
     }
     off[waves] = (int)seg.size() / 4;
-    return (int)total;
+    return (int)pairs;
 }
 
-// Thresholds of the expanded pair test |c_s|^2 - 2 c_s.c_t + |c_t|^2 <
-// (r_s + r_t)^2 + slack, [group][s][k] for group sphere t_first + k:
-// the FP32 evaluation errs by less than 2^-24 * 10 (|c_s| + |c_t|)^2, and the
-// slack, 2^-18 (2 reach + r_s + r_t)^2, is over six times that with both
-// centres within the robot's reach.  Slots past a group's count, and
-// partners s outside its range, hold -1e30 (never a hit).
+// Records of the expanded pair test, [group][s][8] for partner s of the
+// group spheres t = t_first + k: entries k = 0..3 the threshold of
+// |c_s|^2 - 2 c_s.c_t + |c_t|^2 < (r_s + r_t)^2 + slack, entries 4 + k the
+// contact distance r_s + r_t.  The FP32 evaluation of the test errs by less
+// than 2^-24 * 12 (|c_s| + |c_t|)^2, and the slack, 2^-18 (2 reach + r_s +
+// r_t)^2, is over five times that with both centres within the robot's
+// reach.  Slots past a group's count, and partners s outside its range, hold
+// the threshold -1e30 (never a hit) and contact distance 0.
 std::vector<float> storm::self_thresholds(const storm_robot *robot, double reach)
 {
     const int S = robot->n_spheres;
     const std::vector<SelfGroup> groups = self_groups(robot);
-    std::vector<float> thr(groups.size() * (size_t)S * 4, -1.0e30f);
+    std::vector<float> thr(groups.size() * (size_t)S * 8, 0.0f);
     for (size_t gi = 0; gi < groups.size(); ++gi)
-        for (int s = 0; s < groups[gi].s_end; ++s)
-            for (int k = 0; k < groups[gi].count; ++k) {
+        for (int s = 0; s < S; ++s)
+            for (int k = 0; k < 4; ++k) {
+                float *rec = &thr[(gi * S + s) * 8];
+                rec[k] = -1.0e30f;
+                if (s >= groups[gi].s_end || k >= groups[gi].count) continue;
                 const int t = groups[gi].t_first + k;
                 const double rs = (double)robot->spheres[5 * s + 4] + (double)robot->spheres[5 * t + 4];
                 const double span = 2.0 * reach + rs;
-                thr[(gi * S + s) * 4 + k] = (float)(rs * rs + ldexp(span * span, -18));
+                rec[k] = (float)(rs * rs + ldexp(span * span, -18));
+                rec[4 + k] = (float)rs;
             }
     return thr;
 }

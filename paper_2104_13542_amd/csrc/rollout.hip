@@ -324,19 +324,24 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     if (mask & STORM_COST_SELF) {
         // Pairs by groups of up to four spheres t of one body, held in
         // registers as (-2 c_t, |c_t|^2), against their partners s streamed
-        // from LDS: per s four LDS reads, one scalar load of the four
-        // thresholds and, per pair, the expanded test |c_t|^2 - 2 c_s.c_t <
-        // threshold - |c_s|^2 (three FMAs, a subtraction, a compare).  Lanes
-        // that pass get the exact penetration (r_s + r_t) - |c_s - c_t|, at or
-        // below zero for a rounding near-miss; unused slots of a short group
-        // repeat its last sphere against a threshold no pair passes.
+        // from LDS, two partners per round.  Per pair, the expanded form
+        // a = |c_t|^2 - 2 c_s.c_t (three FMAs) less the pair's threshold;
+        // the group's minimum plus |c_s|^2 is negative at a lane where some
+        // pair may touch: one compare per partner and one branch per round,
+        // no per-pair lane masks.  Only a partner, and then a pair, that some
+        // lane passes gets the exact penetration (r_s + r_t) - |c_s - c_t|,
+        // at every lane: a lane whose pair fails the expanded test is apart
+        // by more than the contact distance plus the rounding, so its
+        // penetration is negative and leaves the maximum unchanged.  Unused
+        // slots of a short group repeat its last sphere against a threshold
+        // of -1e30, and the round after the last partner of an odd count
+        // repeats that partner.
         const STORM_CONST_AS int32_t *segs = uniform_ptr(reinterpret_cast<const int32_t *>(R.self_seg));
         const STORM_CONST_AS int32_t *off = uniform_ptr(R.self_off);
         const STORM_CONST_AS float *thr = uniform_ptr(R.self_thr);
-        const STORM_CONST_AS float *sloc = uniform_ptr(reinterpret_cast<const float *>(R.sph_local));
         const int g1 = off[wave + 1];
         for (int g = off[wave]; g < g1; ++g) {
-            const int code = segs[4 * g], grp = segs[4 * g + 1], s_end = segs[4 * g + 3];
+            const int code = segs[4 * g], grp = segs[4 * g + 1], s_begin = segs[4 * g + 2], s_end = segs[4 * g + 3];
             const int t_first = code & 255, count = code >> 8;
             float mx[4], my[4], mz[4], nt[4];
 #pragma unroll
@@ -347,32 +352,55 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                 mz[k] = -2.0f * s_cen[(t * 3 + 2) * kLanes + lane];
                 nt[k] = s_cn[t * kLanes + lane];
             }
-            const STORM_CONST_AS float *tg = thr + (size_t)grp * S * 4;
-            for (int sp = segs[4 * g + 2]; sp < s_end; ++sp) {
-                const float cx = s_cen[(sp * 3 + 0) * kLanes + lane];
-                const float cy = s_cen[(sp * 3 + 1) * kLanes + lane];
-                const float cz = s_cen[(sp * 3 + 2) * kLanes + lane];
-                const float ns = s_cn[sp * kLanes + lane];
-                const STORM_CONST_AS float *th = tg + 4 * sp;
-                bool hit[4];
-                uint64_t any = 0;
+            const STORM_CONST_AS float *tg = thr + (size_t)grp * S * 8;
+            // one round: partners s0 and s1 (s1 == s0 for the last of an odd
+            // count), whose records start at tp and tp + dt
+            auto round = [&](const int s0, const int s1, const STORM_CONST_AS float *tp, const int dt)
+                              __attribute__((always_inline)) {
+                const int ps[2] = {s0, s1};
+                float cx[2], cy[2], cz[2], ns[2], m[2], d[2][4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float a = fmaf(cx, mx[k], fmaf(cy, my[k], fmaf(cz, mz[k], nt[k])));
-                    hit[k] = a < th[k] - ns;
-                    any |= __builtin_amdgcn_ballot_w64(hit[k]);
+                for (int u = 0; u < 2; ++u) {
+                    const int s = ps[u];
+                    cx[u] = s_cen[(s * 3 + 0) * kLanes + lane];
+                    cy[u] = s_cen[(s * 3 + 1) * kLanes + lane];
+                    cz[u] = s_cen[(s * 3 + 2) * kLanes + lane];
+                    ns[u] = s_cn[s * kLanes + lane];
+                    const STORM_CONST_AS float *th = tp + u * dt;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        d[u][k] = fmaf(cx[u], mx[k], fmaf(cy[u], my[k], fmaf(cz[u], mz[k], nt[k]))) - th[k];
+                    m[u] = fminf(fminf(d[u][0], d[u][1]), fminf(d[u][2], d[u][3])) + ns[u];
                 }
-                if (__builtin_expect(any != 0, 0)) {
-                    const float rs = sloc[4 * sp + 3];
+                // the contact distances come with the thresholds (one scalar
+                // load per round), not in the rare branch
+                float rc[2][4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int t = t_first + (k < count ? k : count - 1);
-                        const float dx = fmaf(0.5f, mx[k], cx), dy = fmaf(0.5f, my[k], cy), dz = fmaf(0.5f, mz[k], cz);
-                        const float pen = (rs + sloc[4 * t + 3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                        if (hit[k]) selfpen = fmaxf(selfpen, pen);
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) rc[u][k] = tp[u * dt + 4 + k];
+                asm volatile("" : : "s"(rc[0][0]), "s"(rc[0][1]), "s"(rc[0][2]), "s"(rc[0][3]), "s"(rc[1][0]),
+                             "s"(rc[1][1]), "s"(rc[1][2]), "s"(rc[1][3]));
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(fminf(m[0], m[1]) < 0.0f) != 0, 0)) {
+                    // the partners, then the pairs, that some lane passes
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        if (__builtin_amdgcn_ballot_w64(m[u] < 0.0f) == 0) continue;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (k >= count || __builtin_amdgcn_ballot_w64(d[u][k] + ns[u] < 0.0f) == 0) continue;
+                            const float dx = fmaf(0.5f, mx[k], cx[u]), dy = fmaf(0.5f, my[k], cy[u]),
+                                        dz = fmaf(0.5f, mz[k], cz[u]);
+                            const float pen = rc[u][k] - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                            selfpen = fmaxf(selfpen, pen);
+                        }
                     }
                 }
-            }
+            };
+            int sp = s_begin;
+            const STORM_CONST_AS float *tp = tg + 8 * s_begin;
+            for (; sp + 1 < s_end; sp += 2, tp += 16) round(sp, sp + 1, tp, 8);
+            if (sp < s_end) round(sp, sp, tp, 0);
         }
     }
     s_penv[wave * kLanes + lane] = env;

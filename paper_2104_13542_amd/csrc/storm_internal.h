@@ -66,7 +66,7 @@ struct RobotDev {
     int32_t n_spheres, n_pairs, pad0, pad1;
     const float4 *sph_local;  // [S] body-frame centre (x, y, z), radius
     const int32_t *sph_body;  // [S] frame index 0..7 the sphere is attached to
-    const float *self_thr;    // [groups][S][4] threshold of the expanded pair test (group spheres x partner s)
+    const float *self_thr;    // [groups][S][8] expanded pair test thresholds (4), contact distances (4)
     const int4 *self_seg;     // self-collision items (t_first | count << 8, group, s_begin, s_end)
     const int32_t *self_off;  // [W + 1] segment range of each wave of the rollout workgroup
 };
