@@ -466,16 +466,19 @@ def main():
     torch.cuda.synchronize()
     graph_ms = start.elapsed_time(end) / K
 
-    # the rollout kernel alone, K launches back to back on the stream it runs
-    # on, bracketed by HIP events (its average duration prices the roofline)
+    # the rollout kernel's own duration within a control step (it reads the
+    # mean that the previous step's update has just written): HIP events on
+    # the stream it runs on bracket the rollout launch of each of K eager
+    # steps; their average prices the roofline
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(K):
+    for before, after in marks:
+        before.record()
         r.step(goal, x0=x0, C=C)
-    end.record()
+        after.record()
+        r.update(shift=True, want_mean=False, cmd=cmd)
     torch.cuda.synchronize()
-    rollout_ms = start.elapsed_time(end) / K
-    r.update(shift=True, want_mean=False, cmd=cmd)
+    rollout_ms = float(np.mean([before.elapsed_time(after) for before, after in marks]))
 
     # eager (two launches per step from the host) for comparison
     torch.cuda.synchronize()

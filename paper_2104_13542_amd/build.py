@@ -19,6 +19,11 @@ HIPCC_FLAGS = [
     "-Wall",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the leading scalar and pointer arguments of a kernel arrive in SGPRs at
+    # wave launch (the code object keeps a load prologue for firmware that
+    # does not preload), which takes a memory round trip off the start of
+    # the latency-bound plain rollout and update kernels
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
 ]
 
 

@@ -451,14 +451,32 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     }
 }
 
+// The fields the first loads of a tile depend on come first, as scalar
+// arguments, so that they are preloaded into SGPRs; the rest of the problem
+// follows in P.
 template <int W>
-__global__ __launch_bounds__(W * kLanes) void rollout_kernel(ProblemDev P, RobotDev R,
-                                                             const float *__restrict__ x0,
+__global__ __launch_bounds__(W * kLanes) void rollout_kernel(uint32_t *step, float *mean, float *sigma2,
+                                                             const float *halton, const float *tables, int32_t N,
+                                                             int32_t H, int32_t ppt, int32_t n_halton,
+                                                             int32_t n_null, uint32_t cost_mask, ProblemDev P,
+                                                             RobotDev R, const float *__restrict__ x0,
                                                              const float *__restrict__ goal,
                                                              const float *__restrict__ noise, StepOut out)
 {
     extern __shared__ float smem[];
-    rollout_tile<W>(P, R, blockIdx.x, x0, goal, noise, out, smem);
+    ProblemDev Q = P;
+    Q.step = step;
+    Q.mean = mean;
+    Q.sigma2 = sigma2;
+    Q.halton = halton;
+    Q.tables = tables;
+    Q.N = N;
+    Q.H = H;
+    Q.ppt = ppt;
+    Q.n_halton = n_halton;
+    Q.n_null = n_null;
+    Q.cost_mask = cost_mask;
+    rollout_tile<W>(Q, R, blockIdx.x, x0, goal, noise, out, smem);
 }
 
 // Persistent form for many problems: each workgroup takes (problem, tile)
@@ -538,9 +556,11 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
     const size_t lds = rollout_lds_bytes(R.n_spheres, waves);
     const dim3 grid((unsigned)P.n_tiles);
     if (waves == 16) {
-        hipLaunchKernelGGL(rollout_kernel<16>, grid, dim3(16 * kLanes), lds, stream, P, R, x0, goal, noise, out);
+        hipLaunchKernelGGL(rollout_kernel<16>, grid, dim3(16 * kLanes), lds, stream, P.step, P.mean, P.sigma2, P.halton,
+                           P.tables, P.N, P.H, P.ppt, P.n_halton, P.n_null, P.cost_mask, P, R, x0, goal, noise, out);
     } else if (waves == 8) {
-        hipLaunchKernelGGL(rollout_kernel<8>, grid, dim3(8 * kLanes), lds, stream, P, R, x0, goal, noise, out);
+        hipLaunchKernelGGL(rollout_kernel<8>, grid, dim3(8 * kLanes), lds, stream, P.step, P.mean, P.sigma2, P.halton,
+                           P.tables, P.N, P.H, P.ppt, P.n_halton, P.n_null, P.cost_mask, P, R, x0, goal, noise, out);
     } else {
         return hipErrorInvalidValue;
     }

@@ -324,11 +324,22 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     }
 }
 
-__global__ __launch_bounds__(kThreads) void update_kernel(ProblemDev P, float *__restrict__ mean_out,
-                                                          float *__restrict__ sigma2_out, float *__restrict__ cmd,
-                                                          int shift)
+// The fields the first loads depend on come first, as scalar arguments, so
+// that they are preloaded into SGPRs; the rest of the problem follows in P.
+__global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, float *mean, float *sigma2, int32_t N,
+                                                          int32_t H, float beta, ProblemDev P,
+                                                          float *__restrict__ mean_out, float *__restrict__ sigma2_out,
+                                                          float *__restrict__ cmd, int shift)
 {
-    update_joint(P, blockIdx.x, mean_out, sigma2_out, cmd, shift);
+    ProblemDev Q = P;
+    Q.C = C;
+    Q.u = u;
+    Q.mean = mean;
+    Q.sigma2 = sigma2;
+    Q.N = N;
+    Q.H = H;
+    Q.beta = beta;
+    update_joint(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift);
 }
 
 // Workgroup (p, j) of a batch; commands go to cmd[p][7].
@@ -352,7 +363,8 @@ hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *c
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(kDof), dim3(kThreads), 0, stream, P, mean_out, sigma2_out, cmd, shift);
+    hipLaunchKernelGGL(update_kernel, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2, P.N, P.H,
+                       P.beta, P, mean_out, sigma2_out, cmd, shift);
     return hipGetLastError();
 }
 
