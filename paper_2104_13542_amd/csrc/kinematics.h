@@ -10,25 +10,26 @@ namespace storm {
 // row-major rotation r[9] and origin p[3].  RotX mixes rotation columns 1 and
 // 2, RotZ mixes columns 0 and 1, the translations move the origin along the
 // current x and z axes.
+// One row of dh_step: row i of R and component i of p depend only on row i
+// of the previous frame, so the rows can be carried separately.
+__device__ __forceinline__ void dh_step_row(float r[3], float &p, float ca, float sa, float a, float d, float ct,
+                                            float st)
+{
+    const float y = r[1], z = r[2];
+    r[1] = fmaf(ca, y, sa * z);
+    r[2] = fmaf(-sa, y, ca * z);
+    p = fmaf(a, r[0], p);
+    const float x = r[0], y2 = r[1];
+    r[0] = fmaf(ct, x, st * y2);
+    r[1] = fmaf(-st, x, ct * y2);
+    p = fmaf(d, r[2], p);
+}
+
 __device__ __forceinline__ void dh_step(float r[9], float p[3], float ca, float sa, float a, float d, float ct,
                                         float st)
 {
 #pragma unroll
-    for (int row = 0; row < 3; ++row) {
-        const float y = r[row * 3 + 1], z = r[row * 3 + 2];
-        r[row * 3 + 1] = fmaf(ca, y, sa * z);
-        r[row * 3 + 2] = fmaf(-sa, y, ca * z);
-    }
-#pragma unroll
-    for (int row = 0; row < 3; ++row) p[row] = fmaf(a, r[row * 3 + 0], p[row]);
-#pragma unroll
-    for (int row = 0; row < 3; ++row) {
-        const float x = r[row * 3 + 0], y = r[row * 3 + 1];
-        r[row * 3 + 0] = fmaf(ct, x, st * y);
-        r[row * 3 + 1] = fmaf(-st, x, ct * y);
-    }
-#pragma unroll
-    for (int row = 0; row < 3; ++row) p[row] = fmaf(d, r[row * 3 + 2], p[row]);
+    for (int row = 0; row < 3; ++row) dh_step_row(r + 3 * row, p[row], ca, sa, a, d, ct, st);
 }
 
 // sqrt(det(J J^T)) for the geometric Jacobian whose column k is

@@ -9,16 +9,18 @@
 //                  (joints 4k..4k+3); or the Halton table; or the override
 //   A1  waves 0-6  one joint each: u = mu + sigma eps, then the two
 //                  segmented prefix sums of the triple integrator (Eq. 7) as
-//                  wavefront shuffle scans over the particle's lanes, and the
-//                  joint's sine and cosine
-//   B   wave 0     forward kinematics (Eq. 8), eight frames to LDS
-//       wave 1     joint / velocity / stop costs (Eq. 10-11)
-//   C   all waves  world centres of the body spheres to LDS
+//                  wavefront DPP scans over the particle's lanes, the joint's
+//                  sine and cosine, and its squared joint, velocity and stop
+//                  hinges (Eq. 10-11)
+//   B   waves 0-2  forward kinematics (Eq. 8), one row of the eight frames
+//                  per wave, to LDS
+//   C   waves 0..W-3  world centres of the body spheres to LDS
+//       wave W-2   manipulability (Eq. 12)
+//       wave W-1   the hinge norms (Eq. 10-11) and pose (Eq. 9)
 //   D   all waves  environment (spheres x obstacles) and self-collision
-//                  (sphere pairs) split over waves; pose cost (Eq. 9) and
-//                  manipulability (Eq. 12) on the last two waves
+//                  (sphere pairs) split over waves
 //   E   wave 0     weighted running cost (Eq. 15), horizon sum (Eq. 2) as a
-//                  segmented shuffle scan
+//                  segmented DPP scan
 // Obstacle, sphere and pair records are indexed by wave-uniform loop
 // counters, so they are fetched with scalar loads into SGPRs; every per-point
 // LDS array is [row][lane] (conflict-free).  Reductions run in a fixed order:
@@ -76,6 +78,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     float *s_terms = s_pself + W * kLanes;  // [8][64]
     float *s_sc = s_terms + 8 * kLanes;     // [7][2][64]: sin q_j, cos q_j
     float *s_cn = s_sc + 14 * kLanes;       // [S][64]: |c|^2 of the sphere centres
+    float *s_lim = s_cn + S * kLanes;       // [3][7][64]: squared joint, velocity, stop hinges per joint
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -94,6 +97,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     const float mu_j = live ? P.mean[h * kDof + jw] : 0.0f;
     const float sig_j = sqrtf(P.sigma2[jw]);
     const float dt_h = tab[kTabDt + h];
+    const float vs_h = tab[kTabVstop + h];
     const float q0_j = x0[jw], v0_j = x0[kDof + jw];
     // culling record of obstacle `lane` (first 64 obstacles) for phase D
     const float4 bound0 = (mask & STORM_COST_ENV) ? load_bound(P.obs_bound, lane, P.n_sph_obs + P.n_box_obs)
@@ -120,6 +124,14 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         const float q = q0_j + segmented_scan(dt_h * v, h, H);
         s_q[j * kLanes + lane] = q;
         s_v[j * kLanes + lane] = v;
+        // this joint's squared joint, velocity and stop hinges (Eq. 10-11),
+        // summed over the joints in phase C
+        const float hj = hinge_box(q, tab[kTabJlo + j], tab[kTabJhi + j]);
+        const float hv = hinge_box(v, tab[kTabVlo + j], tab[kTabVhi + j]);
+        const float hs = fmaxf(fabsf(v) - vs_h, 0.0f);
+        s_lim[(0 * kDof + j) * kLanes + lane] = hj * hj;
+        s_lim[(1 * kDof + j) * kLanes + lane] = hv * hv;
+        s_lim[(2 * kDof + j) * kLanes + lane] = hs * hs;
         float sq, cq;
         sincosf(q, &sq, &cq);
         s_sc[(2 * j) * kLanes + lane] = sq;
@@ -135,10 +147,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     }
     __syncthreads();
 
-    // ---- B: forward kinematics | limit costs --------------------------------
-    if (wave == 0) {
-        float r[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
-        float p[3] = {0.0f, 0.0f, 0.0f};
+    // ---- B: forward kinematics, one row of the frames per wave ----------------
+    if (wave < 3) {
+        const int row = wave;
+        float r[3] = {row == 0 ? 1.0f : 0.0f, row == 1 ? 1.0f : 0.0f, row == 2 ? 1.0f : 0.0f};
+        float p = 0.0f;
 #pragma unroll
         for (int f = 0; f < kFrames; ++f) {
             float st = 0.0f, ct = 1.0f;
@@ -146,28 +159,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                 st = s_sc[(2 * f) * kLanes + lane];
                 ct = s_sc[(2 * f + 1) * kLanes + lane];
             }
-            dh_step(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
+            dh_step_row(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) s_fr[(f * 12 + c) * kLanes + lane] = r[c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) s_fr[(f * 12 + 9 + c) * kLanes + lane] = p[c];
+            for (int c = 0; c < 3; ++c) s_fr[(f * 12 + row * 3 + c) * kLanes + lane] = r[c];
+            s_fr[(f * 12 + 9 + row) * kLanes + lane] = p;
         }
-    } else if (wave == 1) {
-        float ej = 0.0f, ev = 0.0f, es = 0.0f;
-        const float vs = tab[kTabVstop + h];
-#pragma unroll
-        for (int j = 0; j < kDof; ++j) {
-            const float q = s_q[j * kLanes + lane], v = s_v[j * kLanes + lane];
-            const float a = hinge_box(q, tab[kTabJlo + j], tab[kTabJhi + j]);
-            const float b = hinge_box(v, tab[kTabVlo + j], tab[kTabVhi + j]);
-            const float c = fmaxf(fabsf(v) - vs, 0.0f);
-            ej = fmaf(a, a, ej);
-            ev = fmaf(b, b, ev);
-            es = fmaf(c, c, es);
-        }
-        s_terms[2 * kLanes + lane] = fast_sqrt(ej);
-        s_terms[3 * kLanes + lane] = fast_sqrt(ev);
-        s_terms[4 * kLanes + lane] = fast_sqrt(es);
     }
     __syncthreads();
 
@@ -178,20 +174,38 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     constexpr int WC = W - kPoseWaves;
     if (wave < WC) {
         if (mask & (STORM_COST_SELF | STORM_COST_ENV)) {
-            for (int s = wave; s < S; s += WC) {
+            // a contiguous run of spheres per wave (sorted by body): the
+            // frame of a body is read from LDS once per run
+            const int s0 = wave * S / WC, s1 = (wave + 1) * S / WC;
+            const STORM_CONST_AS int32_t *body = uniform_ptr(R.sph_body);
+            int fb = -1;
+            float F[12];
+            for (int s = s0; s < s1; ++s) {
                 const STORM_CONST_AS float *sl = uniform_ptr(reinterpret_cast<const float *>(R.sph_local)) + 4 * s;
-                const float *F = s_fr + uniform_ptr(R.sph_body)[s] * 12 * kLanes + lane;
+                const int b = body[s];
+                if (b != fb) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) F[c] = s_fr[(b * 12 + c) * kLanes + lane];
+                    fb = b;
+                }
                 float cc[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    cc[c] = fmaf(F[(c * 3 + 0) * kLanes], sl[0],
-                                 fmaf(F[(c * 3 + 1) * kLanes], sl[1], fmaf(F[(c * 3 + 2) * kLanes], sl[2], F[(9 + c) * kLanes])));
+                    cc[c] = fmaf(F[c * 3 + 0], sl[0], fmaf(F[c * 3 + 1], sl[1], fmaf(F[c * 3 + 2], sl[2], F[9 + c])));
                     s_cen[(s * 3 + c) * kLanes + lane] = cc[c];
                 }
                 s_cn[s * kLanes + lane] = fmaf(cc[0], cc[0], fmaf(cc[1], cc[1], cc[2] * cc[2]));
             }
         }
     } else if (wave == W - 1) {
+        // Eq. 10-11: norms over the joints of the hinges formed in phase A1
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kDof; ++j) acc += s_lim[(k * kDof + j) * kLanes + lane];
+            s_terms[(2 + k) * kLanes + lane] = fast_sqrt(acc);
+        }
         if (mask & STORM_COST_POSE) {
             // Eq. 9: rotation error |diag(alpha_rot)(I - R_g^T R)|_F and position
             // error |diag(alpha_pos) R_g^T (p - p_g)|.
@@ -512,7 +526,7 @@ __global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const Problem
 
 size_t rollout_lds_bytes(int S, int W)
 {
-    return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof) * kLanes * sizeof(float);
+    return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof + 3 * kDof) * kLanes * sizeof(float);
 }
 
 }  // namespace
