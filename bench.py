@@ -11,8 +11,8 @@ GPU before timing; the timed region is K back-to-back steps on one stream.
 Prints one JSON line: rollout-steps/s (N * H * K / device time), the MPC-step
 latency (host wall clock from enqueue to the command being readable on the
 host) p50/p99, the roofline position of the rollout kernel (algorithmic FP32
-FLOPs per launch / its average duration from HIP events recorded around each
-launch in the timed region) and the FP64 CPU oracle timed on the host.
+FLOPs per launch / its average duration from HIP events around K back-to-back
+launches on its stream) and the FP64 CPU oracle timed on the host.
 """
 import argparse
 import json
@@ -466,19 +466,18 @@ def main():
     torch.cuda.synchronize()
     graph_ms = start.elapsed_time(end) / K
 
-    # the rollout kernel's own duration within a control step (it reads the
-    # mean that the previous step's update has just written): HIP events on
-    # the stream it runs on bracket the rollout launch of each of K eager
-    # steps; their average prices the roofline
-    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    # the rollout kernel's average duration: K launches back to back on the
+    # stream it runs on, bracketed by HIP events (an event pair around a
+    # single launch would also time its dispatch from an idle queue); it
+    # prices the roofline
     torch.cuda.synchronize()
-    for before, after in marks:
-        before.record()
+    start.record()
+    for _ in range(K):
         r.step(goal, x0=x0, C=C)
-        after.record()
-        r.update(shift=True, want_mean=False, cmd=cmd)
+    end.record()
     torch.cuda.synchronize()
-    rollout_ms = float(np.mean([before.elapsed_time(after) for before, after in marks]))
+    rollout_ms = start.elapsed_time(end) / K
+    r.update(shift=True, want_mean=False, cmd=cmd)
 
     # eager (two launches per step from the host) for comparison
     torch.cuda.synchronize()
