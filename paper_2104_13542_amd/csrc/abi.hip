@@ -555,11 +555,12 @@ hipError_t enqueue_refine(storm_ctx ctx, const float *d_x0, const float *d_goal,
                           float *d_cmd, int shift, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    for (int it = 1; e == hipSuccess && it <= iterations; ++it) {
-        e = storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, ctx->P.mean, nullptr, nullptr, nullptr, s);
-        if (e == hipSuccess) e = storm::launch_adam(ctx->P, it, lr, s);
-    }
-    if (e == hipSuccess) e = storm::launch_command(ctx->P, d_cmd, shift, s);
+    // each launch: adjoint, then the reduction with Adam step `it` fused; the
+    // last also writes the command and the shift
+    for (int it = 1; e == hipSuccess && it <= iterations; ++it)
+        e = storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, ctx->P.mean, nullptr, nullptr, nullptr, it, lr,
+                               it == iterations ? d_cmd : nullptr, shift, s);
+    if (e == hipSuccess && iterations == 0) e = storm::launch_command(ctx->P, d_cmd, shift, s);
     return e;
 }
 
@@ -630,7 +631,7 @@ int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal
     if (!ctx || !d_x0 || !d_goal || !d_mean) return STORM_E_NULL;
     if (ctx->error != STORM_OK) return ctx->error;
     if (ctx->P.grad_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
-    if (storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, d_mean, d_noise, d_grad, d_J,
+    if (storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, d_mean, d_noise, d_grad, d_J, 0, 0.0f, nullptr, 0,
                            static_cast<hipStream_t>(stream)) != hipSuccess) {
         ctx->error = STORM_E_DEVICE;
         return STORM_E_DEVICE;

@@ -269,53 +269,11 @@ __device__ __forceinline__ float wave_sum(float x)
 // grad[h][j] = (1/N) sum over chunks of the partials, J = (1/N) sum of the
 // chunk cost sums; rows of threads take chunks r, r + R, ..., then the rows
 // are added in order.
-__device__ __forceinline__ void grad_reduce(const ProblemDev &P, float *__restrict__ grad_out,
-                                            float *__restrict__ J_out)
+// One Adam step with gradient g on the stored mean, element t (moments
+// restart at it == 1).
+__device__ __forceinline__ void adam_step(const ProblemDev &P, int t, float g, int it, float lr, float b1, float b2,
+                                          float eps)
 {
-    __shared__ float s_red[kRedThreads];
-    __shared__ float s_wave[kRedThreads / kLanes];
-    const int t = threadIdx.x;
-    const int H = P.H, T = min(P.n_tiles, kAdjChunks);
-    const int ncol = kDof * H;
-    const int rows = kRedThreads / ncol;
-    const int r = t / ncol, col = t - r * ncol;
-    const int j = col / H, h = col - j * H;
-    float acc = 0.0f;
-    if (r < rows) {
-        int k = r;
-        for (; k + 3 * rows < T; k += 4 * rows) {
-            float v[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) v[m] = P.grad_part[((size_t)(k + m * rows) * kDof + j) * kMaxH + h];
-            acc += (v[0] + v[1]) + (v[2] + v[3]);
-        }
-        for (; k < T; k += rows) acc += P.grad_part[((size_t)k * kDof + j) * kMaxH + h];
-    }
-    s_red[t] = acc;
-    float cs = 0.0f;
-    for (int k = t; k < T; k += kRedThreads) cs += P.cost_part[k];
-    cs = wave_sum(cs);
-    if ((t & (kLanes - 1)) == 0) s_wave[t / kLanes] = cs;
-    __syncthreads();
-    const float invN = 1.0f / (float)P.N;
-    if (t < ncol) {
-        float s = 0.0f;
-        for (int k = 0; k < rows; ++k) s += s_red[k * ncol + t];
-        const float g = s * invN;
-        P.grad[h * kDof + j] = g;
-        if (grad_out) grad_out[h * kDof + j] = g;
-    }
-    if (t == 0) {
-        float J = 0.0f;
-        for (int k = 0; k < kRedThreads / kLanes; ++k) J += s_wave[k];
-        if (J_out) *J_out = J * invN;
-    }
-}
-
-// One Adam step on the stored mean, element t (moments restart at it == 1).
-__device__ __forceinline__ void adam_step(const ProblemDev &P, int t, int it, float lr, float b1, float b2, float eps)
-{
-    const float g = P.grad[t];
     const float m0 = it == 1 ? 0.0f : P.adam_m[t];
     const float v0 = it == 1 ? 0.0f : P.adam_v[t];
     const float m = fmaf(b1, m0, (1.0f - b1) * g);
@@ -340,32 +298,92 @@ __device__ __forceinline__ void command(const ProblemDev &P, float *__restrict__
         for (int k = t; k < n; k += blockDim.x) P.mean[k] = k + kDof < n ? s_mu[k + kDof] : 0.0f;
 }
 
-__global__ __launch_bounds__(kRedThreads) void grad_reduce_kernel(ProblemDev P, float *__restrict__ grad_out,
-                                                                  float *__restrict__ J_out)
+// Gradient of joint j: the chunk partials of (h, j) summed in a fixed order
+// (thread (r, h) over chunks r, r + rows, ..., every load in flight at once,
+// then wave 0 over the rows), divided by N; joint 0 also sums the chunk
+// costs into J.  With it > 0, lane h of wave 0 then takes the Adam step on
+// mu[h][j]; with cmd, it writes the command mu[0][j] and the warm-start
+// shift of the joint (the next step's value through a DPP wave shift).
+__device__ __forceinline__ void grad_step(const ProblemDev &P, int j, float *__restrict__ grad_out,
+                                          float *__restrict__ J_out, int it, float lr, float *__restrict__ cmd,
+                                          int shift)
 {
-    grad_reduce(P, grad_out, J_out);
+    constexpr int kMaxPerThread = (kAdjChunks * kMaxH + kRedThreads - 1) / kRedThreads;
+    __shared__ float s_red[kRedThreads];
+    __shared__ float s_wave[kRedThreads / kLanes];
+    const int t = threadIdx.x;
+    const int lane = t & (kLanes - 1), wave = t / kLanes;
+    const int H = P.H, T = min(P.n_tiles, kAdjChunks);
+    const int rows = kRedThreads / H;
+    const int r = t / H, h = t - r * H;
+    float acc = 0.0f;
+    if (r < rows) {
+        const float *__restrict__ src = P.grad_part + (size_t)j * kMaxH + h;
+        float v[kMaxPerThread];
+#pragma unroll
+        for (int i = 0; i < kMaxPerThread; ++i) {
+            const int k = r + i * rows;
+            v[i] = k < T ? src[(size_t)k * kDof * kMaxH] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxPerThread; ++i) acc += v[i];
+    }
+    s_red[t] = acc;
+    if (j == 0) {
+        float cs = 0.0f;
+        for (int k = t; k < T; k += kRedThreads) cs += P.cost_part[k];
+        cs = wave_sum(cs);
+        if (lane == 0) s_wave[wave] = cs;
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    const float invN = 1.0f / (float)P.N;
+    if (j == 0 && lane == 0 && J_out) {
+        float J = 0.0f;
+        for (int k = 0; k < kRedThreads / kLanes; ++k) J += s_wave[k];
+        *J_out = J * invN;
+    }
+    float mu = 0.0f;
+    if (lane < H) {
+        float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        int k = 0;
+        for (; k + 3 < rows; k += 4)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) p4[m] += s_red[(k + m) * H + lane];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            if (k + m < rows) p4[m] += s_red[(k + m) * H + lane];
+        const float g = ((p4[0] + p4[1]) + (p4[2] + p4[3])) * invN;
+        const int e = lane * kDof + j;
+        P.grad[e] = g;
+        if (grad_out) grad_out[e] = g;
+        if (it > 0) adam_step(P, e, g, it, lr, 0.9f, 0.999f, 1e-8f);
+        if (cmd) mu = P.mean[e];
+    }
+    if (cmd) {
+        const float mu_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(mu), 0x130, 0xf, 0xf,
+                                                                         true));  // wave_shl:1
+        if (lane == 0) cmd[j] = mu;
+        if (shift && lane < H) P.mean[lane * kDof + j] = lane + 1 < H ? mu_next : 0.0f;
+    }
 }
 
-__global__ void adam_kernel(ProblemDev P, int it, float lr, float b1, float b2, float eps)
+__global__ __launch_bounds__(kRedThreads) void grad_step_kernel(ProblemDev P, float *__restrict__ grad_out,
+                                                                float *__restrict__ J_out, int it, float lr,
+                                                                float *__restrict__ cmd, int shift)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < P.H * kDof) adam_step(P, t, it, lr, b1, b2, eps);
+    grad_step(P, blockIdx.x, grad_out, J_out, it, lr, cmd, shift);
 }
 
 __global__ void command_kernel(ProblemDev P, float *__restrict__ cmd, int shift) { command(P, cmd, shift); }
 
-// Batched forms: workgroup p serves problem p.
-__global__ __launch_bounds__(kRedThreads) void grad_reduce_batch_kernel(const ProblemDev *__restrict__ probs)
+// Batched forms: workgroup p * 7 + j serves joint j of problem p.
+__global__ __launch_bounds__(kRedThreads) void grad_step_batch_kernel(const ProblemDev *__restrict__ probs, int it,
+                                                                      float lr, float *__restrict__ cmd, int shift)
 {
-    const ProblemDev P = load_uniform(probs + blockIdx.x);
-    grad_reduce(P, nullptr, nullptr);
-}
-
-__global__ __launch_bounds__(kDof *kMaxH) void adam_batch_kernel(const ProblemDev *__restrict__ probs, int it,
-                                                                 float lr, float b1, float b2, float eps)
-{
-    const ProblemDev P = load_uniform(probs + blockIdx.x);
-    if ((int)threadIdx.x < P.H * kDof) adam_step(P, threadIdx.x, it, lr, b1, b2, eps);
+    const int p = blockIdx.x / kDof, j = blockIdx.x - p * kDof;
+    const ProblemDev P = load_uniform(probs + p);
+    grad_step(P, j, nullptr, nullptr, it, lr, cmd ? cmd + (size_t)p * kDof : nullptr, shift);
 }
 
 __global__ void command_batch_kernel(const ProblemDev *__restrict__ probs, float *__restrict__ cmd, int shift)
@@ -377,22 +395,16 @@ __global__ void command_batch_kernel(const ProblemDev *__restrict__ probs, float
 }  // namespace
 
 hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal, const float *mean,
-                       const float *noise, float *grad_out, float *J_out, hipStream_t stream)
+                       const float *noise, float *grad_out, float *J_out, int it, float lr, float *cmd, int shift,
+                       hipStream_t stream)
 {
     const int chunks = P.n_tiles < kAdjChunks ? P.n_tiles : kAdjChunks;
     hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)chunks), dim3(kAdjWaves * kLanes), 0, stream, P, R, x0, goal,
                        mean, noise);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(kRedThreads), 0, stream, P, grad_out, J_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_adam(const ProblemDev &P, int it, float lr, hipStream_t stream)
-{
-    const int n = P.H * kDof;
-    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, P, it, lr, 0.9f,
-                       0.999f, 1e-8f);
+    hipLaunchKernelGGL(grad_step_kernel, dim3(kDof), dim3(kRedThreads), 0, stream, P, grad_out, J_out, it, lr, cmd,
+                       shift);
     return hipGetLastError();
 }
 
@@ -412,15 +424,11 @@ hipError_t launch_refine_batch(const ProblemDev *probs, int n_problems, const in
                            probs, items, R, x0s, goals);
         e = hipGetLastError();
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(grad_reduce_batch_kernel, dim3((unsigned)n_problems), dim3(kRedThreads), 0, stream,
-                           probs);
-        e = hipGetLastError();
-        if (e != hipSuccess) break;
-        hipLaunchKernelGGL(adam_batch_kernel, dim3((unsigned)n_problems), dim3(kDof * kMaxH), 0, stream, probs, it,
-                           lr, 0.9f, 0.999f, 1e-8f);
+        hipLaunchKernelGGL(grad_step_batch_kernel, dim3((unsigned)(n_problems * kDof)), dim3(kRedThreads), 0, stream,
+                           probs, it, lr, it == iterations ? cmd : nullptr, shift);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && iterations == 0) {
         hipLaunchKernelGGL(command_batch_kernel, dim3((unsigned)n_problems), dim3(256), 0, stream, probs, cmd, shift);
         e = hipGetLastError();
     }

@@ -121,15 +121,18 @@ hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int 
                                 const RobotDev &R, const float *x0s, const float *goals, int waves, int grid,
                                 hipStream_t stream);
 hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *cmd, int shift, hipStream_t stream);
-// Differentiable form: adjoint + fixed-order reduction (grad, J), Adam step on
-// the stored mean, and the command / shift of a refined mean.
+// Differentiable form: adjoint + fixed-order reduction (grad, J) per joint;
+// with it > 0 the same launch takes Adam step `it` on the stored mean, and
+// with cmd it also writes the command and the shift of the refined mean.
+// launch_command writes them for a refinement of zero steps.
 hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal, const float *mean,
-                       const float *noise, float *grad_out, float *J_out, hipStream_t stream);
-hipError_t launch_adam(const ProblemDev &P, int it, float lr, hipStream_t stream);
+                       const float *noise, float *grad_out, float *J_out, int it, float lr, float *cmd, int shift,
+                       hipStream_t stream);
 hipError_t launch_command(const ProblemDev &P, float *cmd, int shift, hipStream_t stream);
 // Batched refinement: `iterations` Adam steps on the gradient of every
-// problem (adjoint over the (problem, chunk) items, per-problem reduce and
-// Adam), then the commands cmd [P][7] and the shift.
+// problem (adjoint over the (problem, chunk) items, then reduce + Adam per
+// (problem, joint)), the last also writing the commands cmd [P][7] and the
+// shift.
 hipError_t launch_refine_batch(const ProblemDev *probs, int n_problems, const int2 *items, int n_items,
                                const RobotDev &R, const float *x0s, const float *goals, int iterations, float lr,
                                float *cmd, int shift, hipStream_t stream);
