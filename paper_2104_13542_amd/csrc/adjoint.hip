@@ -6,16 +6,16 @@
 // subgradient 0.  States are recomputed from mu and the noise, never stored.
 //
 // Per 64-lane tile (ppt particles x H steps), eight wavefronts:
-//   A   noise, controls and the forward integrator (as kernel R)
-//   B   wave 0: forward kinematics to LDS; wave 1: limit costs and their
-//       gradients with respect to q and v
+//   A   noise, controls, the forward integrator and sin/cos of q (as kernel R)
+//   B   waves 0-2: forward kinematics to LDS, one frame row each; wave 3:
+//       limit costs and their gradients with respect to q and v
 //   C   wave 0: pose cost and dC/dq through the Jacobian columns,
 //       dp/dq_k = z_k x (p - o_k) and dR/dq_k = [z_k]x R; horizon cost
 //   D   waves 0-6: the integrator backwards, two segmented suffix sums:
 //       dC/dv_k = gv_k + dt_k sum_{h>=k} gq_h,  dC/du_m = dt_m sum_{k>=m} dC/dv_k
 //   E   per (joint, step) sum over the tile's particles -> partial gradient
-// A second kernel adds the tile partials in a fixed order; a third takes an
-// Adam step (Kingma and Ba, 2015) on mu.
+// A second kernel adds the tile partials per (joint, step) in a fixed order
+// and, when refining, takes an Adam step (Kingma and Ba, 2015) on mu.
 #include "kinematics.h"
 #include "sampling.h"
 
@@ -37,6 +37,7 @@ __device__ __forceinline__ void adjoint_tile(const ProblemDev &P, const RobotDev
     __shared__ float s_q[kDof][kLanes];
     __shared__ float s_v[kDof][kLanes];
     __shared__ float s_fr[kFrames * 12][kLanes];
+    __shared__ float s_sc[2 * kDof][kLanes];  // sin q_j, cos q_j
     __shared__ float s_gl[kDof][kLanes];  // limit-cost gradient d c / d q
     __shared__ float s_gv[kDof][kLanes];  // limit and stop gradient d c / d v
     __shared__ float s_gq[kDof][kLanes];  // horizon-weighted d C / d q
@@ -73,24 +74,31 @@ __device__ __forceinline__ void adjoint_tile(const ProblemDev &P, const RobotDev
         const float q = x0[j] + segmented_scan(dt_h * v, h, H);
         s_q[j][lane] = q;
         s_v[j][lane] = v;
+        float sq, cq;
+        sincosf(q, &sq, &cq);
+        s_sc[2 * j][lane] = sq;
+        s_sc[2 * j + 1][lane] = cq;
     }
     __syncthreads();
 
-    // ---- B: kinematics | limit costs and their gradients -------------------
-    if (wave == 0) {
-        float r[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
-        float p[3] = {0.0f, 0.0f, 0.0f};
+    // ---- B: kinematics, one frame row per wave | limit costs and gradients ---
+    if (wave < 3) {
+        const int row = wave;
+        float r[3] = {row == 0 ? 1.0f : 0.0f, row == 1 ? 1.0f : 0.0f, row == 2 ? 1.0f : 0.0f};
+        float p = 0.0f;
 #pragma unroll
         for (int f = 0; f < kFrames; ++f) {
             float st = 0.0f, ct = 1.0f;
-            if (f < kDof) sincosf(s_q[f][lane], &st, &ct);
-            dh_step(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
+            if (f < kDof) {
+                st = s_sc[2 * f][lane];
+                ct = s_sc[2 * f + 1][lane];
+            }
+            dh_step_row(r, p, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) s_fr[f * 12 + c][lane] = r[c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) s_fr[f * 12 + 9 + c][lane] = p[c];
+            for (int c = 0; c < 3; ++c) s_fr[f * 12 + row * 3 + c][lane] = r[c];
+            s_fr[f * 12 + 9 + row][lane] = p;
         }
-    } else if (wave == 1) {
+    } else if (wave == 3) {
         float ej[kDof], ev[kDof], es[kDof];
         float nj = 0.0f, nv = 0.0f, ns = 0.0f;
         const float vs = tab[kTabVstop + h];
@@ -238,13 +246,26 @@ __device__ __forceinline__ void adjoint_chunk(const ProblemDev &P, const RobotDe
     if (threadIdx.x == 0) P.cost_part[c] = cacc;
 }
 
-__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(ProblemDev P, RobotDev R,
+// The fields the first loads of a tile depend on come first, as scalar
+// arguments, so that they are preloaded into SGPRs; the rest of the problem
+// follows in P.
+__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(const float *__restrict__ mean, uint32_t *last_step,
+                                                                    float *sigma2, const float *halton,
+                                                                    const float *tables, int32_t N, int32_t H,
+                                                                    int32_t ppt, ProblemDev P, RobotDev R,
                                                                     const float *__restrict__ x0,
                                                                     const float *__restrict__ goal,
-                                                                    const float *__restrict__ mean,
                                                                     const float *__restrict__ noise)
 {
-    adjoint_chunk(P, R, blockIdx.x, x0, goal, mean, noise);
+    ProblemDev Q = P;
+    Q.last_step = last_step;
+    Q.sigma2 = sigma2;
+    Q.halton = halton;
+    Q.tables = tables;
+    Q.N = N;
+    Q.H = H;
+    Q.ppt = ppt;
+    adjoint_chunk(Q, R, blockIdx.x, x0, goal, mean, noise);
 }
 
 // Batched form: workgroup k takes chunk items[k] = (problem, chunk).
@@ -399,8 +420,8 @@ hipError_t launch_grad(const ProblemDev &P, const RobotDev &R, const float *x0, 
                        hipStream_t stream)
 {
     const int chunks = P.n_tiles < kAdjChunks ? P.n_tiles : kAdjChunks;
-    hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)chunks), dim3(kAdjWaves * kLanes), 0, stream, P, R, x0, goal,
-                       mean, noise);
+    hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)chunks), dim3(kAdjWaves * kLanes), 0, stream, mean, P.last_step,
+                       P.sigma2, P.halton, P.tables, P.N, P.H, P.ppt, P, R, x0, goal, noise);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grad_step_kernel, dim3(kDof), dim3(kRedThreads), 0, stream, P, grad_out, J_out, it, lr, cmd,
