@@ -130,3 +130,33 @@ def test_self_colliding_start(oracle_lib, q0):
     g, ro, up, o, _ = run_pair(prob, oracle_lib)
     _config2_checks(g, ro, o, prob)
     assert np.mean(ro["terms"][..., 6] > 0) > 0.2, "the start should self-collide often"
+
+
+def _odd_sphere_model():
+    """32 spheres with 3, 5, 1, 7, 2, 6, 5, 3 per body, taken (cycling, with a
+    1 cm shift on repeats) from the rows of the 52-sphere model: pair groups
+    of one to four spheres and odd partner ranges (3 and 9 partners)."""
+    base = inputs.panda_spheres()
+    counts = [3, 5, 1, 7, 2, 6, 5, 3]
+    rows = []
+    for b, n in enumerate(counts, start=1):
+        own = base[base[:, 0] == b]
+        for k in range(n):
+            r = own[k % len(own)].copy()
+            r[3] += 0.01 * (k // len(own))
+            rows.append(r)
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("q0", [[0.794, -0.812, -2.66, -3.022, 1.815, 3.424, 0.618],
+                                [1.638, 1.227, 0.041, -3.039, 0.047, 1.228, 0.314]])
+def test_self_collision_odd_groups(oracle_lib, q0):
+    """A sphere model whose self-collision groups hold one to four spheres and
+    whose partner ranges have odd lengths, so that the kernel's last round of
+    a group tests a single partner; folded starts so that pairs penetrate."""
+    prob = inputs.config2(27, n_particles=96, horizon=30, n_obs_spheres=6, n_obs_cuboids=4)
+    prob.spheres = _odd_sphere_model()
+    prob.q0 = np.array(q0)
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    _config2_checks(g, ro, o, prob)
+    assert np.mean(ro["terms"][..., 6] > 0) > 0.05, "the start should self-collide"
