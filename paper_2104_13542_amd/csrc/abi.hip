@@ -328,7 +328,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
 
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
     float *self_thr, *grad_part, *cost_part, *grad, *adam;
-    float4 *sph_obs, *env_sph, *obs_bound, *sph_local;
+    float4 *sph_obs, *obs_bound, *sph_local;
     int32_t *sph_body, *self_off;
     int4 *self_seg;
     uint32_t *counters;
@@ -343,7 +343,6 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &tables, storm::kTabSize));
     STORM_TRY(dalloc(c, &halton, (size_t)STORM_DOF * params->n_halton * H));
     STORM_TRY(dalloc(c, &sph_obs, (size_t)n_sph_obs));
-    STORM_TRY(dalloc(c, &env_sph, (size_t)n_sph_obs * robot->n_spheres));
     STORM_TRY(dalloc(c, &box_obs, (size_t)16 * n_box_obs));
     STORM_TRY(dalloc(c, &obs_bound, (size_t)n_obs));
     STORM_TRY(dalloc(c, &mean, (size_t)H * STORM_DOF));
@@ -393,7 +392,6 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         P.tables = tables;
         P.halton = halton;
         P.sph_obs = sph_obs;
-        P.env_sph = env_sph;
         P.box_obs = box_obs;
         P.obs_bound = obs_bound;
         P.mean = mean;
@@ -415,8 +413,8 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         c->R.self_off = self_off;
         STORM_TRY(storm::launch_init_tables(P, dt_raw, lim_raw, params->acc_stop, params->gamma, params->w_term,
                                             params->k_jl, params->k_vl, sig_raw, params->n_knots, obs_raw, n_obs,
-                                            sph_obs, env_sph, box_obs, obs_bound, sph_raw_d, robot->n_spheres,
-                                            reach_bound(robot), sph_local, sph_body, s));
+                                            sph_obs, box_obs, obs_bound, sph_raw_d, robot->n_spheres, sph_local,
+                                            sph_body, s));
         STORM_TRY(hipStreamSynchronize(s));
     }
 #undef STORM_TRY

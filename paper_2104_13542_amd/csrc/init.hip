@@ -43,15 +43,14 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
 }
 
 // Geometry records in device form, one flat index space over all of them.
-//   sphere obstacles: (centre, radius) and, for every body sphere s, the
-//                     record (centre, (r_s + r_o)^2) used by the penetration test
+//   sphere obstacles: (centre, radius)
+//   all obstacles:    the culling ball (centre, bounding radius + margin)
 //   cuboids:          the world-to-box map l = M x + t with M = R^T,
 //                     t = -R^T c, then the half extents
 //   body spheres:     (local centre, radius) and the frame index
-//   self pairs:       (r_s + r_t)^2 for every sphere pair
 __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float *box_raw, int n_bo,
-                                float4 *sph_obs, float4 *env_sph, float *box_obs, float4 *obs_bound,
-                                const float *sph_raw, int S, double reach, float4 *sph_local, int32_t *sph_body)
+                                float4 *sph_obs, float *box_obs, float4 *obs_bound, const float *sph_raw, int S,
+                                float4 *sph_local, int32_t *sph_body)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_so) {
@@ -70,24 +69,6 @@ __global__ void geometry_kernel(const float *sph_obs_raw, int n_so, const float 
         const double rad = sphere ? (double)r[4]
                                   : sqrt((double)r[4] * r[4] + (double)r[5] * r[5] + (double)r[6] * r[6]);
         obs_bound[t] = make_float4(r[1], r[2], r[3], (float)(rad + 1e-4));
-    }
-    if (t < S * n_so) {
-        // test record of (body sphere s, obstacle o) for the expanded form
-        // |x|^2 - 2 c.x + |c|^2 < (r_s + r_o)^2: (-2c, (r_s + r_o)^2 - |c|^2 +
-        // slack).  The FP32 evaluation (two three-term FMA chains and the
-        // rounded record) errs by less than 2^-21 (|x| + |c| + r_s + r_o)^2;
-        // the slack is eight times that with |x| bounded by the robot's
-        // reach, so the test has no false negatives.  Hits are resolved with
-        // the exact distance.
-        const int s = t / n_so, o = t - s * n_so;
-        const float *r = sph_obs_raw + o * STORM_OBSTACLE_STRIDE;
-        const double cx = r[1], cy = r[2], cz = r[3];
-        const double c2 = cx * cx + cy * cy + cz * cz;
-        const double rr = (double)sph_raw[s * 5 + 4] + (double)r[4];
-        const double span = reach + sqrt(c2) + rr;
-        const double slack = ldexp(span * span, -18);
-        env_sph[t] = make_float4((float)(-2.0 * cx), (float)(-2.0 * cy), (float)(-2.0 * cz),
-                                 (float)(rr * rr - c2 + slack));
     }
     if (t < n_bo) {
         const float *r = box_raw + t * STORM_OBSTACLE_STRIDE;
@@ -201,9 +182,8 @@ __global__ void halton_smooth_kernel(int n_halton, int K, int H, const double *Z
 
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
-                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
-                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres,
-                              double reach, float4 *d_sph_local,
+                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
+                              float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
                               int32_t *d_sph_body, hipStream_t stream)
 {
     (void)n_obs;
@@ -214,13 +194,12 @@ hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const 
     // d_obs_raw holds the sphere records first, then the cuboid records
     const int S = n_spheres, n_so = P.n_sph_obs, n_bo = P.n_box_obs;
     int ng = S;
-    if (S * n_so > ng) ng = S * n_so;
     if (n_so + n_bo > ng) ng = n_so + n_bo;
     const int gthreads = 256;
     const int gblocks = ng > 0 ? (ng + gthreads - 1) / gthreads : 1;
     hipLaunchKernelGGL(geometry_kernel, dim3(gblocks), dim3(gthreads), 0, stream, d_obs_raw, n_so,
-                       d_obs_raw + (size_t)STORM_OBSTACLE_STRIDE * n_so, n_bo, d_sph_obs, d_env_sph, d_box_obs,
-                       d_obs_bound, d_sph_raw, S, reach, d_sph_local, d_sph_body);
+                       d_obs_raw + (size_t)STORM_OBSTACLE_STRIDE * n_so, n_bo, d_sph_obs, d_box_obs, d_obs_bound,
+                       d_sph_raw, S, d_sph_local, d_sph_body);
     e = hipGetLastError();
     if (e != hipSuccess || P.n_halton == 0) return e;
     double *Z = nullptr;

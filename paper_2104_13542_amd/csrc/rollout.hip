@@ -260,7 +260,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // only when some lane of the wave touches one of them.
     float env = 0.0f, selfpen = 0.0f;
     if (mask & STORM_COST_ENV) {
-        const STORM_CONST_AS float *esph = uniform_ptr(reinterpret_cast<const float *>(P.env_sph));
         const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
         const STORM_CONST_AS float *box = uniform_ptr(P.box_obs);
         const STORM_CONST_AS float *sloc = uniform_ptr(reinterpret_cast<const float *>(R.sph_local));
@@ -271,7 +270,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             const float z = s_cen[(s * 3 + 2) * kLanes + lane];
             const float rs = sloc[4 * s + 3];
             const float rs2 = rs * rs;
-            const float xs2 = fmaf(x, x, fmaf(y, y, z * z));
             // Broad phase: the wave's 64 centres of this sphere lie in the
             // ball of radius rad about lane 0's centre; by the triangle
             // inequality an obstacle whose bounding ball is farther than
@@ -296,19 +294,16 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                     const int o = o0 + (int)__builtin_ctzll(cand);
                     cand &= cand - 1;
                     if (o < nso) {
-                        // |x|^2 - 2 c.x + |c|^2 against the record's threshold;
-                        // lanes that pass get the exact penetration
-                        // (r_s + r_o) - |x - c|, which a rounding near-miss
-                        // leaves at or below zero
-                        const STORM_CONST_AS float *ob = esph + (size_t)4 * (s * nso + o);
-                        const float a = fmaf(x, ob[0], fmaf(y, ob[1], fmaf(z, ob[2], xs2)));
-                        const bool hit = a < ob[3];
-                        if (__builtin_amdgcn_ballot_w64(hit) != 0) {
-                            const STORM_CONST_AS float *so = sob + 4 * o;
-                            const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
-                            const float pen = (rs + so[3]) - fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                            if (hit) best = fmaxf(best, pen);
-                        }
+                        // the direct squared distance (no cancellation) against
+                        // the squared contact distance, from the obstacle's own
+                        // 16-byte record; where a lane touches, the penetration
+                        // (r_s + r_o) - |x - c| at every lane (at or below zero
+                        // where a lane does not touch)
+                        const STORM_CONST_AS float *so = sob + 4 * o;
+                        const float dx = x - so[0], dy = y - so[1], dz = z - so[2];
+                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float rc = rs + so[3];
+                        if (__builtin_amdgcn_ballot_w64(d2 < rc * rc) != 0) best = fmaxf(best, rc - fast_sqrt(d2));
                     } else {
                         const STORM_CONST_AS float *bb = box + (size_t)(o - nso) * 16;
                         const float lx = fmaf(bb[0], x, fmaf(bb[1], y, fmaf(bb[2], z, bb[9])));

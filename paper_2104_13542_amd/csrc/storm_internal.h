@@ -44,7 +44,6 @@ struct ProblemDev {
     const float *tables;    // [kTabSize]
     const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
     const float4 *sph_obs;  // [n_sph_obs] centre, radius
-    const float4 *env_sph;  // [S][n_sph_obs] -2 c_o, (r_s + r_o)^2 - |c_o|^2 + slack for body sphere s
     const float *box_obs;   // [n_box_obs][16]: M = R^T (9, row-major), t = -R^T c (3), half extents (3), pad
     const float4 *obs_bound;  // [n_sph_obs + n_box_obs] centre, culling radius (bounding sphere + 1e-4 m)
     float *mean;            // [H][7]
@@ -104,9 +103,8 @@ struct StepOut {
 // Launchers (defined in the .hip translation units).
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
-                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float4 *d_env_sph,
-                              float *d_box_obs, float4 *d_obs_bound, const float *d_sph_raw, int n_spheres,
-                              double reach, float4 *d_sph_local,
+                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
+                              float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
                               int32_t *d_sph_body, hipStream_t stream);
 hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,
                           const float *noise, const StepOut &out, int waves, hipStream_t stream);
