@@ -109,10 +109,19 @@ def cpu_baseline(prob, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
+    model = "unknown CPU"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": p.n_particles * p.horizon * steps / el,
         "unit": "rollout-steps/s",
         "cores": 1,
+        "host": "%s, %d cores available to the process" % (model, len(os.sched_getaffinity(0))),
         "kind": "oracle",
         "sample": "%d whole steps (noise + rollout + update) of the N=%d H=%d workload, %.1f s, 1 thread"
                   % (steps, p.n_particles, p.horizon, el),
