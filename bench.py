@@ -220,6 +220,60 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
     }
 
 
+def mixed_bench(seed, steps, warmup):
+    """The STORM-shaped step with the paper's "mixed" sampling: 0.6 N Halton +
+    B-spline particles and 0.4 N Gaussian particles smoothed by the comb
+    filter (coefficients 0.4, 0.4, 0.2), every cost term; the step (eager
+    and one graph launch) and the rollout kernel alone, back to back."""
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    prob = inputs.config2(seed)
+    p = prob.params
+    N, H = p.n_particles, p.horizon
+    p.n_halton = int(0.6 * N)
+    p.comb_filter = 1
+    p.comb = (0.4, 0.4, 0.2)
+    r = storm.Rollout(prob)
+    qg = torch.tensor(prob.q_goal, dtype=torch.float32, device="cuda").reshape(1, 7)
+    goal = storm.fk(qg)[0][0].contiguous()
+    C = torch.empty(N, dtype=torch.float32, device="cuda")
+    cmd = torch.empty(7, dtype=torch.float32, device="cuda")
+    x0 = r.x0.clone()
+    graph = r.graph(x0, goal, cmd, iterations=1, shift=True)
+
+    def eager_step():
+        r.step(goal, x0=x0, C=C)
+        r.update(shift=True, want_mean=False, cmd=cmd)
+
+    for _ in range(warmup):
+        graph.launch()
+        eager_step()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn in (("graph", graph.launch), ("eager", eager_step), ("rollout", lambda: r.step(goal, x0=x0, C=C))):
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            fn()
+        end.record()
+        torch.cuda.synchronize()
+        res[name] = start.elapsed_time(end) / steps
+    graph.close()
+    r.close()
+    ms = min(res["graph"], res["eager"])
+    return {
+        "workload": "N=500 (300 Halton + B-spline, 200 comb-filtered Gaussian, c = 0.4, 0.4, 0.2), H=30, "
+                    "all cost terms, 30 sphere + 20 cuboid obstacles",
+        "ms_per_step": ms,
+        "rollout_steps_per_s": N * H / (ms * 1e-3),
+        "rollout_kernel_us": res["rollout"] * 1e3,
+    }
+
+
 def differentiable_bench(steps, latency_steps, warmup):
     """Differentiable form on the N=1024, H=30 workload (pose + joint-limit
     costs): a control step with 3 Adam refinement steps of the mean (one
@@ -424,6 +478,7 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=256, help="batched workload size (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-latency-steps", type=int, default=1000)
+    ap.add_argument("--mixed-steps", type=int, default=500, help="mixed-sampling steps (0 = skip)")
     ap.add_argument("--diff-steps", type=int, default=200, help="differentiable-form steps (0 = skip)")
     ap.add_argument("--large-problems", type=int, default=64, help="large workload size (0 = skip)")
     ap.add_argument("--large-steps", type=int, default=100)
@@ -587,6 +642,9 @@ def main():
         line["batched"] = batched_bench(args.batch_problems, args.batch_steps, args.batch_latency_steps,
                                         warmup=5, tune_reps=3)
         progress("batched workload done")
+    if args.mixed_steps > 0:
+        line["mixed"] = mixed_bench(args.seed, args.mixed_steps, warmup=50)
+        progress("mixed-sampling workload done")
     if args.diff_steps > 0:
         line["differentiable"] = differentiable_bench(args.diff_steps, args.diff_steps, warmup=10)
         progress("differentiable workload done")

@@ -112,6 +112,13 @@ typedef struct storm_params {
     float a_stop, a_joint, a_vel, a_manip, a_coll; /* Eq. 15 weights */
     uint32_t grad_mask;  /* terms of the differentiable form (storm_rollout_grad / refine): a subset of
                             POSE | JOINT | VEL | STOP; 0 = cost_mask, which must then be such a subset */
+    int32_t comb_filter; /* 1: the comb filter of Sec. 3.3 smooths the noise of the Gaussian (Philox)
+                            particles along the horizon, per joint, in step order:
+                            e'_h = comb[0] e_h + comb[1] e'_{h-1} + comb[2] e'_{h-2}, e'_{-1} = e'_{-2} = 0,
+                            and u = mu + sigma e'.  With n_halton = 0.6 N this is the paper's "mixed"
+                            sampling (B-spline and comb particles).  Halton particles, null particles and
+                            a noise override are not filtered.  0: no filter */
+    float comb[3];       /* comb filter coefficients c1, c2, c3, finite */
 } storm_params;
 
 /* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame

@@ -48,7 +48,7 @@ class OracleParams(ctypes.Structure):
         ("alpha_pos", ctypes.c_double * 3), ("alpha_rot", ctypes.c_double * 3),
         ("a_stop", ctypes.c_double), ("a_joint", ctypes.c_double), ("a_vel", ctypes.c_double),
         ("a_manip", ctypes.c_double), ("a_coll", ctypes.c_double),
-        ("cost_mask", ctypes.c_uint32), ("pad1", ctypes.c_uint32),
+        ("cost_mask", ctypes.c_uint32), ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_double * 3),
     ]
 
 
@@ -252,6 +252,9 @@ class Oracle:
             p.alpha_rot[k] = float(pr.alpha_rot[k])
         p.a_stop, p.a_joint, p.a_vel, p.a_manip, p.a_coll = pr.a_stop, pr.a_joint, pr.a_vel, pr.a_manip, pr.a_coll
         p.cost_mask = pr.cost_mask
+        p.comb_filter = int(getattr(pr, "comb_filter", 0))
+        for k, c in enumerate(getattr(pr, "comb", (1.0, 0.0, 0.0))):
+            p.comb[k] = float(c)
         self.params = p
 
         self.dh = _f64(inputs.PANDA_DH if dh is None else dh)

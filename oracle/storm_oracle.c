@@ -10,7 +10,8 @@
  * Each step is written out as the paper states it, in double precision, with
  * no blocking, fusion or reordering:
  *   sampling        Sec. 3.3 (Halton sequence, cubic B-spline smoothing,
- *                   per-joint covariance, null particles) plus Gaussian noise
+ *                   per-joint covariance, null particles, comb filter) plus
+ *                   Gaussian noise
  *   integrator      Sec. 3.1, Eq. 7
  *   kinematics      Sec. 3.1, Eq. 8 (FK and geometric Jacobian)
  *   running cost    Sec. 3.2, Eq. 9-15
@@ -59,7 +60,9 @@ typedef struct {
     double w_pos, w_rot;
     double alpha_pos[3], alpha_rot[3];
     double a_stop, a_joint, a_vel, a_manip, a_coll;
-    uint32_t cost_mask, pad1;
+    uint32_t cost_mask;
+    int32_t comb_filter; /* 1: comb-filter the Gaussian particles' noise (Sec. 3.3) */
+    double comb[3];      /* c1, c2, c3 */
 } oracle_params;
 
 typedef struct {
@@ -253,8 +256,25 @@ int oracle_halton_noise(int n_halton, int H, int K, double *eps)
     return 0;
 }
 
+/* Comb filter (Sec. 3.3) of one joint's noise sequence x_0 .. x_{H-1}
+ * (stride DOF), applied in step order and in place, so that the earlier
+ * terms are already filtered: x'_h = c1 x_h + c2 x'_{h-1} + c3 x'_{h-2} with
+ * x'_{-1} = x'_{-2} = 0.  The paper prints the third term with the index of
+ * the second; it is read as the step before that. */
+static void comb_filter(int H, const double c[3], double *x)
+{
+    double p1 = 0.0, p2 = 0.0;
+    for (int h = 0; h < H; ++h) {
+        const double y = c[0] * x[(size_t)h * DOF] + c[1] * p1 + c[2] * p2;
+        x[(size_t)h * DOF] = y;
+        p2 = p1;
+        p1 = y;
+    }
+}
+
 /* Full standard-noise tensor eps[N][H][7] for control step `step`: Halton
- * particles first, then Gaussian particles, then null particles (zero). */
+ * particles first, then Gaussian particles (comb-filtered when enabled),
+ * then null particles (zero). */
 int oracle_noise(const oracle_params *p, uint32_t step, double *eps)
 {
     int N = p->n, H = p->h;
@@ -269,6 +289,9 @@ int oracle_noise(const oracle_params *p, uint32_t step, double *eps)
             else
                 oracle_gauss7(p->seed, step, (uint32_t)i, (uint32_t)h, e);
         }
+    if (p->comb_filter)
+        for (int i = p->n_halton; i < N - p->n_null; ++i)
+            for (int j = 0; j < DOF; ++j) comb_filter(H, p->comb, eps + (size_t)i * H * DOF + j);
     return 0;
 }
 

@@ -69,6 +69,9 @@ int32_t validate_params(const storm_params *p)
     if (p->n_halton > 0 && (p->n_knots < 4 || p->n_knots > 32)) return STORM_E_RANGE;
     if (p->cost_mask & ~STORM_COST_ALL) return STORM_E_PARAM;
     if (p->grad_mask & ~(STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP)) return STORM_E_PARAM;
+    if (p->comb_filter != 0 && p->comb_filter != 1) return STORM_E_PARAM;
+    for (int c = 0; c < 3; ++c)
+        if (!finite_f(p->comb[c])) return STORM_E_PARAM;
     if (!p->dt) return STORM_E_NULL;
     for (int h = 0; h < p->horizon; ++h)
         if (!finite_f(p->dt[h]) || !(p->dt[h] > 0.0f)) return STORM_E_PARAM;
@@ -289,6 +292,8 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
             obs_sorted.insert(obs_sorted.end(), r, r + STORM_OBSTACLE_STRIDE);
             if (is_sphere) ++n_sph_obs; else ++n_box_obs;
         }
+    const float comb[3] = {params->comb_filter ? params->comb[0] : 1.0f, params->comb_filter ? params->comb[1] : 0.0f,
+                           params->comb_filter ? params->comb[2] : 0.0f};
     std::vector<int> seg, seg_off;
     const int n_pairs = storm::self_segments(robot, c->waves, seg, seg_off);
     const std::vector<float> thr = storm::self_thresholds(robot, reach_bound(robot));
@@ -298,6 +303,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     P.N = N;
     P.H = H;
     P.n_halton = params->n_halton;
+    P.comb = params->comb_filter ? 1u : 0u;
     P.n_null = params->n_null;
     P.n_sph_obs = n_sph_obs;
     P.n_box_obs = n_box_obs;
@@ -412,7 +418,8 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         c->R.self_seg = self_seg;
         c->R.self_off = self_off;
         STORM_TRY(storm::launch_init_tables(P, dt_raw, lim_raw, params->acc_stop, params->gamma, params->w_term,
-                                            params->k_jl, params->k_vl, sig_raw, params->n_knots, obs_raw, n_obs,
+                                            params->k_jl, params->k_vl, sig_raw, comb, params->n_knots, obs_raw,
+                                            n_obs,
                                             sph_obs, box_obs, obs_bound, sph_raw_d, robot->n_spheres, sph_local,
                                             sph_body, s));
         STORM_TRY(hipStreamSynchronize(s));

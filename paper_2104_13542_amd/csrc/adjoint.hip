@@ -68,8 +68,15 @@ __device__ __forceinline__ void adjoint_tile(const ProblemDev &P, const RobotDev
     __syncthreads();
     if (wave < kDof) {
         const int j = wave;
+        float e = s_eps[j][lane];
+        // the comb filter on the sampled Gaussian particles' noise, as in kernel R
+        const bool comb = P.comb && noise == nullptr && live && i >= P.n_halton;
+        if (__builtin_amdgcn_ballot_w64(comb) != 0) {
+            const float f = comb_noise(&s_eps[j][0], lane, h, H, tab);
+            if (comb) e = f;
+        }
         float u = 0.0f;
-        if (live) u = fmaf(sqrtf(P.sigma2[j]), s_eps[j][lane], mean[h * kDof + j]);
+        if (live) u = fmaf(sqrtf(P.sigma2[j]), e, mean[h * kDof + j]);
         const float v = x0[kDof + j] + segmented_scan(dt_h * u, h, H);
         const float q = x0[j] + segmented_scan(dt_h * v, h, H);
         s_q[j][lane] = q;

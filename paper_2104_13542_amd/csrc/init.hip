@@ -12,7 +12,8 @@ namespace {
 // (Eq. 2: gamma^h, terminal step scaled by w_term), band-shrunk position and
 // velocity limits (Eq. 11), initial mean 0 and variance sigma_init^2.
 __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, const float *lim_raw, float acc_stop,
-                              float gamma, float w_term, float k_jl, float k_vl, const float *sigma_init)
+                              float gamma, float w_term, float k_jl, float k_vl, const float *sigma_init, float c1,
+                              float c2, float c3)
 {
     const int t = threadIdx.x;
     const int H = P.H;
@@ -39,6 +40,16 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
         *P.step = 0u;
         *P.status = 0u;
         *P.last_step = 0u;
+        // comb filter (Sec. 3.3) as a convolution: e'_h = sum_{k <= h} g_k e_{h-k}
+        // with g_k = c1 r_k, r the impulse response of r_k = c2 r_{k-1} + c3 r_{k-2}
+        // (zero past H: the kernels read the response in batches of eight)
+        double r1 = 0.0, r2 = 0.0;
+        for (int k = 0; k < kMaxH; ++k) {
+            const double r = k == 0 ? 1.0 : (double)c2 * r1 + (double)c3 * r2;
+            tables[kTabComb + k] = k < H ? (float)((double)c1 * r) : 0.0f;
+            r2 = r1;
+            r1 = r;
+        }
     }
 }
 
@@ -182,13 +193,13 @@ __global__ void halton_smooth_kernel(int n_halton, int K, int H, const double *Z
 
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
-                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
+                              const float comb[3], int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
                               float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
                               int32_t *d_sph_body, hipStream_t stream)
 {
     (void)n_obs;
     hipLaunchKernelGGL(tables_kernel, dim3(1), dim3(kMaxH), 0, stream, P, const_cast<float *>(P.tables), d_dt_raw,
-                       d_lim_raw, acc_stop, gamma, w_term, k_jl, k_vl, d_sigma_init);
+                       d_lim_raw, acc_stop, gamma, w_term, k_jl, k_vl, d_sigma_init, comb[0], comb[1], comb[2]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // d_obs_raw holds the sphere records first, then the cuboid records

@@ -118,8 +118,15 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // ---- A1: controls and the triple integrator (Eq. 7) ---------------------
     if (wave < kDof) {
         const int j = wave;
+        float e = s_eps[j * kLanes + lane];
+        // the comb filter on the sampled Gaussian particles' noise (Sec. 3.3)
+        const bool comb = P.comb && noise == nullptr && live && i >= P.n_halton;
+        if (__builtin_amdgcn_ballot_w64(comb) != 0) {
+            const float f = comb_noise(s_eps + j * kLanes, lane, h, H, tab);
+            if (comb) e = f;
+        }
         float u = 0.0f;
-        if (live) u = fmaf(sig_j, s_eps[j * kLanes + lane], mu_j);
+        if (live) u = fmaf(sig_j, e, mu_j);
         const float v = v0_j + segmented_scan(dt_h * u, h, H);
         const float q = q0_j + segmented_scan(dt_h * v, h, H);
         s_q[j * kLanes + lane] = q;

@@ -95,6 +95,30 @@ __device__ __forceinline__ float segmented_suffix_scan(float x, int h, int H)
     return x;
 }
 
+// Comb-filtered noise of one joint at step h (Sec. 3.3), from that joint's
+// row of standard noise over the tile's lanes: the filter's recursion in
+// step order written as its convolution, sum over k <= h of g_k e_{h-k},
+// with the response g in the tables; e_{h-k} is the lane k below, in the
+// same particle.
+__device__ __forceinline__ float comb_noise(const float *row, int lane, int h, int H,
+                                            const float *__restrict__ tab)
+{
+    // eight terms per batch, every read of a batch in flight at once (the
+    // response is zero past H, and within the table's kMaxH entries)
+    float acc = 0.0f;
+    for (int k0 = 0; k0 < H; k0 += 8) {
+        float g[8], e[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            g[m] = tab[kTabComb + k0 + m];
+            e[m] = k0 + m <= h ? row[lane - k0 - m] : 0.0f;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc = fmaf(g[m], e[m], acc);
+    }
+    return acc;
+}
+
 // Standard noise of joints 4k..4k+3 for one (particle, step) point from the
 // override, the Halton table or Philox (k = 0 or 1).
 __device__ __forceinline__ void standard_noise4(const ProblemDev &P, const float *__restrict__ noise, int k, int i,

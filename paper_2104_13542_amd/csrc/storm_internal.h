@@ -29,7 +29,8 @@ constexpr int kTabJlo = 192;        // band-shrunk joint position limits [7]
 constexpr int kTabJhi = 200;
 constexpr int kTabVlo = 208;        // band-shrunk joint velocity limits [7]
 constexpr int kTabVhi = 216;
-constexpr int kTabSize = 224;
+constexpr int kTabComb = 224;        // comb filter response g_k (e'_h = sum_k g_k e_{h-k}) [H]
+constexpr int kTabSize = 288;
 
 
 // Per-problem description read by the kernels.  All pointers are device memory.
@@ -40,7 +41,8 @@ struct ProblemDev {
     float beta, alpha_mu, alpha_sigma, sigma2_min;
     float k_m, w_pos, w_rot, a_stop;
     float a_joint, a_vel, a_manip, a_coll;
-    float alpha_pos[3], alpha_rot[3], pad1[2];
+    float alpha_pos[3], alpha_rot[3];
+    uint32_t comb, pad1;  // comb: the Gaussian particles' noise is comb-filtered (response in the tables)
     const float *tables;    // [kTabSize]
     const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
     const float4 *sph_obs;  // [n_sph_obs] centre, radius
@@ -103,7 +105,8 @@ struct StepOut {
 // Launchers (defined in the .hip translation units).
 hipError_t launch_init_tables(const ProblemDev &P, const float *d_dt_raw, const float *d_lim_raw, float acc_stop,
                               float gamma, float w_term, float k_jl, float k_vl, const float *d_sigma_init,
-                              int n_knots, const float *d_obs_raw, int n_obs, float4 *d_sph_obs, float *d_box_obs,
+                              const float comb[3], int n_knots, const float *d_obs_raw, int n_obs,
+                              float4 *d_sph_obs, float *d_box_obs,
                               float4 *d_obs_bound, const float *d_sph_raw, int n_spheres, float4 *d_sph_local,
                               int32_t *d_sph_body, hipStream_t stream);
 hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,

@@ -131,6 +131,8 @@ class Params:
     a_coll: float = 1000.0
     cost_mask: int = COST_POSE | COST_JOINT
     grad_mask: int = 0  # terms of the differentiable form; 0 = cost_mask
+    comb_filter: int = 0  # 1: comb-filter the Gaussian particles' noise along the horizon (Sec. 3.3)
+    comb: tuple = (1.0, 0.0, 0.0)  # (c1, c2, c3): e'_h = c1 e_h + c2 e'_{h-1} + c3 e'_{h-2}
 
 
 @dataclasses.dataclass

@@ -54,6 +54,7 @@ class storm_params(ctypes.Structure):
         ("alpha_pos", ctypes.c_float * 3), ("alpha_rot", ctypes.c_float * 3),
         ("a_stop", ctypes.c_float), ("a_joint", ctypes.c_float), ("a_vel", ctypes.c_float),
         ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float), ("grad_mask", ctypes.c_uint32),
+        ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_float * 3),
     ]
 
 
@@ -166,6 +167,10 @@ def make_params(p: "inputs.Params"):
     sp.n_halton, sp.n_null, sp.n_knots = p.n_halton, p.n_null, p.n_knots
     sp.cost_mask, sp.seed = p.cost_mask, p.seed
     sp.grad_mask = getattr(p, "grad_mask", 0)
+    sp.comb_filter = int(getattr(p, "comb_filter", 0))
+    comb = getattr(p, "comb", (1.0, 0.0, 0.0))
+    for c in range(3):
+        sp.comb[c] = float(comb[c])
     dt = np.ascontiguousarray(p.dt, dtype=np.float32)
     sp.dt = dt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     for j in range(DOF):

@@ -77,6 +77,7 @@ def test_init_validation(storm):
         ("k_jl", 0.5, E.STORM_E_PARAM), ("sigma2_min", -1.0, E.STORM_E_PARAM),
         ("cost_mask", 0x80, E.STORM_E_PARAM), ("w_pos", float("inf"), E.STORM_E_PARAM),
         ("grad_mask", 0x40, E.STORM_E_PARAM), ("grad_mask", 0x10, E.STORM_E_PARAM),
+        ("comb_filter", 2, E.STORM_E_PARAM), ("comb_filter", -1, E.STORM_E_PARAM),
     ]
     for field, val, want in cases:
         sp2, rb2, sc2, keep2 = _args(storm)
@@ -91,6 +92,10 @@ def test_init_validation(storm):
     sp2, rb2, sc2, keep2 = _args(storm)
     sp2.dt = None
     assert _init(storm, sp2, rb2, sc2) == E.STORM_E_NULL
+    sp2, rb2, sc2, keep2 = _args(storm)
+    sp2.comb_filter = 1
+    sp2.comb[1] = float("nan")  # comb filter coefficients must be finite
+    assert _init(storm, sp2, rb2, sc2) == E.STORM_E_PARAM
 
 
 def test_robot_and_scene_validation(storm):

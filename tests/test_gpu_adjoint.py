@@ -123,6 +123,38 @@ def test_grad_uses_last_step_noise(oracle_lib):
         r.close()
 
 
+def test_grad_comb_filtered_noise(oracle_lib):
+    """The adjoint recomputes the comb-filtered noise (Sec. 3.3) of the last
+    step exactly as the rollout drew it; mixed Halton and comb particles."""
+    from paper_2104_13542_amd import storm
+
+    N, H = 96, 30
+    prob = inputs.config4(4)
+    prob.params.n_particles, prob.params.horizon = N, H
+    prob.params.dt = np.full(H, 0.02)
+    prob.params.n_halton = 37
+    prob.params.n_knots = 8
+    prob.params.comb_filter = 1
+    prob.params.comb = (0.4, 0.4, 0.2)
+    prob.q0 = np.array([2.5, 1.5, -2.4, -2.9, 2.4, 3.5, 2.5])
+    prob.v0 = np.array([1.9, -1.9, 1.2, 0.0, 2.3, -2.3, 1.0])
+    o = _oracle(oracle_lib, prob)
+    mean = f32(np.random.default_rng(4).normal(size=(H, 7)) * 0.5)
+    r = storm.Rollout(prob)
+    try:
+        goal = _dev(o.goal)
+        r.step(goal)
+        g, J = r.grad(_dev(mean), goal)
+        torch.cuda.synchronize()
+        eps = o.noise(0)
+        _, sig2, _ = r.get_state()
+        g_ref, J_ref = o.grad(mean, np.sqrt(sig2.astype(np.float64)), eps)
+        assert abs(J.item() - J_ref) <= 1e-4 * abs(J_ref)
+        assert np.linalg.norm(g.cpu().double().numpy() - g_ref) <= 1e-3 * np.linalg.norm(g_ref)
+    finally:
+        r.close()
+
+
 def test_refine_matches_oracle_adam(oracle_lib):
     from paper_2104_13542_amd import storm
 

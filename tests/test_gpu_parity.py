@@ -96,6 +96,37 @@ def test_config1_philox_noise(oracle_lib, seed):
     assert np.all(np.abs(g["mean"] - up["mean"]) <= TOL_MEAN + 2.0 * bound)
 
 
+@pytest.mark.parametrize("c,H", [((0.4, 0.4, 0.2), 16), ((1.0, -0.5, 0.25), 16), ((0.5, 0.3, 0.2), 64)])
+def test_config1_comb_filter(oracle_lib, c, H):
+    """Comb-filtered Gaussian noise (Sec. 3.3): the kernel's convolution with
+    the filter's response against the oracle's recursion in step order; null
+    particles stay unfiltered (and zero)."""
+    prob = inputs.config1(2, v0_random=True)
+    prob.params.horizon = H
+    prob.params.dt = np.full(H, 0.02)
+    prob.params.n_null = 3
+    prob.params.comb_filter = 1
+    prob.params.comb = c
+    g, ro, up, o, eps = run_pair(prob, oracle_lib)
+    assert_states(g, ro)
+    assert np.max(cost_error(g["c"], ro["c"])) <= TOL_COST_REL
+    assert np.max(cost_error(g["C"], ro["C"])) <= TOL_COST_REL
+    bound = _update_bound(ro, up, g["C"], prob.params.beta)
+    assert np.all(np.abs(g["mean"] - up["mean"]) <= TOL_MEAN + 2.0 * bound)
+
+
+def test_config2_mixed_sampling(oracle_lib):
+    """The paper's "mixed" sampling (Sec. 5 ablation): 0.6 N Halton + B-spline
+    particles and 0.4 N comb-filtered Gaussian particles, every cost term;
+    n_halton is odd, so one tile holds a particle of each kind."""
+    prob = inputs.config2(7, n_particles=201, horizon=30)
+    prob.params.n_halton = 121
+    prob.params.comb_filter = 1
+    prob.params.comb = (0.4, 0.4, 0.2)
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    _config2_checks(g, ro, o, prob)
+
+
 def _config2_checks(g, ro, o, prob):
     p = prob.params
     assert_states(g, ro)

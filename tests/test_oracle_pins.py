@@ -154,6 +154,49 @@ def test_noise_layout(oracle_lib):
     np.testing.assert_allclose(eps[12, 4], oracle_lib.gauss7(prob.params.seed, 5, 12, 4), atol=0)
 
 
+def _comb_noise(oracle_lib, c, N=24, H=17, step=4):
+    prob = inputs.config2(0, n_particles=N, horizon=H)
+    prob.params.n_null = 3
+    raw = oracle_lib.Oracle(prob).noise(step)
+    prob.params.comb_filter = 1
+    prob.params.comb = c
+    return prob, raw, oracle_lib.Oracle(prob).noise(step)
+
+
+@pytest.mark.parametrize("c", [(0.5, 0.3, 0.2), (0.4, 0.4, 0.2), (1.0, -0.5, 0.25)])
+def test_comb_filter_matches_lfilter(oracle_lib, c):
+    """Comb filter (Sec. 3.3), read as the recursion e'_h = c1 e_h + c2 e'_{h-1}
+    + c3 e'_{h-2} in step order: per (particle, joint) the IIR filter with
+    numerator [c1] and denominator [1, -c2, -c3] (scipy.signal.lfilter).
+    Halton and null particles are not filtered."""
+    from scipy.signal import lfilter
+
+    prob, raw, eps = _comb_noise(oracle_lib, c)
+    g0, g1 = prob.params.n_halton, prob.params.n_particles - prob.params.n_null
+    np.testing.assert_array_equal(eps[:g0], raw[:g0])
+    np.testing.assert_array_equal(eps[g1:], 0.0)
+    want = lfilter([c[0]], [1.0, -c[1], -c[2]], raw[g0:g1], axis=1)
+    np.testing.assert_allclose(eps[g0:g1], want, rtol=1e-12, atol=1e-13)
+
+
+def test_comb_filter_closed_forms(oracle_lib):
+    """(1, 0, 0) leaves the draws unchanged; with c3 = 0 the filter is the
+    geometric sum e'_h = c1 sum_{k <= h} c2^k e_{h-k}; with c2 = 0 only steps
+    of the same parity as h contribute, c1 sum_k c3^k e_{h-2k}."""
+    prob, raw, eps = _comb_noise(oracle_lib, (1.0, 0.0, 0.0))
+    np.testing.assert_array_equal(eps, raw)
+    H = prob.params.horizon
+    g0, g1 = prob.params.n_halton, prob.params.n_particles - prob.params.n_null
+    _, raw, eps = _comb_noise(oracle_lib, (0.7, 0.6, 0.0))
+    for h in range(H):
+        want = 0.7 * sum(0.6 ** k * raw[g0:g1, h - k] for k in range(h + 1))
+        np.testing.assert_allclose(eps[g0:g1, h], want, rtol=1e-12, atol=1e-13)
+    _, raw, eps = _comb_noise(oracle_lib, (0.5, 0.0, -0.4))
+    for h in range(H):
+        want = 0.5 * sum((-0.4) ** k * raw[g0:g1, h - 2 * k] for k in range(h // 2 + 1))
+        np.testing.assert_allclose(eps[g0:g1, h], want, rtol=1e-12, atol=1e-13)
+
+
 # --------------------------------------------------------------------------
 # Integrator (Sec. 3.1, Eq. 7)
 # --------------------------------------------------------------------------
