@@ -104,7 +104,7 @@ def cpu_baseline(prob, budget_s):
     steps = 0
     while True:
         _, up = o.step(steps, mean, sig2)
-        mean, sig2 = up["mean_shift"], up["sigma2"]
+        mean, sig2 = up["mean_shift"], up["sigma2_shift"]
         steps += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
@@ -220,32 +220,27 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
     }
 
 
-def mixed_bench(seed, steps, warmup):
-    """The STORM-shaped step with the paper's "mixed" sampling: 0.6 N Halton +
-    B-spline particles and 0.4 N Gaussian particles smoothed by the comb
-    filter (coefficients 0.4, 0.4, 0.2), every cost term; the step (eager
-    and one graph launch) and the rollout kernel alone, back to back."""
+def _variant_step(prob, steps, warmup, iterations=1):
+    """Time one variant of the STORM-shaped step: K = `iterations` rollouts
+    and updates per control step (the last one shifts), eager and as one
+    graph launch, and the rollout kernel alone, back to back."""
     import torch
 
-    from paper_2104_13542_amd import inputs, storm
+    from paper_2104_13542_amd import storm
 
-    prob = inputs.config2(seed)
-    p = prob.params
-    N, H = p.n_particles, p.horizon
-    p.n_halton = int(0.6 * N)
-    p.comb_filter = 1
-    p.comb = (0.4, 0.4, 0.2)
+    N = prob.params.n_particles
     r = storm.Rollout(prob)
     qg = torch.tensor(prob.q_goal, dtype=torch.float32, device="cuda").reshape(1, 7)
     goal = storm.fk(qg)[0][0].contiguous()
     C = torch.empty(N, dtype=torch.float32, device="cuda")
     cmd = torch.empty(7, dtype=torch.float32, device="cuda")
     x0 = r.x0.clone()
-    graph = r.graph(x0, goal, cmd, iterations=1, shift=True)
+    graph = r.graph(x0, goal, cmd, iterations=iterations, shift=True)
 
     def eager_step():
-        r.step(goal, x0=x0, C=C)
-        r.update(shift=True, want_mean=False, cmd=cmd)
+        for k in range(iterations):
+            r.step(goal, x0=x0, C=C)
+            r.update(shift=k == iterations - 1, want_mean=False, cmd=cmd)
 
     for _ in range(warmup):
         graph.launch()
@@ -266,12 +261,44 @@ def mixed_bench(seed, steps, warmup):
     r.close()
     ms = min(res["graph"], res["eager"])
     return {
-        "workload": "N=500 (300 Halton + B-spline, 200 comb-filtered Gaussian, c = 0.4, 0.4, 0.2), H=30, "
-                    "all cost terms, 30 sphere + 20 cuboid obstacles",
         "ms_per_step": ms,
-        "rollout_steps_per_s": N * H / (ms * 1e-3),
+        "rollout_steps_per_s": iterations * N * prob.params.horizon / (ms * 1e-3),
         "rollout_kernel_us": res["rollout"] * 1e3,
     }
+
+
+def mixed_bench(seed, steps, warmup):
+    """The STORM-shaped step with the paper's "mixed" sampling: 0.6 N Halton +
+    B-spline particles and 0.4 N Gaussian particles smoothed by the comb
+    filter (coefficients 0.4, 0.4, 0.2), every cost term."""
+    from paper_2104_13542_amd import inputs
+
+    prob = inputs.config2(seed)
+    p = prob.params
+    p.n_halton = int(0.6 * p.n_particles)
+    p.comb_filter = 1
+    p.comb = (0.4, 0.4, 0.2)
+    out = {"workload": "N=500 (300 Halton + B-spline, 200 comb-filtered Gaussian, c = 0.4, 0.4, 0.2), H=30, "
+                       "all cost terms, 30 sphere + 20 cuboid obstacles"}
+    out.update(_variant_step(prob, steps, warmup))
+    return out
+
+
+def variants_bench(seed, steps, warmup):
+    """Two variants of Alg. 1 on the STORM-shaped step: a per-(step, joint)
+    covariance (Eq. 5 kept per step), and K = 2 optimisation iterations per
+    control step."""
+    from paper_2104_13542_amd import inputs
+
+    prob = inputs.config2(seed)
+    prob.params.cov_per_step = 1
+    cov = {"workload": "N=500 (250 Halton + B-spline, 250 Gaussian), H=30, all cost terms, one variance per "
+                       "(step, joint)"}
+    cov.update(_variant_step(prob, steps, warmup))
+    k2 = {"workload": "N=500 (250 Halton + B-spline, 250 Gaussian), H=30, all cost terms, K=2 iterations per "
+                      "control step (rollout-steps counted over both)"}
+    k2.update(_variant_step(inputs.config2(seed), steps, warmup, iterations=2))
+    return {"cov_per_step": cov, "iterations_2": k2}
 
 
 def differentiable_bench(steps, latency_steps, warmup):
@@ -478,7 +505,7 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=256, help="batched workload size (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-latency-steps", type=int, default=1000)
-    ap.add_argument("--mixed-steps", type=int, default=500, help="mixed-sampling steps (0 = skip)")
+    ap.add_argument("--mixed-steps", type=int, default=500, help="steps of the mixed-sampling and variant workloads (0 = skip)")
     ap.add_argument("--diff-steps", type=int, default=200, help="differentiable-form steps (0 = skip)")
     ap.add_argument("--large-problems", type=int, default=64, help="large workload size (0 = skip)")
     ap.add_argument("--large-steps", type=int, default=100)
@@ -645,6 +672,8 @@ def main():
     if args.mixed_steps > 0:
         line["mixed"] = mixed_bench(args.seed, args.mixed_steps, warmup=50)
         progress("mixed-sampling workload done")
+        line["variants"] = variants_bench(args.seed, args.mixed_steps, warmup=50)
+        progress("variant workloads done")
     if args.diff_steps > 0:
         line["differentiable"] = differentiable_bench(args.diff_steps, args.diff_steps, warmup=10)
         progress("differentiable workload done")

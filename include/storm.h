@@ -27,7 +27,8 @@
  *   x0     [3][7]        q0, v0, a0 (joint position, velocity, acceleration)
  *   goal   [12]          goal rotation R_g (row-major 3x3), then position p_g
  *   mean   [H][7]        Gaussian means of the controls (joint accelerations)
- *   sigma2 [7]           per-joint control variance (shared over the horizon)
+ *   sigma2 [7]           per-joint control variance (shared over the horizon);
+ *          [H][7]        per step and joint with storm_params.cov_per_step
  *   noise  [7][N][H]     standard-normal override (joint, particle, step)
  *   u, q, v, a [7][N][H] controls and states (joint, particle, step)
  *   c      [N][H]        running cost; terms [8][N][H] unweighted terms in the
@@ -119,6 +120,11 @@ typedef struct storm_params {
                             sampling (B-spline and comb particles).  Halton particles, null particles and
                             a noise override are not filtered.  0: no filter */
     float comb[3];       /* comb filter coefficients c1, c2, c3, finite */
+    int32_t cov_per_step; /* 1: Eq. 5 as printed, per step: a diagonal variance per (step, joint),
+                             sigma2 [H][7], each updated from the weighted deviations at its step; the
+                             shift moves it forward one step with sigma_init^2 appended.  0: the
+                             per-joint variance shared over the horizon (Sec. 3.3 parameterisation),
+                             sigma2 [7], which the shift leaves as it is */
 } storm_params;
 
 /* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame
@@ -171,10 +177,11 @@ int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal
 
 /* Policy update (Alg. 1 update_distribution, Eq. 4-6) from the last step,
  * then next_command: d_cmd [7] = updated mu_0.  d_mean [H][7] and d_sigma2
- * [7] (nullable) receive the updated (unshifted) mean and variance.  With
- * shift != 0 the stored mean is shifted one step and a zero mean appended
- * (the warm start of the next control step); otherwise it is stored as is
- * (for K > 1 iterations).  Non-finite costs or a zero weight sum keep mu and
+ * ([7], or [H][7] with cov_per_step; nullable) receive the updated
+ * (unshifted) mean and variance.  With shift != 0 the stored mean is shifted
+ * one step and a zero mean appended (the warm start of the next control
+ * step), and a per-step variance likewise with sigma_init^2 appended;
+ * otherwise they are stored as they are (for K > 1 iterations).  Non-finite costs or a zero weight sum keep mu and
  * sigma2 and raise a status flag.  Increments the sampling step counter.
  * Errors: E_NULL (d_cmd), E_STATE (no step since the last update), E_DEVICE. */
 int32_t storm_rollout_update(storm_ctx ctx, float *d_mean, float *d_sigma2, float *d_cmd, int32_t shift,
@@ -187,12 +194,14 @@ int32_t storm_rollout_destroy(storm_ctx ctx);
  * `stream`; not for the hot loop. */
 int32_t storm_rollout_status(storm_ctx ctx, uint32_t *h_flags, void *stream);
 
-/* Read the policy state to host memory (mean [H][7], sigma2 [7], step
- * counter); any pointer may be NULL.  Synchronises `stream`. */
+/* Read the policy state to host memory (mean [H][7], sigma2 [7] or [H][7]
+ * with cov_per_step, step counter); any pointer may be NULL.  Synchronises
+ * `stream`. */
 int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, uint32_t *h_step, void *stream);
 
 /* Restore the policy state from host memory (NULL pointers leave that part
- * unchanged).  Clears a pending step.  Synchronises `stream`. */
+ * unchanged; sigma2 as in get_state, finite and >= 0).  Clears a pending
+ * step.  Synchronises `stream`. */
 int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float *h_sigma2, const uint32_t *h_step,
                                 void *stream);
 

@@ -49,6 +49,7 @@ class OracleParams(ctypes.Structure):
         ("a_stop", ctypes.c_double), ("a_joint", ctypes.c_double), ("a_vel", ctypes.c_double),
         ("a_manip", ctypes.c_double), ("a_coll", ctypes.c_double),
         ("cost_mask", ctypes.c_uint32), ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_double * 3),
+        ("cov_per_step", ctypes.c_int32), ("pad2", ctypes.c_int32), ("sigma_init2", ctypes.c_double * 7),
     ]
 
 
@@ -112,7 +113,7 @@ def lib():
         L.oracle_running_cost.restype = ctypes.c_double
         L.oracle_rollout.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD, _PD,
                                      _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
-        L.oracle_update.argtypes = [ctypes.POINTER(OracleParams), _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
+        L.oracle_update.argtypes = [ctypes.POINTER(OracleParams), _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
         L.oracle_grad.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD, _PD,
                                   _PD, _PD, _PD, _PD, _PD]
         L.oracle_expected_cost.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD,
@@ -253,6 +254,9 @@ class Oracle:
         p.a_stop, p.a_joint, p.a_vel, p.a_manip, p.a_coll = pr.a_stop, pr.a_joint, pr.a_vel, pr.a_manip, pr.a_coll
         p.cost_mask = pr.cost_mask
         p.comb_filter = int(getattr(pr, "comb_filter", 0))
+        p.cov_per_step = int(getattr(pr, "cov_per_step", 0))
+        for j in range(DOF):
+            p.sigma_init2[j] = float(pr.sigma_init[j]) ** 2
         for k, c in enumerate(getattr(pr, "comb", (1.0, 0.0, 0.0))):
             p.comb[k] = float(c)
         self.params = p
@@ -285,11 +289,17 @@ class Oracle:
             raise RuntimeError("oracle_noise failed")
         return eps
 
+    def _sig(self, sigma):
+        """Standard deviation per (step, joint): a per-joint sigma [7] is
+        repeated over the steps."""
+        s = _f64(sigma)
+        return np.ascontiguousarray(np.broadcast_to(s, (self.H, DOF))) if s.ndim == 1 else s
+
     # -- rollout -----------------------------------------------------------
     def rollout(self, mean, sigma, eps, goal=None, x0=None, want_terms=True):
         N, H = self.N, self.H
         mean = _f64(mean)
-        sigma = _f64(sigma)
+        sigma = self._sig(sigma)
         eps = _f64(eps)
         goal = self.goal if goal is None else _f64(goal)
         x0 = self.x0 if x0 is None else _f64(x0)
@@ -307,7 +317,7 @@ class Oracle:
 
     def costs_only(self, mean, sigma, eps, goal=None, x0=None):
         N = self.N
-        mean, sigma, eps = _f64(mean), _f64(sigma), _f64(eps)
+        mean, sigma, eps = _f64(mean), self._sig(sigma), _f64(eps)
         goal = self.goal if goal is None else _f64(goal)
         x0 = self.x0 if x0 is None else _f64(x0)
         C = np.zeros(N)
@@ -323,15 +333,18 @@ class Oracle:
         C, u, mean, sigma2 = _f64(C), _f64(u), _f64(mean), _f64(sigma2)
         w = np.zeros(N)
         mean_new = np.zeros((H, DOF))
-        sigma2_new = np.zeros(DOF)
+        shape = (H, DOF) if self.params.cov_per_step else (DOF,)
+        sigma2 = np.ascontiguousarray(np.broadcast_to(sigma2, shape))
+        sigma2_new = np.zeros(shape)
+        sigma2_shift = np.zeros(shape)
         cmd = np.zeros(DOF)
         mean_shift = np.zeros((H, DOF))
         bad = lib().oracle_update(ctypes.byref(self.params), _d(C), _d(u), _d(mean), _d(sigma2), _d(w),
-                                  _d(mean_new), _d(sigma2_new), _d(cmd), _d(mean_shift))
+                                  _d(mean_new), _d(sigma2_new), _d(cmd), _d(mean_shift), _d(sigma2_shift))
         if bad < 0:
             raise RuntimeError("oracle_update failed")
         return {"w": w, "mean": mean_new, "sigma2": sigma2_new, "cmd": cmd, "mean_shift": mean_shift,
-                "bad": bool(bad)}
+                "sigma2_shift": sigma2_shift, "bad": bool(bad)}
 
     # -- gradient ----------------------------------------------------------
     def _grad_params(self):
@@ -347,7 +360,7 @@ class Oracle:
 
     def grad(self, mean, sigma, eps, goal=None, x0=None):
         H = self.H
-        mean, sigma, eps = _f64(mean), _f64(sigma), _f64(eps)
+        mean, sigma, eps = _f64(mean), self._sig(sigma), _f64(eps)
         goal = self.goal if goal is None else _f64(goal)
         x0 = self.x0 if x0 is None else _f64(x0)
         g = np.zeros((H, DOF))
@@ -359,7 +372,7 @@ class Oracle:
         return g, J.value
 
     def expected_cost(self, mean, sigma, eps, goal=None, x0=None):
-        mean, sigma, eps = _f64(mean), _f64(sigma), _f64(eps)
+        mean, sigma, eps = _f64(mean), self._sig(sigma), _f64(eps)
         goal = self.goal if goal is None else _f64(goal)
         x0 = self.x0 if x0 is None else _f64(x0)
         J = ctypes.c_double()

@@ -63,6 +63,9 @@ typedef struct {
     uint32_t cost_mask;
     int32_t comb_filter; /* 1: comb-filter the Gaussian particles' noise (Sec. 3.3) */
     double comb[3];      /* c1, c2, c3 */
+    int32_t cov_per_step; /* 1: Eq. 5 per step: sigma2 is [H][7], shifted with sigma_init2 appended */
+    int32_t pad2;
+    double sigma_init2[DOF]; /* the value a per-step shift appends */
 } oracle_params;
 
 typedef struct {
@@ -617,7 +620,8 @@ static double horizon_weight(const oracle_params *p, int h)
 /* ------------------------------------------------------------------------ */
 
 /* x0 = [q0 (7), v0 (7), a0 (7)]; goal = [R_g (9), p_g (3)]; mean[H][7];
- * sigma[7] = per-joint standard deviation; eps[N][H][7] standard noise.
+ * sigma[H][7] = standard deviation per step and joint (a per-joint sigma is
+ * passed repeated over the steps); eps[N][H][7] standard noise.
  * Controls u = mean + sigma * eps (u = 0 for null particles).  Outputs
  * (nullable except C): u, q, v, a [N][H][7], c[N][H], terms[N][H][8], C[N]. */
 int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double *dt, const double x0[3 * DOF],
@@ -633,7 +637,7 @@ int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double
         for (int h = 0; h < H; ++h)
             for (int j = 0; j < DOF; ++j) {
                 size_t idx = ((size_t)i * H + h) * DOF + j;
-                u[h * DOF + j] = is_null ? 0.0 : mean[h * DOF + j] + sigma[j] * eps[idx];
+                u[h * DOF + j] = is_null ? 0.0 : mean[h * DOF + j] + sigma[h * DOF + j] * eps[idx];
             }
         oracle_integrate(H, dt, x0, x0 + DOF, u, q, v, a);
         double total = 0.0;
@@ -670,9 +674,10 @@ int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double
  * were) when any C is non-finite or the weight sum is not positive. */
 int oracle_update(const oracle_params *p, const double *C, const double *u, const double *mean,
                   const double *sigma2, double *w_out, double *mean_new, double *sigma2_new, double *cmd,
-                  double *mean_shift)
+                  double *mean_shift, double *sigma2_shift)
 {
     int N = p->n, H = p->h;
+    const int nsig = p->cov_per_step ? H * DOF : DOF;
     double cmin = INFINITY;
     int bad = 0;
     for (int i = 0; i < N; ++i) {
@@ -688,7 +693,7 @@ int oracle_update(const oracle_params *p, const double *C, const double *u, cons
     }
     if (bad || !(sw > 0.0) || !isfinite(sw)) {
         for (int k = 0; k < H * DOF; ++k) mean_new[k] = mean[k];
-        for (int j = 0; j < DOF; ++j) sigma2_new[j] = sigma2[j];
+        for (int k = 0; k < nsig; ++k) sigma2_new[k] = sigma2[k];
         bad = 1;
     } else {
         for (int i = 0; i < N; ++i) w[i] /= sw;
@@ -698,15 +703,30 @@ int oracle_update(const oracle_params *p, const double *C, const double *u, cons
                 for (int i = 0; i < N; ++i) s += w[i] * u[((size_t)i * H + h) * DOF + j];
                 mean_new[h * DOF + j] = (1.0 - p->alpha_mu) * mean[h * DOF + j] + p->alpha_mu * s;
             }
-        for (int j = 0; j < DOF; ++j) {
-            double acc = 0.0;
+        if (p->cov_per_step) {
+            /* Eq. 5 as printed, per step h: the weighted variance of joint j
+             * about the updated mean at that step */
             for (int h = 0; h < H; ++h)
-                for (int i = 0; i < N; ++i) {
-                    double d = u[((size_t)i * H + h) * DOF + j] - mean_new[h * DOF + j];
-                    acc += w[i] * d * d;
+                for (int j = 0; j < DOF; ++j) {
+                    double acc = 0.0;
+                    for (int i = 0; i < N; ++i) {
+                        double d = u[((size_t)i * H + h) * DOF + j] - mean_new[h * DOF + j];
+                        acc += w[i] * d * d;
+                    }
+                    double s2 = (1.0 - p->alpha_sigma) * sigma2[h * DOF + j] + p->alpha_sigma * acc;
+                    sigma2_new[h * DOF + j] = s2 > p->sigma2_min ? s2 : p->sigma2_min;
                 }
-            double s2 = (1.0 - p->alpha_sigma) * sigma2[j] + p->alpha_sigma * acc / (double)H;
-            sigma2_new[j] = s2 > p->sigma2_min ? s2 : p->sigma2_min;
+        } else {
+            for (int j = 0; j < DOF; ++j) {
+                double acc = 0.0;
+                for (int h = 0; h < H; ++h)
+                    for (int i = 0; i < N; ++i) {
+                        double d = u[((size_t)i * H + h) * DOF + j] - mean_new[h * DOF + j];
+                        acc += w[i] * d * d;
+                    }
+                double s2 = (1.0 - p->alpha_sigma) * sigma2[j] + p->alpha_sigma * acc / (double)H;
+                sigma2_new[j] = s2 > p->sigma2_min ? s2 : p->sigma2_min;
+            }
         }
     }
     if (w_out)
@@ -716,6 +736,17 @@ int oracle_update(const oracle_params *p, const double *C, const double *u, cons
         for (int h = 0; h + 1 < H; ++h)
             for (int j = 0; j < DOF; ++j) mean_shift[h * DOF + j] = mean_new[(h + 1) * DOF + j];
         for (int j = 0; j < DOF; ++j) mean_shift[(H - 1) * DOF + j] = 0.0;
+    }
+    /* the covariance shift (Alg. 1): a per-step covariance moves forward with
+     * sigma_init^2 appended; a per-joint one, shared over the steps, stays */
+    if (sigma2_shift) {
+        if (p->cov_per_step) {
+            for (int h = 0; h + 1 < H; ++h)
+                for (int j = 0; j < DOF; ++j) sigma2_shift[h * DOF + j] = sigma2_new[(h + 1) * DOF + j];
+            for (int j = 0; j < DOF; ++j) sigma2_shift[(H - 1) * DOF + j] = p->sigma_init2[j];
+        } else {
+            for (int j = 0; j < DOF; ++j) sigma2_shift[j] = sigma2_new[j];
+        }
     }
     free(w);
     return bad;
@@ -842,7 +873,7 @@ int oracle_grad(const oracle_params *p, const oracle_model *mdl, const double *d
         int is_null = i >= N - p->n_null;
         for (int h = 0; h < H; ++h)
             for (int j = 0; j < DOF; ++j)
-                u[h * DOF + j] = is_null ? 0.0 : mean[h * DOF + j] + sigma[j] * eps[((size_t)i * H + h) * DOF + j];
+                u[h * DOF + j] = is_null ? 0.0 : mean[h * DOF + j] + sigma[h * DOF + j] * eps[((size_t)i * H + h) * DOF + j];
         oracle_integrate(H, dt, x0, x0 + DOF, u, q, v, a);
         double Ci = 0.0;
         for (int h = 0; h < H; ++h) {

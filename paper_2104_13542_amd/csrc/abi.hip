@@ -59,6 +59,9 @@ int32_t validate_scene(const storm_scene *scene)
     return STORM_OK;
 }
 
+// Element count of the stored variance: [7], or [H][7] per step.
+int n_sigma2(const storm::ProblemDev &P) { return P.cov_step ? P.H * STORM_DOF : STORM_DOF; }
+
 int32_t validate_params(const storm_params *p)
 {
     if (!p) return STORM_E_NULL;
@@ -70,6 +73,7 @@ int32_t validate_params(const storm_params *p)
     if (p->cost_mask & ~STORM_COST_ALL) return STORM_E_PARAM;
     if (p->grad_mask & ~(STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP)) return STORM_E_PARAM;
     if (p->comb_filter != 0 && p->comb_filter != 1) return STORM_E_PARAM;
+    if (p->cov_per_step != 0 && p->cov_per_step != 1) return STORM_E_PARAM;
     for (int c = 0; c < 3; ++c)
         if (!finite_f(p->comb[c])) return STORM_E_PARAM;
     if (!p->dt) return STORM_E_NULL;
@@ -304,6 +308,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     P.H = H;
     P.n_halton = params->n_halton;
     P.comb = params->comb_filter ? 1u : 0u;
+    P.cov_step = params->cov_per_step ? 1u : 0u;
     P.n_null = params->n_null;
     P.n_sph_obs = n_sph_obs;
     P.n_box_obs = n_box_obs;
@@ -352,7 +357,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &box_obs, (size_t)16 * n_box_obs));
     STORM_TRY(dalloc(c, &obs_bound, (size_t)n_obs));
     STORM_TRY(dalloc(c, &mean, (size_t)H * STORM_DOF));
-    STORM_TRY(dalloc(c, &sigma2, (size_t)STORM_DOF));
+    STORM_TRY(dalloc(c, &sigma2, (size_t)H * STORM_DOF));  // [7] or [H][7] (cov_per_step)
     STORM_TRY(dalloc(c, &u, (size_t)STORM_DOF * N * H));
     STORM_TRY(dalloc(c, &C, (size_t)N));
     STORM_TRY(dalloc(c, &counters, (size_t)4));
@@ -516,7 +521,7 @@ int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, u
     if (h_mean)
         e = hipMemcpyAsync(h_mean, ctx->P.mean, sizeof(float) * ctx->P.H * STORM_DOF, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && h_sigma2)
-        e = hipMemcpyAsync(h_sigma2, ctx->P.sigma2, sizeof(float) * STORM_DOF, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(h_sigma2, ctx->P.sigma2, sizeof(float) * n_sigma2(ctx->P), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && h_step) e = hipMemcpyAsync(h_step, ctx->P.step, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -535,14 +540,14 @@ int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float 
         for (int k = 0; k < ctx->P.H * STORM_DOF; ++k)
             if (!finite_f(h_mean[k])) return STORM_E_PARAM;
     if (h_sigma2)
-        for (int j = 0; j < STORM_DOF; ++j)
+        for (int j = 0; j < n_sigma2(ctx->P); ++j)
             if (!finite_f(h_sigma2[j]) || h_sigma2[j] < 0.0f) return STORM_E_PARAM;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     if (h_mean)
         e = hipMemcpyAsync(ctx->P.mean, h_mean, sizeof(float) * ctx->P.H * STORM_DOF, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && h_sigma2)
-        e = hipMemcpyAsync(ctx->P.sigma2, h_sigma2, sizeof(float) * STORM_DOF, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(ctx->P.sigma2, h_sigma2, sizeof(float) * n_sigma2(ctx->P), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && h_step) e = hipMemcpyAsync(ctx->P.step, h_step, sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

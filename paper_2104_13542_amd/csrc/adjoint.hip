@@ -76,7 +76,7 @@ __device__ __forceinline__ void adjoint_tile(const ProblemDev &P, const RobotDev
             if (comb) e = f;
         }
         float u = 0.0f;
-        if (live) u = fmaf(sqrtf(P.sigma2[j]), e, mean[h * kDof + j]);
+        if (live) u = fmaf(sqrtf(P.cov_step ? P.sigma2[h * kDof + j] : P.sigma2[j]), e, mean[h * kDof + j]);
         const float v = x0[kDof + j] + segmented_scan(dt_h * u, h, H);
         const float q = x0[j] + segmented_scan(dt_h * v, h, H);
         s_q[j][lane] = q;
@@ -313,17 +313,25 @@ __device__ __forceinline__ void adam_step(const ProblemDev &P, int t, float g, i
     P.mean[t] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// cmd = mu_0, then the warm-start shift of the stored mean if requested.
+// cmd = mu_0, then the warm-start shift of the stored mean (and of a
+// per-step variance, sigma_init^2 appended) if requested.
 __device__ __forceinline__ void command(const ProblemDev &P, float *__restrict__ cmd, int shift)
 {
     __shared__ float s_mu[kDof * kMaxH];
+    __shared__ float s_s2[kDof * kMaxH];
     const int t = threadIdx.x;
     const int n = P.H * kDof;
-    for (int k = t; k < n; k += blockDim.x) s_mu[k] = P.mean[k];
+    for (int k = t; k < n; k += blockDim.x) {
+        s_mu[k] = P.mean[k];
+        if (P.cov_step) s_s2[k] = P.sigma2[k];
+    }
     __syncthreads();
     if (t < kDof) cmd[t] = s_mu[t];
     if (shift)
-        for (int k = t; k < n; k += blockDim.x) P.mean[k] = k + kDof < n ? s_mu[k + kDof] : 0.0f;
+        for (int k = t; k < n; k += blockDim.x) {
+            P.mean[k] = k + kDof < n ? s_mu[k + kDof] : 0.0f;
+            if (P.cov_step) P.sigma2[k] = k + kDof < n ? s_s2[k + kDof] : P.tables[kTabSig0 + k % kDof];
+        }
 }
 
 // Gradient of joint j: the chunk partials of (h, j) summed in a fixed order
@@ -331,7 +339,8 @@ __device__ __forceinline__ void command(const ProblemDev &P, float *__restrict__
 // then wave 0 over the rows), divided by N; joint 0 also sums the chunk
 // costs into J.  With it > 0, lane h of wave 0 then takes the Adam step on
 // mu[h][j]; with cmd, it writes the command mu[0][j] and the warm-start
-// shift of the joint (the next step's value through a DPP wave shift).
+// shift of the joint (the next step's value through a DPP wave shift), with
+// a per-step variance shifted alike.
 __device__ __forceinline__ void grad_step(const ProblemDev &P, int j, float *__restrict__ grad_out,
                                           float *__restrict__ J_out, int it, float lr, float *__restrict__ cmd,
                                           int shift)
@@ -393,6 +402,13 @@ __device__ __forceinline__ void grad_step(const ProblemDev &P, int j, float *__r
                                                                          true));  // wave_shl:1
         if (lane == 0) cmd[j] = mu;
         if (shift && lane < H) P.mean[lane * kDof + j] = lane + 1 < H ? mu_next : 0.0f;
+        if (shift && P.cov_step) {
+            // a per-step variance moves forward too, sigma_init^2 appended
+            const float s2 = lane < H ? P.sigma2[lane * kDof + j] : 0.0f;
+            const float s2_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s2), 0x130, 0xf, 0xf,
+                                                                             true));  // wave_shl:1
+            if (lane < H) P.sigma2[lane * kDof + j] = lane + 1 < H ? s2_next : P.tables[kTabSig0 + j];
+        }
     }
 }
 

@@ -17,6 +17,8 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
 {
     const int t = threadIdx.x;
     const int H = P.H;
+    if (t < H && P.cov_step)
+        for (int j = 0; j < kDof; ++j) P.sigma2[t * kDof + j] = (float)((double)sigma_init[j] * sigma_init[j]);
     if (t < H) {
         double rem = 0.0;
         for (int k = t; k < H; ++k) rem += (double)dt_raw[k];
@@ -34,7 +36,8 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
         tables[kTabVlo + t] = (float)(-vm + (double)k_vl * 2.0 * vm);
         tables[kTabVhi + t] = (float)(vm - (double)k_vl * 2.0 * vm);
         const double s = sigma_init[t];
-        P.sigma2[t] = (float)(s * s);
+        tables[kTabSig0 + t] = (float)(s * s);
+        if (!P.cov_step) P.sigma2[t] = (float)(s * s);
     }
     if (t == 0) {
         *P.step = 0u;

@@ -95,7 +95,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // overlaps the noise generation.
     const int jw = wave < kDof ? wave : 0;
     const float mu_j = live ? P.mean[h * kDof + jw] : 0.0f;
-    const float sig_j = sqrtf(P.sigma2[jw]);
+    const float sig_j = sqrtf(P.cov_step ? P.sigma2[h * kDof + jw] : P.sigma2[jw]);
     const float dt_h = tab[kTabDt + h];
     const float vs_h = tab[kTabVstop + h];
     const float q0_j = x0[jw], v0_j = x0[kDof + jw];

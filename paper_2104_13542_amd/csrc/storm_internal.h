@@ -30,7 +30,8 @@ constexpr int kTabJhi = 200;
 constexpr int kTabVlo = 208;        // band-shrunk joint velocity limits [7]
 constexpr int kTabVhi = 216;
 constexpr int kTabComb = 224;        // comb filter response g_k (e'_h = sum_k g_k e_{h-k}) [H]
-constexpr int kTabSize = 288;
+constexpr int kTabSig0 = 288;        // sigma_init^2 [7], appended by a per-step covariance shift
+constexpr int kTabSize = 296;
 
 
 // Per-problem description read by the kernels.  All pointers are device memory.
@@ -42,14 +43,15 @@ struct ProblemDev {
     float k_m, w_pos, w_rot, a_stop;
     float a_joint, a_vel, a_manip, a_coll;
     float alpha_pos[3], alpha_rot[3];
-    uint32_t comb, pad1;  // comb: the Gaussian particles' noise is comb-filtered (response in the tables)
+    uint32_t comb;      // the Gaussian particles' noise is comb-filtered (response in the tables)
+    uint32_t cov_step;  // sigma2 is [H][7] (Eq. 5 per step) instead of [7]
     const float *tables;    // [kTabSize]
     const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
     const float4 *sph_obs;  // [n_sph_obs] centre, radius
     const float *box_obs;   // [n_box_obs][16]: M = R^T (9, row-major), t = -R^T c (3), half extents (3), pad
     const float4 *obs_bound;  // [n_sph_obs + n_box_obs] centre, culling radius (bounding sphere + 1e-4 m)
     float *mean;            // [H][7]
-    float *sigma2;          // [7]
+    float *sigma2;          // [7], or [H][7] with cov_step
     float *u;               // [7][N][H] controls of the last step
     float *C;               // [N] horizon costs of the last step
     uint32_t *step;         // sampling step counter (Philox counter word 3)

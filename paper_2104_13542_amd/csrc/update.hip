@@ -86,8 +86,11 @@ __device__ __forceinline__ float block_min(float v, float *s_wave, int lane, int
     return m;
 }
 
+// `cov` is P.cov_step, passed apart so that the plain kernel can fix it at
+// compile time.
 __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, float *__restrict__ mean_out,
-                                             float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift)
+                                             float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift,
+                                             const bool cov)
 {
     __shared__ float s_buf[kChunk];  // register path: weights; list: indices, then weights; dense: a chunk
     __shared__ float s_red[2 * kThreads];
@@ -306,11 +309,13 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
         const float mu_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(mu_new), 0x130, 0xf, 0xf,
                                                                          true));  // wave_shl:1
         if (lane == 0) {
-            const float old = P.sigma2[j];
-            float s2n = old;
-            if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
-            P.sigma2[j] = s2n;
-            if (sigma2_out) sigma2_out[j] = s2n;
+            if (!cov) {
+                const float old = P.sigma2[j];
+                float s2n = old;
+                if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
+                P.sigma2[j] = s2n;
+                if (sigma2_out) sigma2_out[j] = s2n;
+            }
             cmd[j] = mu_new;
             if (j == 0) {
                 *P.step = *P.step + 1u;
@@ -321,11 +326,25 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             if (mean_out) mean_out[lane * kDof + j] = mu_new;
             P.mean[lane * kDof + j] = shift ? (lane + 1 < H ? mu_next : 0.0f) : mu_new;
         }
+        if (cov) {
+            // Eq. 5 per step: lane h updates sigma^2[h][j] from the variance at
+            // step h; the shift moves it one step, sigma_init^2 appended
+            const float old = lane < H ? P.sigma2[lane * kDof + j] : 0.0f;
+            const float s2n = ok ? fmaxf(fmaf(P.alpha_sigma, var - old, old), P.sigma2_min) : old;
+            const float s2_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s2n), 0x130, 0xf, 0xf,
+                                                                             true));  // wave_shl:1
+            if (lane < H) {
+                if (sigma2_out) sigma2_out[lane * kDof + j] = s2n;
+                P.sigma2[lane * kDof + j] = shift ? (lane + 1 < H ? s2_next : P.tables[kTabSig0 + j]) : s2n;
+            }
+        }
     }
 }
 
 // The fields the first loads depend on come first, as scalar arguments, so
 // that they are preloaded into SGPRs; the rest of the problem follows in P.
+// kCov: one variance per (step, joint) instead of one per joint.
+template <bool kCov>
 __global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, float *mean, float *sigma2, int32_t N,
                                                           int32_t H, float beta, ProblemDev P,
                                                           float *__restrict__ mean_out, float *__restrict__ sigma2_out,
@@ -339,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, fl
     Q.N = N;
     Q.H = H;
     Q.beta = beta;
-    update_joint(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift);
+    update_joint(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift, kCov);
 }
 
 // Workgroup (p, j) of a batch; commands go to cmd[p][7].
@@ -348,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void update_batch_kernel(const ProblemDev
 {
     const int p = blockIdx.x / kDof, j = blockIdx.x - p * kDof;
     const ProblemDev P = load_uniform(probs + p);
-    update_joint(P, j, nullptr, nullptr, cmd + (size_t)p * kDof, shift);
+    update_joint(P, j, nullptr, nullptr, cmd + (size_t)p * kDof, shift, P.cov_step != 0u);
 }
 
 }  // namespace
@@ -363,8 +382,12 @@ hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *c
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2, P.N, P.H,
-                       P.beta, P, mean_out, sigma2_out, cmd, shift);
+    if (P.cov_step)
+        hipLaunchKernelGGL(update_kernel<true>, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2,
+                           P.N, P.H, P.beta, P, mean_out, sigma2_out, cmd, shift);
+    else
+        hipLaunchKernelGGL(update_kernel<false>, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2,
+                           P.N, P.H, P.beta, P, mean_out, sigma2_out, cmd, shift);
     return hipGetLastError();
 }
 

@@ -133,6 +133,7 @@ class Params:
     grad_mask: int = 0  # terms of the differentiable form; 0 = cost_mask
     comb_filter: int = 0  # 1: comb-filter the Gaussian particles' noise along the horizon (Sec. 3.3)
     comb: tuple = (1.0, 0.0, 0.0)  # (c1, c2, c3): e'_h = c1 e_h + c2 e'_{h-1} + c3 e'_{h-2}
+    cov_per_step: int = 0  # 1: one diagonal covariance per (step, joint), each updated by Eq. 5
 
 
 @dataclasses.dataclass

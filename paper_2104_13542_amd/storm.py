@@ -54,7 +54,7 @@ class storm_params(ctypes.Structure):
         ("alpha_pos", ctypes.c_float * 3), ("alpha_rot", ctypes.c_float * 3),
         ("a_stop", ctypes.c_float), ("a_joint", ctypes.c_float), ("a_vel", ctypes.c_float),
         ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float), ("grad_mask", ctypes.c_uint32),
-        ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_float * 3),
+        ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_float * 3), ("cov_per_step", ctypes.c_int32),
     ]
 
 
@@ -168,6 +168,7 @@ def make_params(p: "inputs.Params"):
     sp.cost_mask, sp.seed = p.cost_mask, p.seed
     sp.grad_mask = getattr(p, "grad_mask", 0)
     sp.comb_filter = int(getattr(p, "comb_filter", 0))
+    sp.cov_per_step = int(getattr(p, "cov_per_step", 0))
     comb = getattr(p, "comb", (1.0, 0.0, 0.0))
     for c in range(3):
         sp.comb[c] = float(comb[c])
@@ -265,11 +266,15 @@ class Rollout:
                "storm_rollout_step")
         return out
 
+    def _sig_shape(self):
+        return (self.H, DOF) if getattr(self.problem.params, "cov_per_step", 0) else (DOF,)
+
     def update(self, shift=True, want_mean=True, cmd=None):
-        """Policy update; returns (cmd [7], mean' [H][7] or None, sigma2' [7] or None)."""
+        """Policy update; returns (cmd [7], mean' [H][7] or None, sigma2' [7]
+        ([H][7] with cov_per_step) or None)."""
         kw = dict(dtype=torch.float32, device=self.device)
         mean = torch.empty((self.H, DOF), **kw) if want_mean else None
-        sigma2 = torch.empty(DOF, **kw) if want_mean else None
+        sigma2 = torch.empty(self._sig_shape(), **kw) if want_mean else None
         cmd = self.cmd if cmd is None else cmd
         _check(lib().storm_rollout_update(self._h, _ptr(mean), _ptr(sigma2), _ptr(cmd), int(bool(shift)),
                                           _stream()), "storm_rollout_update")
@@ -278,7 +283,7 @@ class Rollout:
     # -- state -------------------------------------------------------------
     def get_state(self):
         mean = np.zeros((self.H, DOF), dtype=np.float32)
-        sigma2 = np.zeros(DOF, dtype=np.float32)
+        sigma2 = np.zeros(self._sig_shape(), dtype=np.float32)
         step = ctypes.c_uint32()
         _check(lib().storm_rollout_get_state(self._h, mean.ctypes.data, sigma2.ctypes.data, ctypes.addressof(step),
                                              _stream()), "storm_rollout_get_state")
@@ -454,7 +459,7 @@ class Batch:
     def get_state(self, p):
         pr = self.problems[p].params
         mean = np.zeros((pr.horizon, DOF), dtype=np.float32)
-        sigma2 = np.zeros(DOF, dtype=np.float32)
+        sigma2 = np.zeros((pr.horizon, DOF) if getattr(pr, "cov_per_step", 0) else DOF, dtype=np.float32)
         step = ctypes.c_uint32()
         _check(lib().storm_batch_get_state(self._h, int(p), mean.ctypes.data, sigma2.ctypes.data,
                                            ctypes.addressof(step), _stream()), "storm_batch_get_state")

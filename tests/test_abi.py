@@ -78,6 +78,7 @@ def test_init_validation(storm):
         ("cost_mask", 0x80, E.STORM_E_PARAM), ("w_pos", float("inf"), E.STORM_E_PARAM),
         ("grad_mask", 0x40, E.STORM_E_PARAM), ("grad_mask", 0x10, E.STORM_E_PARAM),
         ("comb_filter", 2, E.STORM_E_PARAM), ("comb_filter", -1, E.STORM_E_PARAM),
+        ("cov_per_step", 2, E.STORM_E_PARAM), ("cov_per_step", -1, E.STORM_E_PARAM),
     ]
     for field, val, want in cases:
         sp2, rb2, sc2, keep2 = _args(storm)

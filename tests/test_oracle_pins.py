@@ -619,6 +619,63 @@ def test_update_covariance(oracle_lib):
     np.testing.assert_allclose(r["sigma2"], 10.0)
 
 
+def test_update_covariance_per_step(oracle_lib):
+    """Eq. 5 kept per (step, joint): with equal weights and alpha_sigma = 1
+    each entry is the plain population variance over the particles at that
+    step; the shift drops step 0 and appends sigma_init^2 (Alg. 1)."""
+    prob = inputs.config1(0)
+    prob.params.cov_per_step = 1
+    N, H = 64, 16
+    o = oracle_lib.Oracle(prob)
+    assert o.params.cov_per_step == 1
+    rng = np.random.default_rng(17)
+    u = rng.normal(size=(N, H, 7)) * rng.uniform(0.5, 2.0, size=(H, 7))
+    sig2 = rng.uniform(0.01, 0.1, (H, 7))
+    o.params.alpha_sigma = 1.0
+    r = o.update(np.zeros(N), u, np.zeros((H, 7)), sig2)
+    ref = np.var(u, axis=0, ddof=0)
+    assert r["sigma2"].shape == (H, 7)
+    np.testing.assert_allclose(r["sigma2"], ref, rtol=1e-12)
+    np.testing.assert_array_equal(r["sigma2_shift"][:-1], r["sigma2"][1:])
+    np.testing.assert_allclose(r["sigma2_shift"][-1], np.asarray(prob.params.sigma_init, float) ** 2, rtol=1e-15)
+    # averaging the per-step result over the steps gives the per-joint form
+    o2 = oracle_lib.Oracle(inputs.config1(0))
+    o2.params.alpha_sigma = 1.0
+    r2 = o2.update(np.zeros(N), u, np.zeros((H, 7)), sig2[0])
+    np.testing.assert_allclose(r2["sigma2"], r["sigma2"].mean(axis=0), rtol=1e-12)
+    np.testing.assert_array_equal(r2["sigma2_shift"], r2["sigma2"])
+    # a single particle carrying all the weight: the variance is zero at
+    # every step, floored at sigma2_min
+    C = np.full(N, 1e6)
+    C[5] = 0.0
+    o.params.sigma2_min = 1e-4
+    r3 = o.update(C, u, np.zeros((H, 7)), sig2)
+    np.testing.assert_allclose(r3["mean"], u[5], rtol=0, atol=1e-300)
+    np.testing.assert_allclose(r3["sigma2"], 1e-4, rtol=0)
+    # alpha_sigma blends step by step
+    o.params.sigma2_min = 0.0
+    o.params.alpha_sigma = 0.25
+    r4 = o.update(np.zeros(N), u, np.zeros((H, 7)), sig2)
+    np.testing.assert_allclose(r4["sigma2"], 0.75 * sig2 + 0.25 * ref, rtol=1e-12)
+
+
+def test_rollout_per_step_sigma(oracle_lib):
+    """A per-step sigma scales the noise of its own (step, joint) only."""
+    prob = inputs.config1(0)
+    o = oracle_lib.Oracle(prob)
+    H = o.H
+    rng = np.random.default_rng(3)
+    eps = rng.normal(size=(o.N, H, 7))
+    mean = rng.normal(scale=0.1, size=(H, 7))
+    s = rng.uniform(0.05, 0.2, (H, 7))
+    r = o.rollout(mean, s, eps, want_terms=False)
+    np.testing.assert_allclose(r["u"][0], mean + s * eps[0], rtol=1e-15)
+    s1 = np.broadcast_to(s[0], (H, 7))
+    r1 = o.rollout(mean, s[0], eps, want_terms=False)
+    r2 = o.rollout(mean, s1, eps, want_terms=False)
+    np.testing.assert_array_equal(r1["C"], r2["C"])
+
+
 def test_update_rejects_nonfinite(oracle_lib):
     prob = inputs.config1(0)
     o = oracle_lib.Oracle(prob)
