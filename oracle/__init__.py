@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "storm_oracle.c")
 _LIB = os.path.join(_HERE, "libstorm_oracle.so")
 
 DOF = 7
-NTERMS = 8
+NTERMS = 9
 TERM_NAMES = ("pos", "rot", "joint", "vel", "stop", "manip", "self", "env")
 
 
@@ -50,6 +50,8 @@ class OracleParams(ctypes.Structure):
         ("a_manip", ctypes.c_double), ("a_coll", ctypes.c_double),
         ("cost_mask", ctypes.c_uint32), ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_double * 3),
         ("cov_per_step", ctypes.c_int32), ("pad2", ctypes.c_int32), ("sigma_init2", ctypes.c_double * 7),
+        ("w_ball", ctypes.c_double), ("ball_gravity", ctypes.c_double * 3), ("ball_center", ctypes.c_double * 2),
+        ("ball", ctypes.c_double * 6),
     ]
 
 
@@ -116,6 +118,11 @@ def lib():
         L.oracle_update.argtypes = [ctypes.POINTER(OracleParams), _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
         L.oracle_grad.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD, _PD,
                                   _PD, _PD, _PD, _PD, _PD]
+        L.oracle_task_space.argtypes = [_PD, _PD, _PD, _PD, _PD, _PD]
+        L.oracle_ball_traj.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD, _PD,
+                                       _PD]
+        L.oracle_cost_ball.argtypes = [ctypes.POINTER(OracleParams), _PD]
+        L.oracle_cost_ball.restype = ctypes.c_double
         L.oracle_expected_cost.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD,
                                            _PD, _PD, _PD, _PD, _PD]
         _lib = L
@@ -204,6 +211,15 @@ def jacobian(frames):
     return J
 
 
+def task_space(dh, q, qd, qdd):
+    """Flange velocity and acceleration (Eq. 8): (xd [6], xdd [6]), linear
+    then angular."""
+    xd = np.zeros(6)
+    xdd = np.zeros(6)
+    lib().oracle_task_space(_d(_f64(dh)), _d(_f64(q)), _d(_f64(qd)), _d(_f64(qdd)), _d(xd), _d(xdd))
+    return xd, xdd
+
+
 def det(A):
     A = _f64(A).copy()
     return lib().oracle_det(A.shape[0], _d(A))
@@ -259,6 +275,11 @@ class Oracle:
             p.sigma_init2[j] = float(pr.sigma_init[j]) ** 2
         for k, c in enumerate(getattr(pr, "comb", (1.0, 0.0, 0.0))):
             p.comb[k] = float(c)
+        p.w_ball = float(getattr(pr, "w_ball", 0.0))
+        for k, g in enumerate(getattr(pr, "ball_gravity", (0.0, 0.0, -9.81))):
+            p.ball_gravity[k] = float(g)
+        for k, c in enumerate(getattr(pr, "ball_center", (0.0, 0.0))):
+            p.ball_center[k] = float(c)
         self.params = p
 
         self.dh = _f64(inputs.PANDA_DH if dh is None else dh)
@@ -390,6 +411,30 @@ class Oracle:
         c = lib().oracle_running_cost(ctypes.byref(self.params), ctypes.byref(self.model), _d(self.dt), int(h),
                                       _d(q), _d(v), _d(goal), _d(terms))
         return c, terms
+
+    def set_ball(self, ball_world):
+        """The ball's position and velocity in the world frame [6] at the
+        current arm state."""
+        b = _f64(ball_world)
+        for k in range(6):
+            self.params.ball[k] = float(b[k])
+
+    def ball_world_from_tray(self, ball_tray, q0=None):
+        """World-frame ball state [6] from a state given in the flange frame
+        of q0 (position x, y, z and velocity), by this oracle's FK."""
+        q0 = self.x0[:DOF] if q0 is None else _f64(q0)
+        E = fk(self.dh, q0)[7]
+        b = _f64(ball_tray)
+        return np.concatenate([E[:3, :3] @ b[:3] + E[:3, 3], E[:3, :3] @ b[3:]])
+
+    def ball_traj(self, q, q0=None):
+        """Ball positions in the flange frame [H][3] along one rolled-out
+        trajectory q [H][7], from the ball state set by set_ball."""
+        q0 = self.x0[:DOF] if q0 is None else _f64(q0)
+        xb = np.zeros((self.H, 3))
+        lib().oracle_ball_traj(ctypes.byref(self.params), ctypes.byref(self.model), _d(self.dt), _d(q0),
+                               _d(_f64(q)), _d(xb))
+        return xb
 
     def cost_self(self, frames):
         frames = _f64(frames)

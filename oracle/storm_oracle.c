@@ -42,10 +42,11 @@
 #define MASK_MANIP (1u << 4)
 #define MASK_SELF (1u << 5)
 #define MASK_ENV (1u << 6)
+#define MASK_BALL (1u << 7)
 
 /* Number of per-step cost terms reported: pos, rot, joint, vel, stop, manip,
- * self, env (all unweighted). */
-#define NTERMS 8
+ * self, env, ball (all unweighted). */
+#define NTERMS 9
 
 typedef struct {
     int32_t n;        /* particles N */
@@ -66,6 +67,11 @@ typedef struct {
     int32_t cov_per_step; /* 1: Eq. 5 per step: sigma2 is [H][7], shifted with sigma_init2 appended */
     int32_t pad2;
     double sigma_init2[DOF]; /* the value a per-step shift appends */
+    /* ball on the tray (appendix on dynamic object balancing) */
+    double w_ball;           /* weight of the ball term */
+    double ball_gravity[3];  /* g in the world frame */
+    double ball_center[2];   /* tray centre in the flange frame (x, y) */
+    double ball[6];          /* ball position and velocity in the world frame at the current state */
 } oracle_params;
 
 typedef struct {
@@ -398,6 +404,133 @@ void oracle_jacobian(const double T[NFRAMES][16], double J[6][DOF])
     }
 }
 
+static void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Task-space velocity and acceleration of the flange (Eq. 8): xd = J qd and
+ * xdd = Jdot qd + J qdd, rows linear x, y, z then angular x, y, z.  Jdot is
+ * formed from its definition, Jdot = sum_m (dJ/dq_m) qd_m, with the partial
+ * derivatives of a revolute chain: for m < k, dz_k/dq_m = z_m x z_k and
+ * do_k/dq_m = z_m x (o_k - o_m) (joint m does not move frames before it, and
+ * joint k turns frame k about its own z through its own origin), and
+ * dp/dq_m = z_m x (p - o_m) for the flange origin p. */
+void oracle_task_space(const double dh[NFRAMES][3], const double q[DOF], const double qd[DOF],
+                       const double qdd[DOF], double xd[6], double xdd[6])
+{
+    double T[NFRAMES][16], J[6][DOF], Jd[6][DOF];
+    oracle_fk(dh, q, T);
+    oracle_jacobian(T, J);
+    const double *E = T[NFRAMES - 1];
+    double pe[3] = {E[3], E[7], E[11]};
+    double z[DOF][3], o[DOF][3];
+    for (int k = 0; k < DOF; ++k)
+        for (int c = 0; c < 3; ++c) {
+            z[k][c] = T[k][c * 4 + 2];
+            o[k][c] = T[k][c * 4 + 3];
+        }
+    for (int r = 0; r < 6; ++r)
+        for (int k = 0; k < DOF; ++k) Jd[r][k] = 0.0;
+    for (int k = 0; k < DOF; ++k) {
+        double rk[3] = {pe[0] - o[k][0], pe[1] - o[k][1], pe[2] - o[k][2]};
+        for (int m = 0; m < DOF; ++m) {
+            double dz[3] = {0.0, 0.0, 0.0}, dok[3] = {0.0, 0.0, 0.0}, dp[3];
+            double rm[3] = {pe[0] - o[m][0], pe[1] - o[m][1], pe[2] - o[m][2]};
+            cross3(z[m], rm, dp);
+            if (m < k) {
+                double okm[3] = {o[k][0] - o[m][0], o[k][1] - o[m][1], o[k][2] - o[m][2]};
+                cross3(z[m], z[k], dz);
+                cross3(z[m], okm, dok);
+            }
+            /* d/dq_m of column k: linear z_k x (p - o_k), angular z_k */
+            double t1[3], t2[3], dr[3] = {dp[0] - dok[0], dp[1] - dok[1], dp[2] - dok[2]};
+            cross3(dz, rk, t1);
+            cross3(z[k], dr, t2);
+            for (int c = 0; c < 3; ++c) {
+                Jd[c][k] += (t1[c] + t2[c]) * qd[m];
+                Jd[3 + c][k] += dz[c] * qd[m];
+            }
+        }
+    }
+    for (int r = 0; r < 6; ++r) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < DOF; ++k) {
+            s1 += J[r][k] * qd[k];
+            s2 += Jd[r][k] * qd[k] + J[r][k] * qdd[k];
+        }
+        xd[r] = s1;
+        xdd[r] = s2;
+    }
+}
+
+/* Ball on the tray (appendix on dynamic object balancing).  The ball's state
+ * at the current arm state q0 is moved into the flange frame, x = R0^T
+ * (x_w - p0) and v = R0^T v_w with its z velocity set to 0.  At step h the
+ * flange rotation R_h of the rolled-out state gives the ball's acceleration
+ * in the tray plane, [g_x, g_y, 0] of g_ee = R_h^T g_w, and the ball is
+ * integrated with the scheme of Eq. 7: v_h = v + sum_{k<=h} dt_k a_k,
+ * x_h = x + sum_{k<=h} dt_k v_k.  Writes xb[H][3]. */
+void oracle_ball_traj(const oracle_params *p, const oracle_model *mdl, const double *dt, const double q0[DOF],
+                      const double *q, double *xb)
+{
+    double T[NFRAMES][16];
+    oracle_fk(mdl->dh, q0, T);
+    const double *E = T[NFRAMES - 1];
+    double x[3], v[3];
+    for (int c = 0; c < 3; ++c) {
+        x[c] = 0.0;
+        v[c] = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            x[c] += E[r * 4 + c] * (p->ball[r] - E[r * 4 + 3]);
+            v[c] += E[r * 4 + c] * p->ball[3 + r];
+        }
+    }
+    v[2] = 0.0;
+    int H = p->h;
+    double *a = (double *)malloc(sizeof(double) * (size_t)H * 2);
+    double *vh = (double *)malloc(sizeof(double) * (size_t)H * 2);
+    if (!a || !vh) {
+        free(a);
+        free(vh);
+        for (int k = 0; k < 3 * H; ++k) xb[k] = NAN;
+        return;
+    }
+    for (int h = 0; h < H; ++h) {
+        oracle_fk(mdl->dh, q + h * DOF, T);
+        E = T[NFRAMES - 1];
+        for (int c = 0; c < 2; ++c) {
+            a[h * 2 + c] = 0.0;
+            for (int r = 0; r < 3; ++r) a[h * 2 + c] += E[r * 4 + c] * p->ball_gravity[r];
+        }
+    }
+    for (int h = 0; h < H; ++h)
+        for (int c = 0; c < 2; ++c) {
+            double sv = 0.0;
+            for (int k = 0; k <= h; ++k) sv += dt[k] * a[k * 2 + c];
+            vh[h * 2 + c] = v[c] + sv;
+        }
+    for (int h = 0; h < H; ++h) {
+        for (int c = 0; c < 2; ++c) {
+            double sx = 0.0;
+            for (int k = 0; k <= h; ++k) sx += dt[k] * vh[k * 2 + c];
+            xb[h * 3 + c] = x[c] + sx;
+        }
+        xb[h * 3 + 2] = x[2];
+    }
+    free(a);
+    free(vh);
+}
+
+/* The ball term: distance of the ball from the tray centre in the tray plane. */
+double oracle_cost_ball(const oracle_params *p, const double xb[3])
+{
+    double dx = xb[0] - p->ball_center[0], dy = xb[1] - p->ball_center[1];
+    return sqrt(dx * dx + dy * dy);
+}
+
 /* Determinant by Gaussian elimination with partial pivoting (A is overwritten). */
 double oracle_det(int n, double *A)
 {
@@ -579,7 +712,9 @@ double oracle_cost_env(const oracle_model *mdl, const double T[NFRAMES][16])
 }
 
 /* All terms at one state; terms = [pos, rot, joint, vel, stop, manip, self,
- * env] (unweighted); returns the weighted running cost of Eq. 15. */
+ * env, ball] (unweighted; the ball term depends on the whole trajectory and
+ * is added by the rollout, 0 here); returns the weighted running cost of
+ * Eq. 15. */
 double oracle_running_cost(const oracle_params *p, const oracle_model *mdl, const double *dt, int h,
                            const double q[DOF], const double v[DOF], const double goal[12], double terms[NTERMS])
 {
@@ -623,7 +758,8 @@ static double horizon_weight(const oracle_params *p, int h)
  * sigma[H][7] = standard deviation per step and joint (a per-joint sigma is
  * passed repeated over the steps); eps[N][H][7] standard noise.
  * Controls u = mean + sigma * eps (u = 0 for null particles).  Outputs
- * (nullable except C): u, q, v, a [N][H][7], c[N][H], terms[N][H][8], C[N]. */
+ * (nullable except C): u, q, v, a [N][H][7], c[N][H], terms[N][H][9], C[N].  With the
+ * ball term on, p->ball holds the ball's state at x0 (world frame). */
 int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double *dt, const double x0[3 * DOF],
                    const double goal[12], const double *mean, const double *sigma, const double *eps, double *u_out,
                    double *q_out, double *v_out, double *a_out, double *c_out, double *terms_out, double *C)
@@ -632,6 +768,14 @@ int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double
     double *u = (double *)malloc(sizeof(double) * (size_t)H * DOF * 4);
     if (!u) return -1;
     double *q = u + (size_t)H * DOF, *v = q + (size_t)H * DOF, *a = v + (size_t)H * DOF;
+    double *xb = NULL;
+    if (p->cost_mask & MASK_BALL) {
+        xb = (double *)malloc(sizeof(double) * (size_t)H * 3);
+        if (!xb) {
+            free(u);
+            return -1;
+        }
+    }
     for (int i = 0; i < N; ++i) {
         int is_null = i >= N - p->n_null;
         for (int h = 0; h < H; ++h)
@@ -640,10 +784,15 @@ int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double
                 u[h * DOF + j] = is_null ? 0.0 : mean[h * DOF + j] + sigma[h * DOF + j] * eps[idx];
             }
         oracle_integrate(H, dt, x0, x0 + DOF, u, q, v, a);
+        if (xb) oracle_ball_traj(p, mdl, dt, x0, q, xb);
         double total = 0.0;
         for (int h = 0; h < H; ++h) {
             double terms[NTERMS];
             double c = oracle_running_cost(p, mdl, dt, h, q + h * DOF, v + h * DOF, goal, terms);
+            if (xb) {
+                terms[8] = oracle_cost_ball(p, xb + h * 3);
+                c += p->w_ball * terms[8];
+            }
             total += horizon_weight(p, h) * c;
             if (c_out) c_out[(size_t)i * H + h] = c;
             if (terms_out) memcpy(terms_out + ((size_t)i * H + h) * NTERMS, terms, sizeof(terms));
@@ -655,6 +804,7 @@ int oracle_rollout(const oracle_params *p, const oracle_model *mdl, const double
         if (v_out) memcpy(v_out + base, v, sizeof(double) * H * DOF);
         if (a_out) memcpy(a_out + base, a, sizeof(double) * H * DOF);
     }
+    free(xb);
     free(u);
     return 0;
 }

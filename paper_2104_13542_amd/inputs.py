@@ -95,7 +95,8 @@ COST_STOP = 1 << 3
 COST_MANIP = 1 << 4
 COST_SELF = 1 << 5
 COST_ENV = 1 << 6
-COST_ALL = 0x7F
+COST_ALL = 0x7F  # the reaching task's terms (the ball term is separate)
+COST_BALL = 1 << 7
 
 
 @dataclasses.dataclass
@@ -134,6 +135,11 @@ class Params:
     comb_filter: int = 0  # 1: comb-filter the Gaussian particles' noise along the horizon (Sec. 3.3)
     comb: tuple = (1.0, 0.0, 0.0)  # (c1, c2, c3): e'_h = c1 e_h + c2 e'_{h-1} + c3 e'_{h-2}
     cov_per_step: int = 0  # 1: one diagonal covariance per (step, joint), each updated by Eq. 5
+    # ball on the tray (dynamic object balancing): the ball term (COST_BALL) is
+    # w_ball times the ball's distance from the tray centre in the tray plane
+    w_ball: float = 0.0
+    ball_gravity: tuple = (0.0, 0.0, -9.81)  # world frame, m/s^2
+    ball_center: tuple = (0.0, 0.0)  # tray centre in the flange frame (x, y), m
 
 
 @dataclasses.dataclass
@@ -145,6 +151,9 @@ class Problem:
     q_goal: np.ndarray  # [7] joint configuration whose flange pose is the goal
     obstacles: np.ndarray  # [O, 16]
     spheres: np.ndarray  # [S, 5]
+    # ball state in the flange frame of q0: position (x, y, z) and velocity;
+    # the caller moves it to the world frame with its own forward kinematics
+    ball_tray: np.ndarray = None
 
 
 def random_rotation(rng: np.random.Generator) -> np.ndarray:
@@ -257,6 +266,21 @@ def config5_problem(p_index: int) -> Problem:
                n_knots=8, seed=5000 + p_index, sigma_init=np.full(DOF, 0.3),
                cost_mask=COST_ALL)
     return Problem(p, q0, np.zeros(DOF), np.zeros(DOF), q_goal, obstacles, panda_spheres())
+
+
+def config_ball(seed: int = 0, n_particles: int = 500, horizon: int = 30) -> Problem:
+    """Ball-on-tray workload: the arm near its ready configuration holds the
+    tray level; a ball at a random place on the tray with a small random
+    velocity.  N=500 (half Halton + B-spline), H=30, dt = linspace(0.01, 0.1),
+    ball + joint + velocity + stop + manipulability + self-collision terms."""
+    rng = np.random.default_rng(7000 + seed)
+    q0 = PANDA_READY + rng.uniform(-0.1, 0.1, DOF)
+    ball = np.concatenate([rng.uniform(-0.08, 0.08, 2), [0.02], rng.uniform(-0.05, 0.05, 2), [0.0]])
+    p = Params(n_particles=n_particles, horizon=horizon, dt=np.linspace(0.01, 0.1, horizon),
+               n_halton=n_particles // 2, n_knots=8, seed=7000 + seed, sigma_init=np.full(DOF, 0.3),
+               cost_mask=COST_BALL | COST_JOINT | COST_VEL | COST_STOP | COST_MANIP | COST_SELF, w_ball=100.0)
+    return Problem(p, q0, np.zeros(DOF), np.zeros(DOF), PANDA_READY.copy(), np.zeros((0, OBSTACLE_STRIDE)),
+                   panda_spheres(), ball)
 
 
 def standard_normal(seed: int, shape) -> np.ndarray:

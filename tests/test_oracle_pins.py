@@ -721,3 +721,138 @@ def test_gradient_finite_differences(oracle_lib, mask):
     assert np.linalg.norm(g - fd) <= 1e-3 * np.linalg.norm(fd)
     # last-step control moves no earlier state: only its own step's cost, through dt^2
     assert np.linalg.norm(g) > 0
+
+
+# ---------------------------------------------------------------------------
+# Task-space velocity and acceleration (Eq. 8) and the ball-on-tray model
+# ---------------------------------------------------------------------------
+
+def _fk_curve(dh, q, qd, qdd, t):
+    import oracle as oracle_lib
+
+    return oracle_lib.fk(dh, q + qd * t + 0.5 * qdd * t * t)[7]
+
+
+def _omega(dh, q, qd, qdd, t, d=1e-5):
+    """Angular velocity of the flange at time t along the quadratic joint
+    curve, from [w]x = Rdot R^T by central differences."""
+    R0 = _fk_curve(dh, q, qd, qdd, t)[:3, :3]
+    Rd = (_fk_curve(dh, q, qd, qdd, t + d)[:3, :3] - _fk_curve(dh, q, qd, qdd, t - d)[:3, :3]) / (2 * d)
+    W = Rd @ R0.T
+    return np.array([W[2, 1] - W[1, 2], W[0, 2] - W[2, 0], W[1, 0] - W[0, 1]]) / 2.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_task_space_matches_differentiated_fk(oracle_lib, seed):
+    """xd and xdd against derivatives of the forward kinematics along
+    q(t) = q + qd t + qdd t^2 / 2: the flange position differenced once and
+    twice, the rotation through Rdot R^T and its derivative."""
+    rng = np.random.default_rng(seed)
+    dh = inputs.PANDA_DH
+    q = inputs.random_q(rng)
+    qd = rng.uniform(-1.5, 1.5, 7)
+    qdd = rng.uniform(-3.0, 3.0, 7)
+    xd, xdd = oracle_lib.task_space(dh, q, qd, qdd)
+    d = 1e-4
+    p = lambda t: _fk_curve(dh, q, qd, qdd, t)[:3, 3]
+    v_fd = (p(d) - p(-d)) / (2 * d)
+    a_fd = (p(d) - 2 * p(0.0) + p(-d)) / (d * d)
+    np.testing.assert_allclose(xd[:3], v_fd, atol=1e-7)
+    np.testing.assert_allclose(a_fd, xdd[:3], atol=2e-5)
+    np.testing.assert_allclose(xd[3:], _omega(dh, q, qd, qdd, 0.0), atol=1e-8)
+    e = 1e-3
+    alpha_fd = (_omega(dh, q, qd, qdd, e) - _omega(dh, q, qd, qdd, -e)) / (2 * e)
+    np.testing.assert_allclose(alpha_fd, xdd[3:], atol=2e-5)
+
+
+def test_task_space_special_cases(oracle_lib):
+    """At rest the acceleration is J qdd; with qdd = 0 and one moving joint
+    the flange point turns about that joint's axis (centripetal
+    acceleration w x (w x r), no angular acceleration)."""
+    rng = np.random.default_rng(5)
+    dh = inputs.PANDA_DH
+    q = inputs.random_q(rng)
+    qdd = rng.normal(size=7)
+    T = oracle_lib.fk(dh, q)
+    J = oracle_lib.jacobian(T)
+    xd, xdd = oracle_lib.task_space(dh, q, np.zeros(7), qdd)
+    np.testing.assert_array_equal(xd, 0.0)
+    np.testing.assert_allclose(xdd, J @ qdd, atol=1e-15)
+    k = 3
+    qd = np.zeros(7)
+    qd[k] = 1.7
+    xd, xdd = oracle_lib.task_space(dh, q, qd, np.zeros(7))
+    z, o, p = T[k][:3, 2], T[k][:3, 3], T[7][:3, 3]
+    w = z * qd[k]
+    np.testing.assert_allclose(xd[:3], np.cross(w, p - o), atol=1e-14)
+    np.testing.assert_allclose(xdd[:3], np.cross(w, np.cross(w, p - o)), atol=1e-13)
+    np.testing.assert_allclose(xdd[3:], 0.0, atol=1e-15)
+
+
+def _ball_oracle(seed=0, H=30, dt=None, gravity=None):
+    import oracle as oracle_lib
+
+    prob = inputs.config_ball(seed, n_particles=8, horizon=H)
+    if dt is not None:
+        prob.params.dt = np.full(H, dt)
+    if gravity is not None:
+        prob.params.ball_gravity = gravity
+    o = oracle_lib.Oracle(prob)
+    return prob, o
+
+
+def test_ball_without_gravity_rolls_straight(oracle_lib):
+    """No gravity: the ball keeps its in-plane velocity, x_h = x + v t_h with
+    t_h the time at the end of step h, and its height on the tray."""
+    prob, o = _ball_oracle(gravity=(0.0, 0.0, 0.0))
+    o.set_ball(o.ball_world_from_tray(prob.ball_tray))
+    rng = np.random.default_rng(1)
+    q = prob.q0 + rng.normal(scale=0.2, size=(o.H, 7))
+    xb = o.ball_traj(q)
+    t = np.cumsum(prob.params.dt)
+    v = np.array([prob.ball_tray[3], prob.ball_tray[4], 0.0])
+    np.testing.assert_allclose(xb, prob.ball_tray[:3] + t[:, None] * v, atol=1e-12)
+
+
+def test_ball_on_a_held_tilted_tray(oracle_lib):
+    """The arm held at q0: the in-plane gravity a = (R0^T g)_xy is constant,
+    and Eq. 7's scheme with a uniform dt gives x_H = x + v T + a T (T + dt) / 2
+    (the sum of t_k dt over the steps); gravity along the tray normal gives no
+    motion in the plane."""
+    H, dt = 40, 0.025
+    prob, o = _ball_oracle(seed=3, H=H, dt=dt)
+    o.set_ball(o.ball_world_from_tray(prob.ball_tray))
+    q = np.tile(prob.q0, (H, 1))
+    xb = o.ball_traj(q)
+    R0 = oracle_lib.fk(inputs.PANDA_DH, prob.q0)[7][:3, :3]
+    a = (R0.T @ np.array(prob.params.ball_gravity))[:2]
+    assert np.linalg.norm(a) > 0.1  # the tray is tilted
+    T = H * dt
+    want = prob.ball_tray[:2] + prob.ball_tray[3:5] * T + 0.5 * a * T * (T + dt)
+    np.testing.assert_allclose(xb[-1, :2], want, atol=1e-12)
+    # gravity along the tray normal
+    prob2, o2 = _ball_oracle(seed=3, H=H, dt=dt, gravity=tuple(-9.81 * R0[:, 2]))
+    b = prob2.ball_tray.copy()
+    b[3:5] = 0.0
+    o2.set_ball(o2.ball_world_from_tray(b))
+    np.testing.assert_allclose(o2.ball_traj(q)[:, :2], np.tile(b[:2], (H, 1)), atol=1e-14)
+
+
+def test_ball_term_in_the_rollout(oracle_lib):
+    """The ball term adds w_ball |x_h - c| at every step to the running cost,
+    weighted over the horizon like every other term (Eq. 2)."""
+    prob, o = _ball_oracle(seed=2, H=12)
+    prob.params.ball_center = (0.01, -0.02)
+    o = oracle_lib.Oracle(prob)
+    o.set_ball(o.ball_world_from_tray(prob.ball_tray))
+    eps = inputs.standard_normal(4, (o.N, o.H, 7))
+    mean = np.zeros((o.H, 7))
+    r = o.rollout(mean, np.full(7, 0.3), eps)
+    o.params.cost_mask = prob.params.cost_mask & ~inputs.COST_BALL
+    r0 = o.rollout(mean, np.full(7, 0.3), eps)
+    for i in range(o.N):
+        xb = o.ball_traj(r["q"][i])
+        d = np.hypot(xb[:, 0] - 0.01, xb[:, 1] + 0.02)
+        np.testing.assert_allclose(r["terms"][i, :, 8], d, rtol=1e-14)
+        np.testing.assert_allclose(r["c"][i], r0["c"][i] + prob.params.w_ball * d, rtol=1e-13)
+    np.testing.assert_array_equal(r0["terms"][..., 8], 0.0)
