@@ -220,7 +220,7 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
     }
 
 
-def _variant_step(prob, steps, warmup, iterations=1):
+def _variant_step(prob, steps, warmup, iterations=1, setup=None):
     """Time one variant of the STORM-shaped step: K = `iterations` rollouts
     and updates per control step (the last one shifts), eager and as one
     graph launch, and the rollout kernel alone, back to back."""
@@ -230,6 +230,8 @@ def _variant_step(prob, steps, warmup, iterations=1):
 
     N = prob.params.n_particles
     r = storm.Rollout(prob)
+    if setup is not None:
+        setup(r)
     qg = torch.tensor(prob.q_goal, dtype=torch.float32, device="cuda").reshape(1, 7)
     goal = storm.fk(qg)[0][0].contiguous()
     C = torch.empty(N, dtype=torch.float32, device="cuda")
@@ -299,6 +301,32 @@ def variants_bench(seed, steps, warmup):
                       "control step (rollout-steps counted over both)"}
     k2.update(_variant_step(inputs.config2(seed), steps, warmup, iterations=2))
     return {"cov_per_step": cov, "iterations_2": k2}
+
+
+def ball_bench(seed, steps, warmup):
+    """The ball-on-tray workload (the paper's dynamic balancing task): the
+    task-space form of the rollout with the ball term, the ball's state set
+    once from its place on the tray at the current arm state."""
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    prob = inputs.config_ball(seed)
+
+    def place_ball(r):
+        E = storm.fk(r.x0[:7].reshape(1, 7).contiguous())[0][0]
+        R, p = E[:9].reshape(3, 3), E[9:12]
+        bt = torch.tensor(prob.ball_tray, dtype=torch.float32, device="cuda")
+        r.set_ball(torch.cat([R @ bt[:3] + p, R @ bt[3:]]).contiguous())
+
+    out = {"workload": "N=500 (250 Halton + B-spline, 250 Gaussian), H=30, ball + joint + velocity + stop + "
+                       "manipulability + self-collision terms, arm near its ready configuration"}
+    out.update(_variant_step(prob, steps, warmup, setup=place_ball))
+    # the same problem without the ball term runs the plain form of the kernel
+    plain = inputs.config_ball(seed)
+    plain.params.cost_mask &= ~inputs.COST_BALL
+    out["without_ball_term"] = _variant_step(plain, steps, warmup)
+    return out
 
 
 def differentiable_bench(steps, latency_steps, warmup):
@@ -673,6 +701,7 @@ def main():
         line["mixed"] = mixed_bench(args.seed, args.mixed_steps, warmup=50)
         progress("mixed-sampling workload done")
         line["variants"] = variants_bench(args.seed, args.mixed_steps, warmup=50)
+        line["variants"]["ball"] = ball_bench(args.seed, args.mixed_steps, warmup=50)
         progress("variant workloads done")
     if args.diff_steps > 0:
         line["differentiable"] = differentiable_bench(args.diff_steps, args.diff_steps, warmup=10)

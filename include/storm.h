@@ -51,7 +51,7 @@ extern "C" {
 #define STORM_MAX_OBSTACLES 256
 #define STORM_MAX_PARTICLES (1 << 20)
 #define STORM_OBSTACLE_STRIDE 16
-#define STORM_NTERMS 8
+#define STORM_NTERMS 9
 
 /* Status codes. */
 #define STORM_OK 0
@@ -71,7 +71,11 @@ extern "C" {
 #define STORM_COST_MANIP (1u << 4) /* Eq. 12 */
 #define STORM_COST_SELF (1u << 5)  /* Eq. 13, as sphere-pair penetration */
 #define STORM_COST_ENV (1u << 6)   /* Eq. 14, as sphere vs obstacle signed distance */
-#define STORM_COST_ALL 0x7Fu
+#define STORM_COST_ALL 0x7Fu       /* the reaching task's terms above */
+/* The ball on the tray (appendix on dynamic object balancing): the ball's
+ * distance from the tray centre in the tray plane, along its trajectory
+ * under in-plane gravity (storm_rollout_set_ball).  Plain contexts only. */
+#define STORM_COST_BALL (1u << 7)
 
 /* Asynchronous device status flags (storm_rollout_status). */
 #define STORM_FLAG_NONFINITE_COST (1u << 0) /* some C_i was NaN/Inf: update kept mu, sigma2 */
@@ -125,6 +129,16 @@ typedef struct storm_params {
                              shift moves it forward one step with sigma_init^2 appended.  0: the
                              per-joint variance shared over the horizon (Sec. 3.3 parameterisation),
                              sigma2 [7], which the shift leaves as it is */
+    /* Ball on the tray (STORM_COST_BALL).  The tray plane is the flange
+       frame's x-y plane.  The ball's state at the current arm state (world
+       frame, storm_rollout_set_ball) is moved into the flange frame of
+       FK(q0) (its z velocity set to 0); at step h its acceleration is the
+       in-plane part of g in the flange frame of the rolled-out state,
+       integrated with the scheme of Eq. 7.  Term = distance of the ball
+       from ball_center in the plane, weighted by w_ball. */
+    float w_ball;          /* >= 0, finite */
+    float ball_gravity[3]; /* world frame, m/s^2, finite */
+    float ball_center[2];  /* tray centre (x, y) in the flange frame, finite */
 } storm_params;
 
 /* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame
@@ -150,7 +164,9 @@ typedef struct storm_scene {
 typedef struct storm_debug {
     float *u, *q, *v, *a; /* [7][N][H] */
     float *c;             /* [N][H] */
-    float *terms;         /* [8][N][H] */
+    float *terms;         /* [9][N][H]: pos, rot, joint, vel, stop, manip, self, env, ball */
+    float *xd, *xdd;      /* [6][N][H]: flange velocity and acceleration in the world frame (Eq. 8),
+                             linear x, y, z then angular x, y, z: xd = J(q) qd, xdd = Jdot qd + J qdd */
 } storm_debug;
 
 typedef struct storm_ctx_s *storm_ctx;
@@ -204,6 +220,14 @@ int32_t storm_rollout_get_state(storm_ctx ctx, float *h_mean, float *h_sigma2, u
  * step.  Synchronises `stream`. */
 int32_t storm_rollout_set_state(storm_ctx ctx, const float *h_mean, const float *h_sigma2, const uint32_t *h_step,
                                 void *stream);
+
+/* The ball's state at the current arm state for the ball term (appendix on
+ * dynamic object balancing): d_ball [6] = position (m) and velocity (m/s)
+ * in the world frame, device memory, copied on `stream` into the context
+ * and read by every later storm_rollout_step (and graph launch) until the
+ * next call.  A new context holds zeros.  Capturable.  Errors: E_NULL,
+ * E_DEVICE. */
+int32_t storm_rollout_set_ball(storm_ctx ctx, const float *d_ball, void *stream);
 
 /* Gradient of the expected horizon cost (the differentiable form; not in
  * the paper): J(mu) = (1/N) sum_i C_i(mu + sigma * eps_i) with the standard
@@ -277,7 +301,7 @@ typedef struct storm_launch_config {
  * robot.  Every per-problem limit and validation rule of storm_rollout_init
  * applies.  Default launch shape: 8 waves, two workgroups per compute unit,
  * cost-ordered queue.  Synchronises `stream`.  Errors: as init, plus E_RANGE
- * for n_problems < 1. */
+ * for n_problems < 1 and E_UNSUPPORTED for a problem with the ball term. */
 int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_params *params,
                          const storm_robot *robot, const storm_scene *scenes, void *stream);
 

@@ -70,12 +70,14 @@ int32_t validate_params(const storm_params *p)
     if (p->n_null < 0 || p->n_null > p->n_particles) return STORM_E_RANGE;
     if (p->n_halton < 0 || p->n_halton > p->n_particles - p->n_null) return STORM_E_RANGE;
     if (p->n_halton > 0 && (p->n_knots < 4 || p->n_knots > 32)) return STORM_E_RANGE;
-    if (p->cost_mask & ~STORM_COST_ALL) return STORM_E_PARAM;
+    if (p->cost_mask & ~(STORM_COST_ALL | STORM_COST_BALL)) return STORM_E_PARAM;
     if (p->grad_mask & ~(STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP)) return STORM_E_PARAM;
     if (p->comb_filter != 0 && p->comb_filter != 1) return STORM_E_PARAM;
     if (p->cov_per_step != 0 && p->cov_per_step != 1) return STORM_E_PARAM;
     for (int c = 0; c < 3; ++c)
-        if (!finite_f(p->comb[c])) return STORM_E_PARAM;
+        if (!finite_f(p->comb[c]) || !finite_f(p->ball_gravity[c])) return STORM_E_PARAM;
+    if (!finite_f(p->w_ball) || p->w_ball < 0.0f) return STORM_E_PARAM;
+    if (!finite_f(p->ball_center[0]) || !finite_f(p->ball_center[1])) return STORM_E_PARAM;
     if (!p->dt) return STORM_E_NULL;
     for (int h = 0; h < p->horizon; ++h)
         if (!finite_f(p->dt[h]) || !(p->dt[h] > 0.0f)) return STORM_E_PARAM;
@@ -333,12 +335,16 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     for (int k = 0; k < 3; ++k) {
         P.alpha_pos[k] = params->alpha_pos[k];
         P.alpha_rot[k] = params->alpha_rot[k];
+        P.ball_g[k] = params->ball_gravity[k];
     }
+    P.w_ball = params->w_ball;
+    P.ball_c[0] = params->ball_center[0];
+    P.ball_c[1] = params->ball_center[1];
     fill_robot_consts(robot, c->R);
     c->R.n_pairs = n_pairs;
 
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
-    float *self_thr, *grad_part, *cost_part, *grad, *adam;
+    float *self_thr, *grad_part, *cost_part, *grad, *adam, *ball;
     float4 *sph_obs, *obs_bound, *sph_local;
     int32_t *sph_body, *self_off;
     int4 *self_seg;
@@ -368,6 +374,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     }
     STORM_TRY(dalloc(c, &grad, (size_t)H * STORM_DOF));
     STORM_TRY(dalloc(c, &adam, (size_t)2 * H * STORM_DOF));
+    STORM_TRY(dalloc(c, &ball, (size_t)8));
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &self_thr, thr.size()));
@@ -415,6 +422,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         P.grad_part = grad_part;
         P.cost_part = cost_part;
         P.grad = grad;
+        P.ball = ball;
         P.adam_m = adam;
         P.adam_v = adam + (size_t)H * STORM_DOF;
         c->R.sph_local = sph_local;
@@ -452,6 +460,8 @@ int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal
         out.a = dbg->a;
         out.c = dbg->c;
         out.terms = dbg->terms;
+        out.xd = dbg->xd;
+        out.xdd = dbg->xdd;
     }
     out.C = d_C;
     const hipError_t e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, d_noise, out, ctx->waves,
@@ -477,6 +487,19 @@ int32_t storm_rollout_update(storm_ctx ctx, float *d_mean, float *d_sigma2, floa
         return STORM_E_DEVICE;
     }
     ctx->pending = false;
+    return STORM_OK;
+}
+
+int32_t storm_rollout_set_ball(storm_ctx ctx, const float *d_ball, void *stream)
+{
+    if (!ctx || !d_ball) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    const hipError_t e = hipMemcpyAsync(ctx->P.ball, d_ball, sizeof(float) * 6, hipMemcpyDeviceToDevice,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
     return STORM_OK;
 }
 

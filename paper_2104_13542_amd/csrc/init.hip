@@ -39,6 +39,7 @@ __global__ void tables_kernel(ProblemDev P, float *tables, const float *dt_raw, 
         tables[kTabSig0 + t] = (float)(s * s);
         if (!P.cov_step) P.sigma2[t] = (float)(s * s);
     }
+    if (t < 8) P.ball[t] = 0.0f;  // no ball state until storm_rollout_set_ball
     if (t == 0) {
         *P.step = 0u;
         *P.status = 0u;

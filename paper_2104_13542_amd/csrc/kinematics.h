@@ -32,6 +32,71 @@ __device__ __forceinline__ void dh_step(float r[9], float p[3], float ca, float 
     for (int row = 0; row < 3; ++row) dh_step_row(r + 3 * row, p[row], ca, sa, a, d, ct, st);
 }
 
+__device__ __forceinline__ void cross3(const float a[3], const float b[3], float c[3])
+{
+    c[0] = fmaf(a[1], b[2], -a[2] * b[1]);
+    c[1] = fmaf(a[2], b[0], -a[0] * b[2]);
+    c[2] = fmaf(a[0], b[1], -a[1] * b[0]);
+}
+
+// Flange velocity and acceleration (Eq. 8), xd = J qd and xdd = Jdot qd +
+// J qdd, by one outward pass over the joints instead of forming Jdot: w is
+// the angular velocity of the link that carries joint k's axis, so that
+// zdot_k = w x z_k, and the origin o_k, fixed in that link, moves with
+// od_k = od_{k-1} + w x (o_k - o_{k-1}).  Column k of Jdot is then
+// [zdot_k x (p - o_k) + z_k x (pd - od_k); zdot_k].  Rows: linear, angular.
+__device__ __forceinline__ void task_space(const float z[kDof][3], const float o[kDof][3], const float pe[3],
+                                           const float qd[kDof], const float qdd[kDof], float xd[6], float xdd[6])
+{
+    float w[3] = {0.0f, 0.0f, 0.0f}, od[3] = {0.0f, 0.0f, 0.0f};
+    float zd[kDof][3], odk[kDof][3];
+#pragma unroll
+    for (int k = 0; k < kDof; ++k) {
+        if (k > 0) {
+            const float d[3] = {o[k][0] - o[k - 1][0], o[k][1] - o[k - 1][1], o[k][2] - o[k - 1][2]};
+            float t[3];
+            cross3(w, d, t);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) od[c] += t[c];
+        }
+        cross3(w, z[k], zd[k]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            odk[k][c] = od[c];
+            w[c] = fmaf(z[k][c], qd[k], w[c]);
+        }
+    }
+    float pd[3];
+    {
+        const float d[3] = {pe[0] - o[kDof - 1][0], pe[1] - o[kDof - 1][1], pe[2] - o[kDof - 1][2]};
+        cross3(w, d, pd);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pd[c] += od[c];
+    }
+    float lin[3] = {0.0f, 0.0f, 0.0f}, ang[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < kDof; ++k) {
+        const float r[3] = {pe[0] - o[k][0], pe[1] - o[k][1], pe[2] - o[k][2]};
+        const float dv[3] = {pd[0] - odk[k][0], pd[1] - odk[k][1], pd[2] - odk[k][2]};
+        float t1[3], t2[3], jc[3];
+        cross3(zd[k], r, t1);
+        cross3(z[k], dv, t2);
+        cross3(z[k], r, jc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lin[c] = fmaf(t1[c] + t2[c], qd[k], fmaf(jc[c], qdd[k], lin[c]));
+            ang[c] = fmaf(zd[k][c], qd[k], fmaf(z[k][c], qdd[k], ang[c]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xd[c] = pd[c];
+        xd[3 + c] = w[c];
+        xdd[c] = lin[c];
+        xdd[3 + c] = ang[c];
+    }
+}
+
 // sqrt(det(J J^T)) for the geometric Jacobian whose column k is
 // [z_k x (p_e - o_k); z_k].  J J^T (6x6, symmetric positive semi-definite) is
 // accumulated over the seven columns and factorised as L D L^T; the

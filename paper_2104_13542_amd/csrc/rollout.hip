@@ -60,9 +60,50 @@ __device__ __forceinline__ float4 load_bound(const float4 *__restrict__ b, int o
     return o < n ? b[o] : make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
 }
 
+// The ball-on-tray term (appendix on dynamic object balancing), by the pose
+// wave: every lane forms the flange frame of the current state q0 and moves
+// the ball's world state into it (its z velocity dropped); lane (particle,
+// h) takes the in-plane gravity in the flange frame of its rolled-out state
+// and the two segmented scans of Eq. 7's scheme give the ball's velocity
+// and position; the term is the distance from the tray centre.
+__device__ __forceinline__ void ball_term(const ProblemDev &P, const RobotDev &R, const float *__restrict__ x0,
+                                          const float *s_fr, float *s_terms, const int lane, const int h,
+                                          const int H, const float *__restrict__ tab)
+{
+    float r0[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f}, p0[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int f = 0; f < kFrames; ++f) {
+        float st = 0.0f, ct = 1.0f;
+        if (f < kDof) sincosf(x0[f], &st, &ct);
+        dh_step(r0, p0, R.ca[f], R.sa[f], R.a[f], R.d[f], ct, st);
+    }
+    const float bw[3] = {P.ball[0] - p0[0], P.ball[1] - p0[1], P.ball[2] - p0[2]};
+    float xb[2], vb[2], ab[2];
+    const float *E = s_fr + 7 * 12 * kLanes + lane;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        xb[c] = fmaf(r0[c], bw[0], fmaf(r0[3 + c], bw[1], r0[6 + c] * bw[2]));
+        vb[c] = fmaf(r0[c], P.ball[3], fmaf(r0[3 + c], P.ball[4], r0[6 + c] * P.ball[5]));
+        ab[c] = fmaf(E[c * kLanes], P.ball_g[0], fmaf(E[(3 + c) * kLanes], P.ball_g[1],
+                                                      E[(6 + c) * kLanes] * P.ball_g[2]));
+    }
+    const float dt_h = tab[kTabDt + h];
+    float d2 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float v = vb[c] + segmented_scan(dt_h * ab[c], h, H);
+        const float x = xb[c] + segmented_scan(dt_h * v, h, H);
+        const float e = x - P.ball_c[c];
+        d2 = fmaf(e, e, d2);
+    }
+    s_terms[8 * kLanes + lane] = fast_sqrt(d2);
+}
+
 // One 64-lane tile of one problem, executed by the W waves of the calling
 // workgroup; smem is the workgroup's dynamic LDS (rollout_lds_bytes).
-template <int W>
+// kTask: the task-space form, which adds the flange velocity and
+// acceleration outputs (Eq. 8) and the ball-on-tray term.
+template <int W, bool kTask = false>
 __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev &R, const int tile,
                                              const float *__restrict__ x0, const float *__restrict__ goal,
                                              const float *__restrict__ noise, const StepOut &out, float *smem)
@@ -75,10 +116,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     float *s_cen = s_fr + 96 * kLanes;      // [S][3][64]
     float *s_penv = s_cen + 3 * S * kLanes; // [W][64]
     float *s_pself = s_penv + W * kLanes;   // [W][64]
-    float *s_terms = s_pself + W * kLanes;  // [8][64]
-    float *s_sc = s_terms + 8 * kLanes;     // [7][2][64]: sin q_j, cos q_j
+    float *s_terms = s_pself + W * kLanes;  // [kTerms][64]
+    float *s_sc = s_terms + kTerms * kLanes;  // [7][2][64]: sin q_j, cos q_j
     float *s_cn = s_sc + 14 * kLanes;       // [S][64]: |c|^2 of the sphere centres
     float *s_lim = s_cn + S * kLanes;       // [3][7][64]: squared joint, velocity, stop hinges per joint
+    float *s_acc = s_lim + 3 * kDof * kLanes;  // [7][64]: joint accelerations (task-space form only)
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -143,6 +185,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         sincosf(q, &sq, &cq);
         s_sc[(2 * j) * kLanes + lane] = sq;
         s_sc[(2 * j + 1) * kLanes + lane] = cq;
+        if (kTask) s_acc[j * kLanes + lane] = u;
         if (valid) {
             const size_t o = ((size_t)j * N + i) * H + h;
             P.u[o] = u;
@@ -240,8 +283,10 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             s_terms[0 * kLanes + lane] = fast_sqrt(pos2);
             s_terms[1 * kLanes + lane] = fast_sqrt(rot2);
         }
+        if (kTask && (mask & STORM_COST_BALL)) ball_term(P, R, x0, s_fr, s_terms, lane, h, H, tab);
     } else {
-        if (mask & STORM_COST_MANIP) {
+        const bool task_out = kTask && (out.xd != nullptr || out.xdd != nullptr);
+        if ((mask & STORM_COST_MANIP) || task_out) {
             float z[kDof][3], o[kDof][3], pe[3];
 #pragma unroll
             for (int k = 0; k < kDof; ++k) {
@@ -255,7 +300,23 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) pe[c] = s_fr[(7 * 12 + 9 + c) * kLanes + lane];
-            s_terms[5 * kLanes + lane] = manipulability(z, o, pe);
+            if (mask & STORM_COST_MANIP) s_terms[5 * kLanes + lane] = manipulability(z, o, pe);
+            if (task_out) {
+                float qd[kDof], qdd[kDof], xd[6], xdd[6];
+#pragma unroll
+                for (int k = 0; k < kDof; ++k) {
+                    qd[k] = s_v[k * kLanes + lane];
+                    qdd[k] = s_acc[k * kLanes + lane];
+                }
+                task_space(z, o, pe, qd, qdd, xd, xdd);
+                if (valid)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        const size_t at = ((size_t)c * N + i) * H + h;
+                        if (out.xd) out.xd[at] = xd[c];
+                        if (out.xdd) out.xdd[at] = xdd[c];
+                    }
+            }
         }
     }
     __syncthreads();
@@ -451,6 +512,10 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         c = fmaf(P.a_stop, t[4], c);
         c = fmaf(P.a_manip, t[5], c);
         c = fmaf(P.a_coll, t[6] + t[7], c);
+        if (kTask && (mask & STORM_COST_BALL)) {
+            t[8] = s_terms[8 * kLanes + lane];
+            c = fmaf(P.w_ball, t[8], c);
+        }
         if (valid) {
             if (out.c) out.c[(size_t)i * H + h] = c;
             if (out.terms)
@@ -470,7 +535,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
 // The fields the first loads of a tile depend on come first, as scalar
 // arguments, so that they are preloaded into SGPRs; the rest of the problem
 // follows in P.
-template <int W>
+template <int W, bool kTask>
 __global__ __launch_bounds__(W * kLanes) void rollout_kernel(uint32_t *step, float *mean, float *sigma2,
                                                              const float *halton, const float *tables, int32_t N,
                                                              int32_t H, int32_t ppt, int32_t n_halton,
@@ -492,7 +557,7 @@ __global__ __launch_bounds__(W * kLanes) void rollout_kernel(uint32_t *step, flo
     Q.n_halton = n_halton;
     Q.n_null = n_null;
     Q.cost_mask = cost_mask;
-    rollout_tile<W>(Q, R, blockIdx.x, x0, goal, noise, out, smem);
+    rollout_tile<W, kTask>(Q, R, blockIdx.x, x0, goal, noise, out, smem);
 }
 
 // Persistent form for many problems: each workgroup takes (problem, tile)
@@ -526,9 +591,10 @@ __global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const Problem
     }
 }
 
-size_t rollout_lds_bytes(int S, int W)
+size_t rollout_lds_bytes(int S, int W, bool task = false)
 {
-    return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof + 3 * kDof) * kLanes * sizeof(float);
+    return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof + 3 * kDof + (task ? kDof : 0)) * kLanes *
+           sizeof(float);
 }
 
 }  // namespace
@@ -537,12 +603,16 @@ hipError_t set_rollout_lds_limit()
 {
     const int bytes16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16);
     const int bytes8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8);
-    const void *fns[4] = {reinterpret_cast<const void *>(&rollout_kernel<16>),
-                          reinterpret_cast<const void *>(&rollout_kernel<8>),
+    const int task16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16, true);
+    const int task8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8, true);
+    const void *fns[6] = {reinterpret_cast<const void *>(&rollout_kernel<16, false>),
+                          reinterpret_cast<const void *>(&rollout_kernel<8, false>),
                           reinterpret_cast<const void *>(&rollout_batch_kernel<16>),
-                          reinterpret_cast<const void *>(&rollout_batch_kernel<8>)};
-    const int bytes[4] = {bytes16, bytes8, bytes16, bytes8};
-    for (int k = 0; k < 4; ++k) {
+                          reinterpret_cast<const void *>(&rollout_batch_kernel<8>),
+                          reinterpret_cast<const void *>(&rollout_kernel<16, true>),
+                          reinterpret_cast<const void *>(&rollout_kernel<8, true>)};
+    const int bytes[6] = {bytes16, bytes8, bytes16, bytes8, task16, task8};
+    for (int k = 0; k < 6; ++k) {
         const hipError_t e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[k]);
         if (e != hipSuccess) return e;
     }
@@ -569,17 +639,16 @@ hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int 
 hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x0, const float *goal,
                           const float *noise, const StepOut &out, int waves, hipStream_t stream)
 {
-    const size_t lds = rollout_lds_bytes(R.n_spheres, waves);
+    // the task-space form only where it is asked for: the ball term, or the
+    // flange velocity and acceleration outputs
+    const bool task = (P.cost_mask & STORM_COST_BALL) || out.xd != nullptr || out.xdd != nullptr;
+    const size_t lds = rollout_lds_bytes(R.n_spheres, waves, task);
     const dim3 grid((unsigned)P.n_tiles);
-    if (waves == 16) {
-        hipLaunchKernelGGL(rollout_kernel<16>, grid, dim3(16 * kLanes), lds, stream, P.step, P.mean, P.sigma2, P.halton,
-                           P.tables, P.N, P.H, P.ppt, P.n_halton, P.n_null, P.cost_mask, P, R, x0, goal, noise, out);
-    } else if (waves == 8) {
-        hipLaunchKernelGGL(rollout_kernel<8>, grid, dim3(8 * kLanes), lds, stream, P.step, P.mean, P.sigma2, P.halton,
-                           P.tables, P.N, P.H, P.ppt, P.n_halton, P.n_null, P.cost_mask, P, R, x0, goal, noise, out);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    if (waves != 16 && waves != 8) return hipErrorInvalidValue;
+    auto kernel = waves == 16 ? (task ? rollout_kernel<16, true> : rollout_kernel<16, false>)
+                              : (task ? rollout_kernel<8, true> : rollout_kernel<8, false>);
+    hipLaunchKernelGGL(kernel, grid, dim3(waves * kLanes), lds, stream, P.step, P.mean, P.sigma2, P.halton, P.tables,
+                       P.N, P.H, P.ppt, P.n_halton, P.n_null, P.cost_mask, P, R, x0, goal, noise, out);
     return hipGetLastError();
 }
 

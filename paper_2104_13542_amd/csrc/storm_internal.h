@@ -45,6 +45,7 @@ struct ProblemDev {
     float alpha_pos[3], alpha_rot[3];
     uint32_t comb;      // the Gaussian particles' noise is comb-filtered (response in the tables)
     uint32_t cov_step;  // sigma2 is [H][7] (Eq. 5 per step) instead of [7]
+    float w_ball, ball_g[3], ball_c[2];  // ball term: weight, gravity (world), tray centre (flange x, y)
     const float *tables;    // [kTabSize]
     const float *halton;    // [7][n_halton][H] smoothed Halton standard noise
     const float4 *sph_obs;  // [n_sph_obs] centre, radius
@@ -61,6 +62,7 @@ struct ProblemDev {
     float *cost_part;       // [chunks] adjoint partial horizon-cost sums per tile chunk
     float *grad;            // [H][7] gradient of the expected horizon cost
     float *adam_m, *adam_v; // [H][7] Adam moments of the refinement
+    float *ball;            // [8]: ball position, velocity (world frame) at the current state, pad
 };
 
 // Robot constants, passed by value (kernel-argument segment, wave-uniform).
@@ -102,6 +104,7 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 // Optional per-step outputs.
 struct StepOut {
     float *u, *q, *v, *a, *c, *terms, *C;
+    float *xd, *xdd;  // [6][N][H] flange velocity and acceleration (Eq. 8)
 };
 
 // Launchers (defined in the .hip translation units).

@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libstorm.so")
 
 DOF = 7
-NTERMS = 8
+NTERMS = 9
 TERM_NAMES = ("pos", "rot", "joint", "vel", "stop", "manip", "self", "env")
 
 STORM_OK = 0
@@ -55,6 +55,7 @@ class storm_params(ctypes.Structure):
         ("a_stop", ctypes.c_float), ("a_joint", ctypes.c_float), ("a_vel", ctypes.c_float),
         ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float), ("grad_mask", ctypes.c_uint32),
         ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_float * 3), ("cov_per_step", ctypes.c_int32),
+        ("w_ball", ctypes.c_float), ("ball_gravity", ctypes.c_float * 3), ("ball_center", ctypes.c_float * 2),
     ]
 
 
@@ -71,7 +72,7 @@ class storm_scene(ctypes.Structure):
 
 
 class storm_debug(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_void_p) for k in ("u", "q", "v", "a", "c", "terms")]
+    _fields_ = [(k, ctypes.c_void_p) for k in ("u", "q", "v", "a", "c", "terms", "xd", "xdd")]
 
 
 _lib = None
@@ -85,7 +86,7 @@ EXPORTS = (
     "storm_batch_set_config", "storm_batch_get_config", "storm_batch_autotune", "storm_batch_get_state",
     "storm_batch_set_state", "storm_batch_costs", "storm_batch_destroy", "storm_plant_step",
     "storm_rollout_grad", "storm_rollout_refine", "storm_rollout_graph_create_refine",
-    "storm_batch_refine", "storm_batch_graph_create_refine",
+    "storm_batch_refine", "storm_batch_graph_create_refine", "storm_rollout_set_ball",
 )
 
 
@@ -108,6 +109,7 @@ def lib():
                                          ctypes.POINTER(storm_robot), ctypes.POINTER(storm_scene), vp]
         L.storm_rollout_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(storm_debug), vp, vp]
         L.storm_rollout_update.argtypes = [vp, vp, vp, vp, i32, vp]
+        L.storm_rollout_set_ball.argtypes = [vp, vp, vp]
         L.storm_rollout_destroy.argtypes = [vp]
         L.storm_rollout_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
         L.storm_rollout_get_state.argtypes = [vp, vp, vp, vp, vp]
@@ -169,6 +171,11 @@ def make_params(p: "inputs.Params"):
     sp.grad_mask = getattr(p, "grad_mask", 0)
     sp.comb_filter = int(getattr(p, "comb_filter", 0))
     sp.cov_per_step = int(getattr(p, "cov_per_step", 0))
+    sp.w_ball = float(getattr(p, "w_ball", 0.0))
+    for c, g in enumerate(getattr(p, "ball_gravity", (0.0, 0.0, -9.81))):
+        sp.ball_gravity[c] = float(g)
+    for c, x in enumerate(getattr(p, "ball_center", (0.0, 0.0))):
+        sp.ball_center[c] = float(x)
     comb = getattr(p, "comb", (1.0, 0.0, 0.0))
     for c in range(3):
         sp.comb[c] = float(comb[c])
@@ -244,9 +251,11 @@ class Rollout:
             pass
 
     # -- MPC iteration -----------------------------------------------------
-    def step(self, goal, x0=None, noise=None, debug=False, C=None):
+    def step(self, goal, x0=None, noise=None, debug=False, C=None, task_space=False):
         """Sample + roll out.  goal: [12] device tensor.  noise: optional
-        [7][N][H] standard normals.  Returns a dict of the requested outputs."""
+        [7][N][H] standard normals.  task_space: also return the flange
+        velocity and acceleration xd, xdd [6][N][H] (Eq. 8).  Returns a dict
+        of the requested outputs."""
         N, H = self.N, self.H
         x0 = self.x0 if x0 is None else x0
         out = {}
@@ -257,7 +266,14 @@ class Rollout:
                 out[k] = torch.empty((DOF, N, H), **kw)
             out["c"] = torch.empty((N, H), **kw)
             out["terms"] = torch.empty((NTERMS, N, H), **kw)
-            dbg = storm_debug(*[ctypes.c_void_p(out[k].data_ptr()) for k in ("u", "q", "v", "a", "c", "terms")])
+            ptrs = [ctypes.c_void_p(out[k].data_ptr()) for k in ("u", "q", "v", "a", "c", "terms")]
+            dbg = storm_debug(*ptrs)
+        if task_space:
+            if dbg is None:
+                dbg = storm_debug()
+            for k in ("xd", "xdd"):
+                out[k] = torch.empty((6, N, H), dtype=torch.float32, device=self.device)
+                setattr(dbg, k, ctypes.c_void_p(out[k].data_ptr()))
         if C is None:
             C = torch.empty(N, dtype=torch.float32, device=self.device)
         out["C"] = C
@@ -265,6 +281,13 @@ class Rollout:
                                         ctypes.byref(dbg) if dbg is not None else None, _ptr(C), _stream()),
                "storm_rollout_step")
         return out
+
+    def set_ball(self, ball):
+        """The ball's world-frame position and velocity [6] (device tensor)
+        at the current arm state, for the ball term."""
+        ball = ball.contiguous()
+        _check(lib().storm_rollout_set_ball(self._h, _ptr(ball), _stream()), "storm_rollout_set_ball")
+        self._ball = ball  # kept alive until the copy has run
 
     def _sig_shape(self):
         return (self.H, DOF) if getattr(self.problem.params, "cov_per_step", 0) else (DOF,)

@@ -29,9 +29,10 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-def run_pair(problem, oracle_mod, noise_nhj=None, step_index=0, mean=None, sigma2=None):
+def run_pair(problem, oracle_mod, noise_nhj=None, step_index=0, mean=None, sigma2=None, task_space=False):
     """One step + update on both sides.  Returns (gpu dict, oracle rollout,
-    oracle update, eps used)."""
+    oracle update, eps used).  A problem with a ball (ball_tray) gets the
+    same float32 world-frame ball state on both sides."""
     from paper_2104_13542_amd import storm
 
     p = problem.params
@@ -46,6 +47,10 @@ def run_pair(problem, oracle_mod, noise_nhj=None, step_index=0, mean=None, sigma
     o.goal = f32(o.goal)
     r = storm.Rollout(problem)
     try:
+        if problem.ball_tray is not None:
+            bw = f32(o.ball_world_from_tray(problem.ball_tray))
+            o.set_ball(bw)
+            r.set_ball(torch.tensor(bw, dtype=torch.float32, device="cuda"))
         if mean is not None or sigma2 is not None or step_index:
             r.set_state(mean=mean, sigma2=sigma2, step=step_index)
         mean0 = np.zeros((H, 7)) if mean is None else f32(mean)
@@ -55,13 +60,16 @@ def run_pair(problem, oracle_mod, noise_nhj=None, step_index=0, mean=None, sigma
         if noise_nhj is not None:
             noise_nhj = f32(noise_nhj)
             noise_t = torch.tensor(noise_nhj.transpose(2, 0, 1).copy(), dtype=torch.float32, device="cuda")
-        out = r.step(goal, noise=noise_t, debug=True)
+        out = r.step(goal, noise=noise_t, debug=True, task_space=task_space)
         cmd, mean_new, sig2_new = r.update(shift=True)
         torch.cuda.synchronize()
         g = {k: v.detach().cpu().double().numpy() for k, v in out.items()}
         for k in ("u", "q", "v", "a"):
             g[k] = g[k].transpose(1, 2, 0)
         g["terms"] = g["terms"].transpose(1, 2, 0)
+        for k in ("xd", "xdd"):
+            if k in g:
+                g[k] = g[k].transpose(1, 2, 0)
         g["cmd"] = cmd.cpu().double().numpy()
         g["mean"] = mean_new.cpu().double().numpy()
         g["sigma2"] = sig2_new.cpu().double().numpy()

@@ -75,10 +75,12 @@ def test_init_validation(storm):
         ("beta", 0.0, E.STORM_E_PARAM), ("beta", float("nan"), E.STORM_E_PARAM), ("gamma", 1.5, E.STORM_E_PARAM),
         ("alpha_mu", -0.1, E.STORM_E_PARAM), ("alpha_sigma", 2.0, E.STORM_E_PARAM),
         ("k_jl", 0.5, E.STORM_E_PARAM), ("sigma2_min", -1.0, E.STORM_E_PARAM),
-        ("cost_mask", 0x80, E.STORM_E_PARAM), ("w_pos", float("inf"), E.STORM_E_PARAM),
+        ("cost_mask", 0x100, E.STORM_E_PARAM), ("w_pos", float("inf"), E.STORM_E_PARAM),
         ("grad_mask", 0x40, E.STORM_E_PARAM), ("grad_mask", 0x10, E.STORM_E_PARAM),
         ("comb_filter", 2, E.STORM_E_PARAM), ("comb_filter", -1, E.STORM_E_PARAM),
         ("cov_per_step", 2, E.STORM_E_PARAM), ("cov_per_step", -1, E.STORM_E_PARAM),
+        ("w_ball", -1.0, E.STORM_E_PARAM), ("w_ball", float("inf"), E.STORM_E_PARAM),
+        ("grad_mask", 0x80, E.STORM_E_PARAM),
     ]
     for field, val, want in cases:
         sp2, rb2, sc2, keep2 = _args(storm)
@@ -97,6 +99,23 @@ def test_init_validation(storm):
     sp2.comb_filter = 1
     sp2.comb[1] = float("nan")  # comb filter coefficients must be finite
     assert _init(storm, sp2, rb2, sc2) == E.STORM_E_PARAM
+    for field, k in (("ball_gravity", 2), ("ball_center", 1)):
+        sp2, rb2, sc2, keep2 = _args(storm)
+        getattr(sp2, field)[k] = float("nan")
+        assert _init(storm, sp2, rb2, sc2) == E.STORM_E_PARAM, field
+
+
+def test_batch_rejects_the_ball_term(storm):
+    """The ball term is for plain contexts: a batch holding a problem with it
+    is refused before any device work."""
+    sp, rb, sc, keep = _args(storm, inputs.config_ball(0, n_particles=32, horizon=10))
+    params = (storm.storm_params * 2)(sp, sp)
+    params[0].cost_mask = inputs.COST_JOINT
+    scenes = (storm.storm_scene * 2)(sc, sc)
+    b = ctypes.c_void_p()
+    assert storm.lib().storm_batch_init(ctypes.byref(b), 2, params, ctypes.byref(rb), scenes, None) \
+        == storm.STORM_E_UNSUPPORTED
+    assert not b.value
 
 
 def test_robot_and_scene_validation(storm):
