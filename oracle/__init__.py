@@ -51,7 +51,7 @@ class OracleParams(ctypes.Structure):
         ("cost_mask", ctypes.c_uint32), ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_double * 3),
         ("cov_per_step", ctypes.c_int32), ("pad2", ctypes.c_int32), ("sigma_init2", ctypes.c_double * 7),
         ("w_ball", ctypes.c_double), ("ball_gravity", ctypes.c_double * 3), ("ball_center", ctypes.c_double * 2),
-        ("ball", ctypes.c_double * 6),
+        ("ball", ctypes.c_double * 6), ("self_model", ctypes.c_int32), ("pad3", ctypes.c_int32),
     ]
 
 
@@ -63,6 +63,7 @@ class OracleModel(ctypes.Structure):
         ("spheres", ctypes.POINTER(ctypes.c_double)),
         ("n_obstacles", ctypes.c_int32), ("pad1", ctypes.c_int32),
         ("obstacles", ctypes.POINTER(ctypes.c_double)),
+        ("self_mlp", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -119,6 +120,10 @@ def lib():
         L.oracle_grad.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD, _PD,
                                   _PD, _PD, _PD, _PD, _PD]
         L.oracle_task_space.argtypes = [_PD, _PD, _PD, _PD, _PD, _PD]
+        L.oracle_self_mlp.argtypes = [_PD, _PD]
+        L.oracle_self_mlp.restype = ctypes.c_double
+        L.oracle_self_distance.argtypes = [ctypes.POINTER(OracleModel), _PD]
+        L.oracle_self_distance.restype = ctypes.c_double
         L.oracle_ball_traj.argtypes = [ctypes.POINTER(OracleParams), ctypes.POINTER(OracleModel), _PD, _PD, _PD,
                                        _PD]
         L.oracle_cost_ball.argtypes = [ctypes.POINTER(OracleParams), _PD]
@@ -220,6 +225,11 @@ def task_space(dh, q, qd, qdd):
     return xd, xdd
 
 
+def self_mlp(prm, q):
+    """The learned self-collision distance (jointNERF form) at q."""
+    return lib().oracle_self_mlp(_d(_f64(prm)), _d(_f64(q)))
+
+
 def det(A):
     A = _f64(A).copy()
     return lib().oracle_det(A.shape[0], _d(A))
@@ -280,6 +290,7 @@ class Oracle:
             p.ball_gravity[k] = float(g)
         for k, c in enumerate(getattr(pr, "ball_center", (0.0, 0.0))):
             p.ball_center[k] = float(c)
+        p.self_model = int(getattr(pr, "self_model", 0))
         self.params = p
 
         self.dh = _f64(inputs.PANDA_DH if dh is None else dh)
@@ -298,6 +309,9 @@ class Oracle:
         m.spheres = _d(self.spheres)
         m.n_obstacles = self.obstacles.shape[0]
         m.obstacles = _d(self.obstacles) if m.n_obstacles else None
+        mlp = getattr(problem, "self_mlp", None)
+        self.self_mlp_prm = None if mlp is None else _f64(mlp)
+        m.self_mlp = None if mlp is None else _d(self.self_mlp_prm)
         self.model = m
         self.dt = _f64(pr.dt)
         self.x0 = _f64(np.concatenate([problem.q0, problem.v0, problem.a0]))
@@ -435,6 +449,10 @@ class Oracle:
         lib().oracle_ball_traj(ctypes.byref(self.params), ctypes.byref(self.model), _d(self.dt), _d(q0),
                                _d(_f64(q)), _d(xb))
         return xb
+
+    def self_distance(self, q):
+        """The sphere model's signed closest distance between links at q."""
+        return lib().oracle_self_distance(ctypes.byref(self.model), _d(fk(self.dh, q)))
 
     def cost_self(self, frames):
         frames = _f64(frames)

@@ -72,6 +72,8 @@ typedef struct {
     double ball_gravity[3];  /* g in the world frame */
     double ball_center[2];   /* tray centre in the flange frame (x, y) */
     double ball[6];          /* ball position and velocity in the world frame at the current state */
+    int32_t self_model;      /* 0: sphere pairs; 1: the learned self-collision network (jointNERF form) */
+    int32_t pad3;
 } oracle_params;
 
 typedef struct {
@@ -81,6 +83,7 @@ typedef struct {
     const double *spheres; /* [S][5]: body (1..8), x, y, z, r in the body frame */
     int32_t n_obstacles, pad1;
     const double *obstacles; /* [O][16]: kind, centre, extents, R (row-major) */
+    const double *self_mlp;  /* the network's parameters (oracle_self_mlp), or NULL */
 } oracle_model;
 
 /* ------------------------------------------------------------------------ */
@@ -711,6 +714,67 @@ double oracle_cost_env(const oracle_model *mdl, const double T[NFRAMES][16])
     return total;
 }
 
+/* Learned self-collision distance (Sec. 3.2, Eq. 13, the jointNERF form):
+ * input [sin q, cos q] (14), three hidden layers of 256, 128 and 64 units
+ * with ReLU, then one linear output, the predicted closest distance
+ * between the links (positive when they penetrate).  prm holds, in order,
+ * W1 [256][14], b1 [256], W2 [128][256], b2 [128], W3 [64][128], b3 [64],
+ * w4 [64], b4 (each weight matrix [out][in]). */
+#define MLP_H1 256
+#define MLP_H2 128
+#define MLP_H3 64
+#define MLP_IN 14
+double oracle_self_mlp(const double *prm, const double q[DOF])
+{
+    double x[MLP_IN], a1[MLP_H1], a2[MLP_H2], a3[MLP_H3];
+    for (int j = 0; j < DOF; ++j) {
+        x[j] = sin(q[j]);
+        x[DOF + j] = cos(q[j]);
+    }
+    const double *W1 = prm, *b1 = W1 + MLP_H1 * MLP_IN;
+    const double *W2 = b1 + MLP_H1, *b2 = W2 + MLP_H2 * MLP_H1;
+    const double *W3 = b2 + MLP_H2, *b3 = W3 + MLP_H3 * MLP_H2;
+    const double *w4 = b3 + MLP_H3, *b4 = w4 + MLP_H3;
+    for (int o = 0; o < MLP_H1; ++o) {
+        double s = b1[o];
+        for (int k = 0; k < MLP_IN; ++k) s += W1[o * MLP_IN + k] * x[k];
+        a1[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < MLP_H2; ++o) {
+        double s = b2[o];
+        for (int k = 0; k < MLP_H1; ++k) s += W2[o * MLP_H1 + k] * a1[k];
+        a2[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < MLP_H3; ++o) {
+        double s = b3[o];
+        for (int k = 0; k < MLP_H2; ++k) s += W3[o * MLP_H2 + k] * a2[k];
+        a3[o] = s > 0.0 ? s : 0.0;
+    }
+    double d = b4[0];
+    for (int k = 0; k < MLP_H3; ++k) d += w4[k] * a3[k];
+    return d;
+}
+
+/* The sphere model's signed closest distance between links: the largest
+ * r_a + r_b - |c_a - c_b| over the checked pairs (positive = penetration),
+ * the quantity the network is trained to predict. */
+double oracle_self_distance(const oracle_model *mdl, const double T[NFRAMES][16])
+{
+    double best = -INFINITY;
+    for (int a = 0; a < mdl->n_spheres; ++a)
+        for (int b = a + 1; b < mdl->n_spheres; ++b) {
+            int ba = (int)mdl->spheres[a * 5], bb = (int)mdl->spheres[b * 5];
+            if (bb - ba < 2 && ba - bb < 2) continue;
+            double ca[3], cb[3];
+            sphere_centre(mdl, T, a, ca);
+            sphere_centre(mdl, T, b, cb);
+            double dx = ca[0] - cb[0], dy = ca[1] - cb[1], dz = ca[2] - cb[2];
+            double v = mdl->spheres[a * 5 + 4] + mdl->spheres[b * 5 + 4] - sqrt(dx * dx + dy * dy + dz * dz);
+            if (v > best) best = v;
+        }
+    return best;
+}
+
 /* All terms at one state; terms = [pos, rot, joint, vel, stop, manip, self,
  * env, ball] (unweighted; the ball term depends on the whole trajectory and
  * is added by the rollout, 0 here); returns the weighted running cost of
@@ -735,7 +799,14 @@ double oracle_running_cost(const oracle_params *p, const oracle_model *mdl, cons
         oracle_jacobian(T, J);
         terms[5] = oracle_cost_manip(oracle_manipulability(J), p->k_m);
     }
-    if (m & MASK_SELF) terms[6] = oracle_cost_self(mdl, T);
+    if (m & MASK_SELF) {
+        if (p->self_model == 1) {
+            double d = oracle_self_mlp(mdl->self_mlp, q);
+            terms[6] = d > 0.0 ? d : 0.0; /* Eq. 13 */
+        } else {
+            terms[6] = oracle_cost_self(mdl, T);
+        }
+    }
     if (m & MASK_ENV) terms[7] = oracle_cost_env(mdl, T);
     return p->w_pos * terms[0] + p->w_rot * terms[1] + p->a_joint * terms[2] + p->a_vel * terms[3] +
            p->a_stop * terms[4] + p->a_manip * terms[5] + p->a_coll * (terms[6] + terms[7]);

@@ -140,6 +140,7 @@ class Params:
     w_ball: float = 0.0
     ball_gravity: tuple = (0.0, 0.0, -9.81)  # world frame, m/s^2
     ball_center: tuple = (0.0, 0.0)  # tray centre in the flange frame (x, y), m
+    self_model: int = 0  # self-collision term: 0 sphere pairs, 1 the learned network (Problem.self_mlp)
 
 
 @dataclasses.dataclass
@@ -154,6 +155,9 @@ class Problem:
     # ball state in the flange frame of q0: position (x, y, z) and velocity;
     # the caller moves it to the world frame with its own forward kinematics
     ball_tray: np.ndarray = None
+    # parameters of the learned self-collision network (self_model = 1), the
+    # layout of SELF_MLP_LAYOUT
+    self_mlp: np.ndarray = None
 
 
 def random_rotation(rng: np.random.Generator) -> np.ndarray:
@@ -281,6 +285,39 @@ def config_ball(seed: int = 0, n_particles: int = 500, horizon: int = 30) -> Pro
                cost_mask=COST_BALL | COST_JOINT | COST_VEL | COST_STOP | COST_MANIP | COST_SELF, w_ball=100.0)
     return Problem(p, q0, np.zeros(DOF), np.zeros(DOF), PANDA_READY.copy(), np.zeros((0, OBSTACLE_STRIDE)),
                    panda_spheres(), ball)
+
+
+# The learned self-collision network (Eq. 13, jointNERF form): input
+# [sin q, cos q], hidden layers of 256, 128 and 64 units (ReLU), one output.
+# Parameters in one flat array, in this order (weights [out][in]).
+SELF_MLP_LAYOUT = (("W1", (256, 14)), ("b1", (256,)), ("W2", (128, 256)), ("b2", (128,)),
+                   ("W3", (64, 128)), ("b3", (64,)), ("w4", (64,)), ("b4", (1,)))
+SELF_MLP_SIZE = sum(int(np.prod(s)) for _, s in SELF_MLP_LAYOUT)
+
+
+def random_self_mlp(seed: int = 0) -> np.ndarray:
+    """Seeded network parameters with He-scaled weights, every value exactly
+    representable in FP16 (so a half-precision evaluation starts from the
+    same weights)."""
+    rng = np.random.default_rng(9000 + seed)
+    out = []
+    for name, shape in SELF_MLP_LAYOUT:
+        if name.startswith("W") or name == "w4":
+            fan_in = shape[-1]
+            v = rng.normal(scale=math.sqrt(2.0 / fan_in), size=shape)
+        else:
+            v = rng.uniform(-0.1, 0.1, size=shape)
+        out.append(v.reshape(-1))
+    return np.concatenate(out).astype(np.float16).astype(np.float64)
+
+
+def config_self_mlp(seed: int = 0, n_particles: int = 500, horizon: int = 30) -> Problem:
+    """The STORM-shaped step with the learned self-collision network in place
+    of the sphere pairs (random parameters of the published shape)."""
+    prob = config2(seed, n_particles=n_particles, horizon=horizon)
+    prob.params.self_model = 1
+    prob.self_mlp = random_self_mlp(seed)
+    return prob
 
 
 def standard_normal(seed: int, shape) -> np.ndarray:

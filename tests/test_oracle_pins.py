@@ -856,3 +856,103 @@ def test_ball_term_in_the_rollout(oracle_lib):
         np.testing.assert_allclose(r["terms"][i, :, 8], d, rtol=1e-14)
         np.testing.assert_allclose(r["c"][i], r0["c"][i] + prob.params.w_ball * d, rtol=1e-13)
     np.testing.assert_array_equal(r0["terms"][..., 8], 0.0)
+
+
+# ---------------------------------------------------------------------------
+# The learned self-collision network (Eq. 13, jointNERF form)
+# ---------------------------------------------------------------------------
+
+def _mlp_parts(prm):
+    out, k = {}, 0
+    for name, shape in inputs.SELF_MLP_LAYOUT:
+        n = int(np.prod(shape))
+        out[name] = prm[k:k + n].reshape(shape)
+        k += n
+    return out
+
+
+def _mlp_flat(parts):
+    return np.concatenate([parts[name].reshape(-1) for name, _ in inputs.SELF_MLP_LAYOUT])
+
+
+def _encode(q):
+    return np.concatenate([np.sin(q), np.cos(q)])
+
+
+def test_self_mlp_linear_regime_collapses(oracle_lib):
+    """With non-negative deep weights and positive biases every ReLU is
+    active, so the network is affine in the encoding: d = w4 W3 W2 W1 x +
+    const, the product taken in the opposite order to the layer loops (a
+    transposed or misindexed layer fails it)."""
+    rng = np.random.default_rng(0)
+    P = _mlp_parts(inputs.random_self_mlp(1).copy())
+    P["W1"] = rng.normal(size=P["W1"].shape) * 0.1
+    P["b1"] = np.full(256, 5.0)
+    P["W2"] = np.abs(rng.normal(size=P["W2"].shape)) * 0.01
+    P["W3"] = np.abs(rng.normal(size=P["W3"].shape)) * 0.01
+    P["b2"], P["b3"] = np.full(128, 0.1), np.full(64, 0.1)
+    prm = _mlp_flat(P)
+    Wt = P["w4"] @ P["W3"] @ P["W2"] @ P["W1"]
+    c = P["w4"] @ (P["W3"] @ (P["W2"] @ P["b1"] + P["b2"]) + P["b3"]) + P["b4"][0]
+    for s in range(5):
+        q = inputs.random_q(np.random.default_rng(10 + s))
+        np.testing.assert_allclose(oracle_lib.self_mlp(prm, q), Wt @ _encode(q) + c, rtol=1e-12)
+
+
+def test_self_mlp_single_relu_path(oracle_lib):
+    """Weights that route sin q_0 through one unit per layer give
+    d = max(0, sin q_0) + b4; a cosine input through the same path gives
+    max(0, cos q_3)."""
+    P = {name: np.zeros(shape) for name, shape in inputs.SELF_MLP_LAYOUT}
+    P["W1"][7, 0] = 1.0
+    P["W2"][3, 7] = 1.0
+    P["W3"][60, 3] = 1.0
+    P["w4"][60] = 1.0
+    P["b4"][0] = -0.25
+    prm = _mlp_flat(P)
+    for q0 in (-0.7, 0.0, 0.4, 2.5):
+        q = np.zeros(7)
+        q[0] = q0
+        assert oracle_lib.self_mlp(prm, q) == pytest.approx(max(0.0, math.sin(q0)) - 0.25, abs=1e-15)
+    P["W1"][7, 0] = 0.0
+    P["W1"][7, 7 + 3] = 1.0
+    prm = _mlp_flat(P)
+    for q3 in (-2.0, 0.3, 1.9):
+        q = np.zeros(7)
+        q[3] = q3
+        assert oracle_lib.self_mlp(prm, q) == pytest.approx(max(0.0, math.cos(q3)) - 0.25, abs=1e-15)
+
+
+def test_self_mlp_hidden_permutation_invariance(oracle_lib):
+    """Renumbering the hidden units of a layer (rows of its weights and bias,
+    columns of the next layer's weights) leaves the output unchanged."""
+    prm = inputs.random_self_mlp(2)
+    P = _mlp_parts(prm.copy())
+    rng = np.random.default_rng(4)
+    p1, p2 = rng.permutation(256), rng.permutation(128)
+    Q = dict(P)
+    Q["W1"], Q["b1"], Q["W2"] = P["W1"][p1], P["b1"][p1], P["W2"][:, p1]
+    Q["W2"], Q["b2"], Q["W3"] = Q["W2"][p2], P["b2"][p2], P["W3"][:, p2]
+    prm2 = _mlp_flat(Q)
+    for s in range(5):
+        q = inputs.random_q(np.random.default_rng(20 + s))
+        assert oracle_lib.self_mlp(prm2, q) == pytest.approx(oracle_lib.self_mlp(prm, q), rel=1e-13, abs=1e-15)
+
+
+def test_self_model_selects_the_network(oracle_lib):
+    """With self_model = 1 the self-collision term is max(0, d) of the
+    network at the state, and the sphere model's term is max(0, signed
+    distance)."""
+    prob = inputs.config_self_mlp(3, n_particles=6, horizon=5)
+    eps = inputs.standard_normal(2, (6, 5, 7))
+    r = oracle_lib.Oracle(prob).rollout(np.zeros((5, 7)), np.full(7, 0.3), eps)
+    d = np.array([[oracle_lib.self_mlp(prob.self_mlp, r["q"][i, h]) for h in range(5)] for i in range(6)])
+    prob.self_mlp[-1] -= np.median(d)  # some states on each side of zero
+    o = oracle_lib.Oracle(prob)
+    r = o.rollout(np.zeros((5, 7)), np.full(7, 0.3), eps)
+    d = d - np.median(d)
+    assert (d > 0).any() and (d < 0).any()
+    np.testing.assert_allclose(r["terms"][..., 6], np.maximum(d, 0.0), rtol=0, atol=1e-14)
+    for i in range(3):
+        T = oracle_lib.fk(o.dh, r["q"][i, 0])
+        assert o.cost_self(T) == pytest.approx(max(0.0, o.self_distance(r["q"][i, 0])), abs=1e-15)
