@@ -303,6 +303,21 @@ def variants_bench(seed, steps, warmup):
     return {"cov_per_step": cov, "iterations_2": k2}
 
 
+def selfnet_bench(seed, steps, warmup):
+    """The STORM-shaped step with the learned self-collision network (Eq. 13,
+    jointNERF form, on the matrix cores) in place of the sphere pairs, and
+    the same problem with the sphere pairs."""
+    from paper_2104_13542_amd import inputs
+
+    out = {"workload": "N=500 (250 Halton + B-spline, 250 Gaussian), H=30, all cost terms, 30 sphere + 20 cuboid "
+                       "obstacles; self-collision by the network [sin q, cos q] -> 256 -> 128 -> 64 -> 1 (ReLU), "
+                       "FP16 operands, FP32 accumulation; random parameters of that shape",
+           "network_flops_per_step": 2 * (14 * 256 + 256 * 128 + 128 * 64 + 64) * 500 * 30}
+    out.update(_variant_step(inputs.config_self_mlp(seed), steps, warmup))
+    out["sphere_pairs"] = _variant_step(inputs.config2(seed), steps, warmup)
+    return out
+
+
 def ball_bench(seed, steps, warmup):
     """The ball-on-tray workload (the paper's dynamic balancing task): the
     task-space form of the rollout with the ball term, the ball's state set
@@ -702,6 +717,7 @@ def main():
         progress("mixed-sampling workload done")
         line["variants"] = variants_bench(args.seed, args.mixed_steps, warmup=50)
         line["variants"]["ball"] = ball_bench(args.seed, args.mixed_steps, warmup=50)
+        line["variants"]["self_network"] = selfnet_bench(args.seed, args.mixed_steps, warmup=50)
         progress("variant workloads done")
     if args.diff_steps > 0:
         line["differentiable"] = differentiable_bench(args.diff_steps, args.diff_steps, warmup=10)

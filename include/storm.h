@@ -52,6 +52,7 @@ extern "C" {
 #define STORM_MAX_PARTICLES (1 << 20)
 #define STORM_OBSTACLE_STRIDE 16
 #define STORM_NTERMS 9
+#define STORM_SELF_MLP_SIZE 45057
 
 /* Status codes. */
 #define STORM_OK 0
@@ -139,6 +140,13 @@ typedef struct storm_params {
     float w_ball;          /* >= 0, finite */
     float ball_gravity[3]; /* world frame, m/s^2, finite */
     float ball_center[2];  /* tray centre (x, y) in the flange frame, finite */
+    /* Self-collision model of STORM_COST_SELF (Sec. 3.2, Eq. 13).  0: sphere
+       pairs, the term being the largest penetration.  1: the learned network
+       (the paper's jointNERF form) whose parameters storm_robot.self_mlp
+       holds: the term is max(0, d) for its predicted distance d, evaluated
+       on the matrix cores with FP16 operands and FP32 accumulation.  Plain
+       contexts only. */
+    int32_t self_model;
 } storm_params;
 
 /* Serial-chain robot: modified (Craig) Denavit-Hartenberg frames 1..8, frame
@@ -152,6 +160,13 @@ typedef struct storm_robot {
     float qd_max[STORM_DOF];                  /* joint speed limits */
     int32_t n_spheres;                        /* 0 .. STORM_MAX_SPHERES */
     const float *spheres;                     /* host [n_spheres][5] */
+    /* Learned self-collision network (used with storm_params.self_model = 1;
+       may be NULL otherwise): host [STORM_SELF_MLP_SIZE] finite floats, copied
+       at init.  Input [sin q_1..7, cos q_1..7], ReLU layers of 256, 128 and
+       64 units, one linear output; in order W1 [256][14], b1 [256],
+       W2 [128][256], b2 [128], W3 [64][128], b3 [64], w4 [64], b4 (weight
+       matrices [out][in]). */
+    const float *self_mlp;
 } storm_robot;
 
 /* Static scene: obstacle records of STORM_OBSTACLE_STRIDE floats. */
@@ -301,7 +316,8 @@ typedef struct storm_launch_config {
  * robot.  Every per-problem limit and validation rule of storm_rollout_init
  * applies.  Default launch shape: 8 waves, two workgroups per compute unit,
  * cost-ordered queue.  Synchronises `stream`.  Errors: as init, plus E_RANGE
- * for n_problems < 1 and E_UNSUPPORTED for a problem with the ball term. */
+ * for n_problems < 1 and E_UNSUPPORTED for a problem with the ball term or
+ * the learned self-collision model. */
 int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_params *params,
                          const storm_robot *robot, const storm_scene *scenes, void *stream);
 

@@ -74,6 +74,7 @@ int32_t validate_params(const storm_params *p)
     if (p->grad_mask & ~(STORM_COST_POSE | STORM_COST_JOINT | STORM_COST_VEL | STORM_COST_STOP)) return STORM_E_PARAM;
     if (p->comb_filter != 0 && p->comb_filter != 1) return STORM_E_PARAM;
     if (p->cov_per_step != 0 && p->cov_per_step != 1) return STORM_E_PARAM;
+    if (p->self_model != 0 && p->self_model != 1) return STORM_E_PARAM;
     for (int c = 0; c < 3; ++c)
         if (!finite_f(p->comb[c]) || !finite_f(p->ball_gravity[c])) return STORM_E_PARAM;
     if (!finite_f(p->w_ball) || p->w_ball < 0.0f) return STORM_E_PARAM;
@@ -269,6 +270,11 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     if (st != STORM_OK) return st;
     st = validate_scene(scene);
     if (st != STORM_OK) return st;
+    if (params->self_model == 1) {
+        if (!robot->self_mlp) return STORM_E_NULL;
+        for (int k = 0; k < STORM_SELF_MLP_SIZE; ++k)
+            if (!finite_f(robot->self_mlp[k])) return STORM_E_PARAM;
+    }
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     storm_ctx c = new (std::nothrow) storm_ctx_s();
@@ -302,6 +308,9 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
                            params->comb_filter ? params->comb[2] : 0.0f};
     std::vector<int> seg, seg_off;
     const int n_pairs = storm::self_segments(robot, c->waves, seg, seg_off);
+    std::vector<_Float16> net_frag;
+    std::vector<float> net_bias;
+    if (params->self_model == 1) storm::pack_selfnet(robot->self_mlp, net_frag, net_bias);
     const std::vector<float> thr = storm::self_thresholds(robot, reach_bound(robot));
     const int n_seg = (int)seg.size() / 4;
 
@@ -318,6 +327,10 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     P.n_tiles = (N + P.ppt - 1) / P.ppt;
     P.cost_mask = params->cost_mask;
     P.grad_mask = params->grad_mask != 0 ? params->grad_mask : params->cost_mask;
+    // the learned model replaces the sphere pairs: the rollout leaves the
+    // self-collision term to the network pass
+    P.selfnet = (params->self_model == 1 && (params->cost_mask & STORM_COST_SELF)) ? 1u : 0u;
+    if (P.selfnet) P.cost_mask &= ~STORM_COST_SELF;
     P.seed_lo = (uint32_t)params->seed;
     P.seed_hi = (uint32_t)(params->seed >> 32);
     P.beta = params->beta;
@@ -344,7 +357,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     c->R.n_pairs = n_pairs;
 
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
-    float *self_thr, *grad_part, *cost_part, *grad, *adam, *ball;
+    float *self_thr, *grad_part, *cost_part, *grad, *adam, *ball, *qbuf = nullptr;
     float4 *sph_obs, *obs_bound, *sph_local;
     int32_t *sph_body, *self_off;
     int4 *self_seg;
@@ -375,6 +388,15 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &grad, (size_t)H * STORM_DOF));
     STORM_TRY(dalloc(c, &adam, (size_t)2 * H * STORM_DOF));
     STORM_TRY(dalloc(c, &ball, (size_t)8));
+    if (P.selfnet) {
+        STORM_TRY(dalloc(c, &qbuf, (size_t)STORM_DOF * N * H));
+        STORM_TRY(dalloc(c, &c->net_frag, net_frag.size()));
+        STORM_TRY(dalloc(c, &c->net_bias, net_bias.size()));
+        STORM_TRY(hipMemcpyAsync(c->net_frag, net_frag.data(), sizeof(_Float16) * net_frag.size(),
+                                 hipMemcpyHostToDevice, s));
+        STORM_TRY(hipMemcpyAsync(c->net_bias, net_bias.data(), sizeof(float) * net_bias.size(),
+                                 hipMemcpyHostToDevice, s));
+    }
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &self_thr, thr.size()));
@@ -423,6 +445,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         P.cost_part = cost_part;
         P.grad = grad;
         P.ball = ball;
+        P.qbuf = qbuf;
         P.adam_m = adam;
         P.adam_v = adam + (size_t)H * STORM_DOF;
         c->R.sph_local = sph_local;
@@ -447,6 +470,16 @@ fail:
     return map_error(e);
 }
 
+// The rollout of one step, and with the learned self-collision model its
+// network pass after it.
+static hipError_t enqueue_rollout(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_noise,
+                                  const StepOut &out, hipStream_t s)
+{
+    hipError_t e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, d_noise, out, ctx->waves, s);
+    if (e == hipSuccess && ctx->P.selfnet) e = storm::launch_selfnet(ctx->P, ctx->net_frag, ctx->net_bias, out, s);
+    return e;
+}
+
 int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_noise,
                            const storm_debug *dbg, float *d_C, void *stream)
 {
@@ -464,8 +497,7 @@ int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal
         out.xdd = dbg->xdd;
     }
     out.C = d_C;
-    const hipError_t e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, d_noise, out, ctx->waves,
-                                               static_cast<hipStream_t>(stream));
+    const hipError_t e = enqueue_rollout(ctx, d_x0, d_goal, d_noise, out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) {
         ctx->error = STORM_E_DEVICE;
         return STORM_E_DEVICE;
@@ -623,7 +655,7 @@ int32_t create_graph(storm_ctx ctx, const float *d_x0, const float *d_goal, floa
     StepOut none{};
     for (int k = 0; e == hipSuccess && k < iterations; ++k) {
         const bool last = k == iterations - 1;
-        e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, nullptr, none, ctx->waves, s);
+        e = enqueue_rollout(ctx, d_x0, d_goal, nullptr, none, s);
         if (e == hipSuccess)
             e = storm::launch_update(ctx->P, nullptr, nullptr, d_cmd, last && shift != 0 && refine_iters == 0, s);
     }

@@ -172,7 +172,7 @@ int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_param
     // the ball term needs a per-problem ball state and the task-space form
     // of the rollout, which the persistent batched kernel does not carry
     for (int p = 0; p < n_problems; ++p)
-        if (params[p].cost_mask & STORM_COST_BALL) return STORM_E_UNSUPPORTED;
+        if ((params[p].cost_mask & STORM_COST_BALL) || params[p].self_model != 0) return STORM_E_UNSUPPORTED;
     storm_batch b = new (std::nothrow) storm_batch_s();
     if (!b) return STORM_E_NOMEM;
     b->n_problems = n_problems;

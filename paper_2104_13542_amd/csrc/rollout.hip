@@ -102,7 +102,8 @@ __device__ __forceinline__ void ball_term(const ProblemDev &P, const RobotDev &R
 // One 64-lane tile of one problem, executed by the W waves of the calling
 // workgroup; smem is the workgroup's dynamic LDS (rollout_lds_bytes).
 // kTask: the task-space form, which adds the flange velocity and
-// acceleration outputs (Eq. 8) and the ball-on-tray term.
+// acceleration outputs (Eq. 8), the ball-on-tray term and the joint
+// positions the learned self-collision network reads.
 template <int W, bool kTask = false>
 __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev &R, const int tile,
                                              const float *__restrict__ x0, const float *__restrict__ goal,
@@ -189,6 +190,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         if (valid) {
             const size_t o = ((size_t)j * N + i) * H + h;
             P.u[o] = u;
+            if (kTask && P.qbuf != nullptr) P.qbuf[o] = q;
             if (out.u) out.u[o] = u;
             if (out.q) out.q[o] = q;
             if (out.v) out.v[o] = v;
@@ -641,7 +643,7 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
 {
     // the task-space form only where it is asked for: the ball term, or the
     // flange velocity and acceleration outputs
-    const bool task = (P.cost_mask & STORM_COST_BALL) || out.xd != nullptr || out.xdd != nullptr;
+    const bool task = (P.cost_mask & STORM_COST_BALL) || P.selfnet || out.xd != nullptr || out.xdd != nullptr;
     const size_t lds = rollout_lds_bytes(R.n_spheres, waves, task);
     const dim3 grid((unsigned)P.n_tiles);
     if (waves != 16 && waves != 8) return hipErrorInvalidValue;

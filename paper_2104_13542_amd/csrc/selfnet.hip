@@ -1,0 +1,219 @@
+// Learned self-collision term (Sec. 3.2, Eq. 13, the jointNERF form) on the
+// matrix cores.  The network maps the encoding [sin q, cos q] through ReLU
+// layers of 256, 128 and 64 units to one output d, the predicted closest
+// distance between the links (positive when they penetrate); the term is
+// max(0, d).
+//
+// One workgroup (8 waves) per 64-lane tile of the rollout (the same
+// (particle, step) rows): the three hidden layers are 64-row GEMMs on
+// v_mfma_f32_16x16x16_f16 (FP16 operands, FP32 accumulation), with the
+// activations staged in LDS between layers and the weights read as
+// pre-packed per-lane fragments (one coalesced 512-byte load per wave and
+// fragment).  The output layer is a 64-term dot product per row on the
+// vector units; the term then joins the running cost (weight a_coll, as the
+// sphere model's) and, through a segmented scan over the steps, the horizon
+// cost C_i that the rollout kernel wrote.
+#include "sampling.h"
+#include "storm_internal.h"
+
+namespace storm {
+
+namespace {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kNetWaves = 8;
+constexpr int kNetThreads = kNetWaves * kLanes;
+constexpr int kIn = 16;  // 14 inputs padded to one k-step
+constexpr int kX = kIn;             // LDS row strides, in halves / floats
+constexpr int kA1 = kNetH1 + 8;
+constexpr int kA2 = kNetH2 + 8;
+constexpr int kA3 = kNetH3 + 4;
+
+// Row m of the tile: lanes hold 16-row by 16-column MFMA operands with
+//   A (16 x 16, rows x k):    lane l holds A[l % 16][4 (l / 16) + j], j < 4
+//   B (16 x 16, k x columns): lane l holds B[4 (l / 16) + j][l % 16]
+//   D (16 x 16):              lane l holds D[4 (l / 16) + j][l % 16]
+__device__ __forceinline__ half4_t load_a(const _Float16 *s, int stride, int m, int ks, int lane)
+{
+    return *reinterpret_cast<const half4_t *>(s + (16 * m + (lane & 15)) * stride + 16 * ks + 4 * (lane >> 4));
+}
+
+// D tile (m, column block n) + bias, ReLU, stored as FP16 rows of the next
+// layer's input.
+__device__ __forceinline__ void store_relu_h(_Float16 *s, int stride, int m, int n, int lane, float4_t d,
+                                             float bias)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        s[(16 * m + 4 * (lane >> 4) + j) * stride + 16 * n + (lane & 15)] = (_Float16)fmaxf(d[j] + bias, 0.0f);
+}
+
+__global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, const _Float16 *__restrict__ frag,
+                                                              const float *__restrict__ bias, StepOut out)
+{
+    __shared__ __attribute__((aligned(16))) _Float16 s_x[64 * kX];
+    __shared__ __attribute__((aligned(16))) _Float16 s_a1[64 * kA1];
+    __shared__ __attribute__((aligned(16))) _Float16 s_a2[64 * kA2];
+    __shared__ __attribute__((aligned(16))) float s_a3[64 * kA3];
+
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x;
+    const int N = P.N, H = P.H;
+
+    // every weight fragment this wave uses, loaded up front (88 VGPRs)
+    const half4_t *F = reinterpret_cast<const half4_t *>(frag);
+    half4_t b1[2], b2[16], b3[8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) b1[t] = F[kNetFrag1 + (2 * wave + t) * kLanes + lane];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) b2[s] = F[kNetFrag2 + (wave * 16 + s) * kLanes + lane];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b3[s] = F[kNetFrag3 + ((wave >> 1) * 8 + s) * kLanes + lane];
+    const float bias1[2] = {bias[kNetBias1 + 16 * (2 * wave) + (lane & 15)],
+                            bias[kNetBias1 + 16 * (2 * wave + 1) + (lane & 15)]};
+    const float bias2 = bias[kNetBias2 + 16 * wave + (lane & 15)];
+    const float bias3 = bias[kNetBias3 + 16 * (wave >> 1) + (lane & 15)];
+
+    // encoding of row `lane` (wave 0): [sin q, cos q, 0, 0]
+    const int pl = lane / H;
+    const int h = lane - pl * H;
+    const int i = tile * P.ppt + pl;
+    const bool valid = pl < P.ppt && i < N;
+    if (wave == 0) {
+        float x[kIn];
+#pragma unroll
+        for (int j = 0; j < kDof; ++j) {
+            const float q = valid ? P.qbuf[((size_t)j * N + i) * H + h] : 0.0f;
+            sincosf(q, &x[j], &x[kDof + j]);
+        }
+        x[14] = 0.0f;
+        x[15] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) s_x[lane * kX + k] = (_Float16)x[k];
+    }
+    __syncthreads();
+
+    // layer 1: 64 x 16 by 16 x 256; wave w: columns 32 w .. 32 w + 31
+    {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const half4_t a = load_a(s_x, kX, m, 0, lane);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+                d = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b1[t], d, 0, 0, 0);
+                store_relu_h(s_a1, kA1, m, 2 * wave + t, lane, d, bias1[t]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // layer 2: 64 x 256 by 256 x 128; wave w: columns 16 w .. 16 w + 15
+    {
+        float4_t d[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                d[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(load_a(s_a1, kA1, m, s, lane), b2[s], d[m], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_relu_h(s_a2, kA2, m, wave, lane, d[m], bias2);
+    }
+    __syncthreads();
+
+    // layer 3: 64 x 128 by 128 x 64; wave w: columns 16 (w / 2) .., rows 32 (w % 2) ..
+    {
+        const int n = wave >> 1;
+        float4_t d[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) d[r] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                d[r] = __builtin_amdgcn_mfma_f32_16x16x16f16(load_a(s_a2, kA2, 2 * (wave & 1) + r, s, lane), b3[s],
+                                                             d[r], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int m = 2 * (wave & 1) + r;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                s_a3[(16 * m + 4 * (lane >> 4) + j) * kA3 + 16 * n + (lane & 15)] = fmaxf(d[r][j] + bias3, 0.0f);
+        }
+    }
+    __syncthreads();
+
+    // output layer, cost term and horizon cost (wave 0, lane = row)
+    if (wave == 0) {
+        float dist = bias[kNetBias4];
+        const float *a3 = s_a3 + lane * kA3;
+#pragma unroll
+        for (int k = 0; k < kNetH3; k += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(a3 + k);
+            dist = fmaf(bias[kNetW4 + k], v.x, dist);
+            dist = fmaf(bias[kNetW4 + k + 1], v.y, dist);
+            dist = fmaf(bias[kNetW4 + k + 2], v.z, dist);
+            dist = fmaf(bias[kNetW4 + k + 3], v.w, dist);
+        }
+        const float term = fmaxf(dist, 0.0f);  // Eq. 13
+        const float dc = P.a_coll * term;
+        const float added = segmented_scan(P.tables[kTabHw + h] * dc, h, H);
+        if (valid) {
+            if (out.terms) out.terms[((size_t)6 * N + i) * H + h] = term;
+            if (out.c) out.c[(size_t)i * H + h] += dc;
+            if (h == H - 1) {
+                const float C = P.C[i] + added;
+                P.C[i] = C;
+                if (out.C) out.C[i] = C;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_selfnet(const ProblemDev &P, const _Float16 *frag, const float *bias, const StepOut &out,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL(selfnet_kernel, dim3((unsigned)P.n_tiles), dim3(kNetThreads), 0, stream, P, frag, bias, out);
+    return hipGetLastError();
+}
+
+// Pack the network's parameters (weights [out][in], FP32) into the per-lane
+// FP16 fragments the kernel loads, and the biases and output weights (FP32).
+void pack_selfnet(const float *prm, std::vector<_Float16> &frag, std::vector<float> &bias)
+{
+    const float *W1 = prm, *b1 = W1 + kNetH1 * kNetIn;
+    const float *W2 = b1 + kNetH1, *b2 = W2 + kNetH2 * kNetH1;
+    const float *W3 = b2 + kNetH2, *b3 = W3 + kNetH3 * kNetH2;
+    const float *w4 = b3 + kNetH3, *b4 = w4 + kNetH3;
+    frag.assign((size_t)kNetFragHalves, (_Float16)0.0f);
+    // fragment (column block t, k-step s) of B = W^T: lane l, element j is
+    // W[16 t + l % 16][16 s + 4 (l / 16) + j]
+    auto put = [&](int base, const float *W, int n_in, int n_tiles, int n_steps) {
+        for (int t = 0; t < n_tiles; ++t)
+            for (int s = 0; s < n_steps; ++s)
+                for (int l = 0; l < kLanes; ++l)
+                    for (int j = 0; j < 4; ++j) {
+                        const int o = 16 * t + (l & 15), k = 16 * s + 4 * (l >> 4) + j;
+                        frag[((size_t)base + ((size_t)t * n_steps + s) * kLanes + l) * 4 + j] =
+                            (_Float16)(k < n_in ? W[o * n_in + k] : 0.0f);
+                    }
+    };
+    put(kNetFrag1, W1, kNetIn, kNetH1 / 16, 1);
+    put(kNetFrag2, W2, kNetH1, kNetH2 / 16, kNetH1 / 16);
+    put(kNetFrag3, W3, kNetH2, kNetH3 / 16, kNetH2 / 16);
+    bias.assign((size_t)kNetBiasSize, 0.0f);
+    for (int k = 0; k < kNetH1; ++k) bias[kNetBias1 + k] = b1[k];
+    for (int k = 0; k < kNetH2; ++k) bias[kNetBias2 + k] = b2[k];
+    for (int k = 0; k < kNetH3; ++k) bias[kNetBias3 + k] = b3[k];
+    for (int k = 0; k < kNetH3; ++k) bias[kNetW4 + k] = w4[k];
+    bias[kNetBias4] = b4[0];
+}
+
+}  // namespace storm

@@ -33,6 +33,20 @@ constexpr int kTabComb = 224;        // comb filter response g_k (e'_h = sum_k g
 constexpr int kTabSig0 = 288;        // sigma_init^2 [7], appended by a per-step covariance shift
 constexpr int kTabSize = 296;
 
+// Learned self-collision network (Eq. 13): layer widths, the packed FP16
+// weight fragments (offsets in units of 4 halves: per column block, k-step
+// and lane) and the FP32 block of biases and output weights.
+constexpr int kNetIn = 14, kNetH1 = 256, kNetH2 = 128, kNetH3 = 64;
+constexpr int kNetFrag1 = 0;                                  // 16 column blocks x 1 k-step
+constexpr int kNetFrag2 = kNetFrag1 + (kNetH1 / 16) * 1 * 64;  // 8 x 16
+constexpr int kNetFrag3 = kNetFrag2 + (kNetH2 / 16) * 16 * 64;  // 4 x 8
+constexpr int kNetFragHalves = (kNetFrag3 + (kNetH3 / 16) * 8 * 64) * 4;
+constexpr int kNetBias1 = 0, kNetBias2 = 256, kNetBias3 = 384, kNetW4 = 448, kNetBias4 = 512;
+constexpr int kNetBiasSize = 516;
+static_assert(kNetH1 * kNetIn + kNetH1 + kNetH2 * kNetH1 + kNetH2 + kNetH3 * kNetH2 + 2 * kNetH3 + 1 ==
+                  STORM_SELF_MLP_SIZE,
+              "network parameter count");
+
 
 // Per-problem description read by the kernels.  All pointers are device memory.
 struct ProblemDev {
@@ -63,6 +77,8 @@ struct ProblemDev {
     float *grad;            // [H][7] gradient of the expected horizon cost
     float *adam_m, *adam_v; // [H][7] Adam moments of the refinement
     float *ball;            // [8]: ball position, velocity (world frame) at the current state, pad
+    float *qbuf;            // [7][N][H] joint positions of the last step (learned self-collision model)
+    uint32_t selfnet;       // the self-collision term comes from the learned network
 };
 
 // Robot constants, passed by value (kernel-argument segment, wave-uniform).
@@ -121,6 +137,12 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
 hipError_t set_rollout_lds_limit();
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream);
+// Learned self-collision term: after the rollout, adds a_coll max(0, d) to
+// every running cost and its horizon sum to C (frag and bias packed by
+// pack_selfnet from the parameter layout of storm_robot.self_mlp).
+hipError_t launch_selfnet(const ProblemDev &P, const _Float16 *frag, const float *bias, const StepOut &out,
+                          hipStream_t stream);
+void pack_selfnet(const float *prm, std::vector<_Float16> &frag, std::vector<float> &bias);
 // Many problems: persistent rollout over a (problem, tile) work queue, and one
 // update workgroup per problem (descriptors in device memory).
 hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int n_items, uint32_t *next,
@@ -168,6 +190,8 @@ struct storm_ctx_s {
     storm_params params{};
     storm::ProblemDev P{};
     storm::RobotDev R{};
+    _Float16 *net_frag = nullptr;  // learned self-collision weights (packed), when self_model = 1
+    float *net_bias = nullptr;
     std::vector<void *> allocs;  // every device allocation of this context
 };
 

@@ -56,6 +56,7 @@ class storm_params(ctypes.Structure):
         ("a_manip", ctypes.c_float), ("a_coll", ctypes.c_float), ("grad_mask", ctypes.c_uint32),
         ("comb_filter", ctypes.c_int32), ("comb", ctypes.c_float * 3), ("cov_per_step", ctypes.c_int32),
         ("w_ball", ctypes.c_float), ("ball_gravity", ctypes.c_float * 3), ("ball_center", ctypes.c_float * 2),
+        ("self_model", ctypes.c_int32),
     ]
 
 
@@ -64,6 +65,7 @@ class storm_robot(ctypes.Structure):
         ("dh", (ctypes.c_float * 3) * 8),
         ("q_min", ctypes.c_float * 7), ("q_max", ctypes.c_float * 7), ("qd_max", ctypes.c_float * 7),
         ("n_spheres", ctypes.c_int32), ("spheres", ctypes.POINTER(ctypes.c_float)),
+        ("self_mlp", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -172,6 +174,7 @@ def make_params(p: "inputs.Params"):
     sp.comb_filter = int(getattr(p, "comb_filter", 0))
     sp.cov_per_step = int(getattr(p, "cov_per_step", 0))
     sp.w_ball = float(getattr(p, "w_ball", 0.0))
+    sp.self_model = int(getattr(p, "self_model", 0))
     for c, g in enumerate(getattr(p, "ball_gravity", (0.0, 0.0, -9.81))):
         sp.ball_gravity[c] = float(g)
     for c, x in enumerate(getattr(p, "ball_center", (0.0, 0.0))):
@@ -192,7 +195,9 @@ def make_params(p: "inputs.Params"):
     return sp, dt
 
 
-def make_robot(spheres=None, dh=None, q_min=None, q_max=None, qd_max=None):
+def make_robot(spheres=None, dh=None, q_min=None, q_max=None, qd_max=None, self_mlp=None):
+    """storm_robot for the Panda (or the given DH and limits); self_mlp: the
+    learned self-collision network's parameters [STORM_SELF_MLP_SIZE]."""
     r = storm_robot()
     dh = inputs.PANDA_DH if dh is None else dh
     for k in range(8):
@@ -206,6 +211,10 @@ def make_robot(spheres=None, dh=None, q_min=None, q_max=None, qd_max=None):
     sph = np.ascontiguousarray(np.zeros((0, 5)) if spheres is None else spheres, dtype=np.float32)
     r.n_spheres = sph.shape[0]
     r.spheres = sph.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if sph.size else None
+    if self_mlp is not None:
+        mlp = np.ascontiguousarray(self_mlp, dtype=np.float32)
+        r.self_mlp = mlp.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        r._self_mlp = mlp  # kept alive with the struct
     return r, sph
 
 
@@ -226,7 +235,7 @@ class Rollout:
         p = problem.params
         self.N, self.H = p.n_particles, p.horizon
         sp, self._dt = make_params(p)
-        rb, self._sph = make_robot(problem.spheres)
+        rb, self._sph = make_robot(problem.spheres, self_mlp=getattr(problem, "self_mlp", None))
         sc, self._obs = make_scene(problem.obstacles)
         self._robot = rb
         handle = ctypes.c_void_p()

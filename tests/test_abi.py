@@ -80,7 +80,7 @@ def test_init_validation(storm):
         ("comb_filter", 2, E.STORM_E_PARAM), ("comb_filter", -1, E.STORM_E_PARAM),
         ("cov_per_step", 2, E.STORM_E_PARAM), ("cov_per_step", -1, E.STORM_E_PARAM),
         ("w_ball", -1.0, E.STORM_E_PARAM), ("w_ball", float("inf"), E.STORM_E_PARAM),
-        ("grad_mask", 0x80, E.STORM_E_PARAM),
+        ("grad_mask", 0x80, E.STORM_E_PARAM), ("self_model", 2, E.STORM_E_PARAM),
     ]
     for field, val, want in cases:
         sp2, rb2, sc2, keep2 = _args(storm)
@@ -103,6 +103,24 @@ def test_init_validation(storm):
         sp2, rb2, sc2, keep2 = _args(storm)
         getattr(sp2, field)[k] = float("nan")
         assert _init(storm, sp2, rb2, sc2) == E.STORM_E_PARAM, field
+
+
+def test_self_network_validation(storm):
+    """The learned self-collision model needs its parameters, all finite."""
+    E = storm
+    prob = inputs.config_self_mlp(0, n_particles=32, horizon=10)
+    sp, rb, sc, keep = _args(storm, prob)
+    assert sp.self_model == 1
+    assert _init(storm, sp, rb, sc) == E.STORM_E_NULL  # robot without self_mlp
+    bad = prob.self_mlp.copy()
+    bad[1000] = float("nan")
+    rb2, k2 = storm.make_robot(prob.spheres, self_mlp=bad)
+    assert _init(storm, sp, rb2, sc) == E.STORM_E_PARAM
+    params = (storm.storm_params * 1)(sp)
+    rb3, k3 = storm.make_robot(prob.spheres, self_mlp=prob.self_mlp)
+    b = ctypes.c_void_p()
+    assert storm.lib().storm_batch_init(ctypes.byref(b), 1, params, ctypes.byref(rb3), ctypes.byref(sc), None) \
+        == E.STORM_E_UNSUPPORTED
 
 
 def test_batch_rejects_the_ball_term(storm):

@@ -538,3 +538,130 @@ def test_ball_state_is_read_at_every_step():
     finally:
         r.close()
         rg.close()
+
+
+def _net_parts(prm):
+    parts, k = {}, 0
+    for name, shape in inputs.SELF_MLP_LAYOUT:
+        n = int(np.prod(shape))
+        parts[name] = prm[k:k + n].reshape(shape)
+        k += n
+    return parts
+
+
+def _net_forward_abs_bound(prm, q, fp16=False):
+    """Rows q [R][7]: the network's output d in FP64 (with fp16=True, the
+    encoding and the first two hidden layers' outputs rounded to FP16 as the
+    kernel stores them), and a first-order bound on the error of the kernel's
+    evaluation: unit roundoff u = 2^-11 on those roundings (the weights are
+    FP16-exact), about K 2^-24 relative per FP32 sum of K terms; ReLU is
+    1-Lipschitz, so an error e in a layer's input moves its output by at most
+    |W| e."""
+    P = _net_parts(prm)
+    r16 = (lambda a: a.astype(np.float16).astype(np.float64)) if fp16 else (lambda a: a)
+    u, acc = 2.0 ** -11, 2.0 ** -24
+    x = r16(np.concatenate([np.sin(q), np.cos(q)], axis=1))
+    a1 = r16(np.maximum(x @ P["W1"].T + P["b1"], 0.0))
+    a2 = r16(np.maximum(a1 @ P["W2"].T + P["b2"], 0.0))
+    a3 = np.maximum(a2 @ P["W3"].T + P["b3"], 0.0)
+    d = a3 @ P["w4"] + P["b4"][0]
+    A1, A2, A3 = np.abs(P["W1"]), np.abs(P["W2"]), np.abs(P["W3"])
+    e1 = (u * np.abs(x) + 1e-6) @ A1.T + u * a1 + 16 * acc * (np.abs(x) @ A1.T)
+    e2 = e1 @ A2.T + u * a2 + 256 * acc * (a1 @ A2.T)
+    e3 = e2 @ A3.T + 128 * acc * (a2 @ A3.T)
+    ed = e3 @ np.abs(P["w4"]) + 64 * acc * (a3 @ np.abs(P["w4"]))
+    return d, ed
+
+
+def _flip_bound(prm, q):
+    """Per row, the largest change of d when one FP16-rounded value (an
+    encoding entry or a hidden output of the first two layers) lands one unit
+    in the last place (at most 2^-10 |value|) away: that unit's derivative of
+    d, through the ReLUs active at the row, times the change."""
+    P = _net_parts(prm)
+    x = np.concatenate([np.sin(q), np.cos(q)], axis=1)
+    z1 = x @ P["W1"].T + P["b1"]
+    a1 = np.maximum(z1, 0.0)
+    z2 = a1 @ P["W2"].T + P["b2"]
+    a2 = np.maximum(z2, 0.0)
+    z3 = a2 @ P["W3"].T + P["b3"]
+    g2 = (P["w4"] * (z3 > 0)) @ P["W3"]  # dd/da2
+    g1 = (g2 * (z2 > 0)) @ P["W2"]  # dd/da1
+    g0 = (g1 * (z1 > 0)) @ P["W1"]  # dd/dx
+    ulp = 2.0 ** -10
+    return ulp * np.maximum(np.maximum(np.max(np.abs(x * g0), axis=1), np.max(np.abs(a1 * g1), axis=1)),
+                            np.max(np.abs(a2 * g2), axis=1))
+
+
+@pytest.mark.parametrize("seed,N", [(0, 64), (1, 500)])
+def test_self_collision_network(oracle_lib, seed, N):
+    """The learned self-collision model (Eq. 13, jointNERF form) on the
+    matrix cores against the oracle's FP64 network: max(0, d) at the
+    kernel's own states within the FP16 error bound of each row, the other
+    terms and the horizon cost unchanged around it."""
+    prob = inputs.config_self_mlp(seed, n_particles=N, horizon=30)
+    o0 = oracle_lib.Oracle(prob)
+    q0s = o0.rollout(np.zeros((30, 7)), np.asarray(prob.params.sigma_init), o0.noise(0))["q"].reshape(-1, 7)
+    d0, _ = _net_forward_abs_bound(prob.self_mlp, q0s)
+    prob.self_mlp[-1] = float(np.float32(prob.self_mlp[-1] - np.median(d0)))  # both signs occur
+    p = prob.params
+    g, ro, up, o, eps = run_pair(prob, oracle_lib)
+    assert_states(g, ro)
+    live = np.arange(p.n_particles)
+    q = g["q"].reshape(-1, 7)
+    d_ref, bound = _net_forward_abs_bound(prob.self_mlp, q)
+    # the FP64 network of the oracle agrees with the numpy forward pass
+    for r in range(0, q.shape[0], 97):
+        assert oracle_lib.self_mlp(prob.self_mlp, q[r]) == pytest.approx(d_ref[r], rel=1e-12, abs=1e-12)
+    term = g["terms"][..., 6].reshape(-1)
+    ref = np.maximum(d_ref, 0.0)
+    assert (d_ref > 0).mean() > 0.2 and (d_ref < 0).mean() > 0.2
+    # against the exact network: within the first-order rounding bound
+    excess = np.abs(term - ref) - (2.0 * bound + 1e-6)
+    assert np.max(excess) <= 0.0, "worst row exceeds its bound by %.3g" % np.max(excess)
+    # against the same roundings taken in FP64: only the FP32 sums differ,
+    # which can move a rounded value by one unit in the last place; allow
+    # four such moves in a row
+    d16, _ = _net_forward_abs_bound(prob.self_mlp, q, fp16=True)
+    tol16 = 4.0 * _flip_bound(prob.self_mlp, q) + 1e-5
+    err16 = np.abs(term - np.maximum(d16, 0.0))
+    assert np.all(err16 <= tol16), (np.max(err16 - tol16), np.max(tol16))
+    # and closer to it than to the exact network, on average
+    assert np.mean(err16) < np.mean(np.abs(ref - np.maximum(d16, 0.0)))
+    # everything else in the running cost is the oracle's
+    other_g = g["c"] - p.a_coll * g["terms"][..., 6]
+    other_o = ro["c"] - p.a_coll * ro["terms"][..., 6]
+    m = manip_values(o, ro["q"])
+    near = np.abs(m - p.k_m) < 1e-4
+    err = np.abs(other_g - other_o) / np.maximum(np.abs(ro["c"]), COST_FLOOR)
+    assert np.max(np.where(near, 0.0, err)) <= TOL_COST_REL
+    # the horizon cost is the weighted sum of the running costs it reports
+    hw = np.ones(p.horizon)
+    np.testing.assert_allclose(g["C"], (g["c"] * hw).sum(axis=1), rtol=2e-5, atol=1e-3)
+    assert live.size == g["C"].shape[0]
+
+
+def test_self_collision_network_in_a_graph():
+    """A captured control step with the network pass equals the eager step
+    (same commands over three steps)."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config_self_mlp(2, n_particles=200)
+    r = storm.Rollout(prob)
+    rg = storm.Rollout(prob)
+    try:
+        goal = torch.tensor([1, 0, 0, 0, -1, 0, 0, 0, -1, 0.4, 0.1, 0.45], dtype=torch.float32, device="cuda")
+        x0 = r.x0.clone()
+        cmd_g = torch.empty(7, device="cuda")
+        cmd_e = torch.empty(7, device="cuda")
+        graph = rg.graph(x0, goal, cmd_g, iterations=1, shift=True)
+        for _ in range(3):
+            graph.launch()
+            r.step(goal, x0=x0)
+            r.update(shift=True, want_mean=False, cmd=cmd_e)
+            torch.cuda.synchronize()
+            assert torch.equal(cmd_g, cmd_e)
+        graph.close()
+    finally:
+        r.close()
+        rg.close()
