@@ -63,36 +63,43 @@ __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, cons
     const int tile = blockIdx.x;
     const int N = P.N, H = P.H;
 
-    // every weight fragment this wave uses, loaded up front (88 VGPRs)
-    const half4_t *F = reinterpret_cast<const half4_t *>(frag);
-    half4_t b1[2], b2[16], b3[8];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) b1[t] = F[kNetFrag1 + (2 * wave + t) * kLanes + lane];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) b2[s] = F[kNetFrag2 + (wave * 16 + s) * kLanes + lane];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) b3[s] = F[kNetFrag3 + ((wave >> 1) * 8 + s) * kLanes + lane];
-    const float bias1[2] = {bias[kNetBias1 + 16 * (2 * wave) + (lane & 15)],
-                            bias[kNetBias1 + 16 * (2 * wave + 1) + (lane & 15)]};
-    const float bias2 = bias[kNetBias2 + 16 * wave + (lane & 15)];
-    const float bias3 = bias[kNetBias3 + 16 * (wave >> 1) + (lane & 15)];
-
-    // encoding of row `lane` (wave 0): [sin q, cos q, 0, 0]
+    // row `lane` of the tile; wave j < 7 encodes joint j of every row.  Its
+    // position is loaded first, so that waiting for it does not wait for the
+    // weight loads behind it (an invalid row reads particle 0 and is ignored).
     const int pl = lane / H;
     const int h = lane - pl * H;
     const int i = tile * P.ppt + pl;
     const bool valid = pl < P.ppt && i < N;
-    if (wave == 0) {
-        float x[kIn];
+    const int jq = wave < kDof ? wave : 0;
+    const float qv = P.qbuf[((size_t)jq * N + (valid ? i : 0)) * H + h];
+    __builtin_amdgcn_sched_barrier(0);  // keep that load ahead of the weight loads
+
+    // every weight fragment this wave uses, loaded up front (88 VGPRs)
+    const half4_t *F = reinterpret_cast<const half4_t *>(frag);
+    // (in the order of use, each layer's biases with its fragments)
+    half4_t b1[2], b2[16], b3[8];
 #pragma unroll
-        for (int j = 0; j < kDof; ++j) {
-            const float q = valid ? P.qbuf[((size_t)j * N + i) * H + h] : 0.0f;
-            sincosf(q, &x[j], &x[kDof + j]);
-        }
-        x[14] = 0.0f;
-        x[15] = 0.0f;
+    for (int t = 0; t < 2; ++t) b1[t] = F[kNetFrag1 + (2 * wave + t) * kLanes + lane];
+    const float bias1[2] = {bias[kNetBias1 + 16 * (2 * wave) + (lane & 15)],
+                            bias[kNetBias1 + 16 * (2 * wave + 1) + (lane & 15)]};
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) s_x[lane * kX + k] = (_Float16)x[k];
+    for (int s = 0; s < 16; ++s) b2[s] = F[kNetFrag2 + (wave * 16 + s) * kLanes + lane];
+    const float bias2 = bias[kNetBias2 + 16 * wave + (lane & 15)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b3[s] = F[kNetFrag3 + ((wave >> 1) * 8 + s) * kLanes + lane];
+    const float bias3 = bias[kNetBias3 + 16 * (wave >> 1) + (lane & 15)];
+
+    // encoding [sin q, cos q, 0, 0] of the 64 rows
+    if (wave < kDof) {
+        float sn, cs;
+        sincosf(valid ? qv : 0.0f, &sn, &cs);
+        s_x[lane * kX + wave] = (_Float16)sn;
+        s_x[lane * kX + kDof + wave] = (_Float16)cs;
+    } else if (wave == kDof) {
+        s_x[lane * kX + 14] = (_Float16)0.0f;
+        s_x[lane * kX + 15] = (_Float16)0.0f;
     }
     __syncthreads();
 
