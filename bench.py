@@ -311,7 +311,7 @@ def selfnet_bench(seed, steps, warmup):
 
     out = {"workload": "N=500 (250 Halton + B-spline, 250 Gaussian), H=30, all cost terms, 30 sphere + 20 cuboid "
                        "obstacles; self-collision by the network [sin q, cos q] -> 256 -> 128 -> 64 -> 1 (ReLU), "
-                       "FP16 operands, FP32 accumulation; random parameters of that shape",
+                       "FP16 operands, FP32 accumulation; parameters fitted to the sphere model's signed link distance",
            "network_flops_per_step": 2 * (14 * 256 + 256 * 128 + 128 * 64 + 64) * 500 * 30}
     out.update(_variant_step(inputs.config_self_mlp(seed), steps, warmup))
     out["sphere_pairs"] = _variant_step(inputs.config2(seed), steps, warmup)

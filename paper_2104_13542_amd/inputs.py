@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -311,12 +312,22 @@ def random_self_mlp(seed: int = 0) -> np.ndarray:
     return np.concatenate(out).astype(np.float16).astype(np.float64)
 
 
-def config_self_mlp(seed: int = 0, n_particles: int = 500, horizon: int = 30) -> Problem:
+# Parameters of the network fitted to the Panda sphere model's signed link
+# distance (written by oracle/train_self_mlp.py; FP16-exact values).
+PANDA_SELF_MLP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "self_mlp_panda.npy")
+
+
+def panda_self_mlp() -> np.ndarray:
+    return np.load(PANDA_SELF_MLP).astype(np.float64)
+
+
+def config_self_mlp(seed: int = 0, n_particles: int = 500, horizon: int = 30, trained: bool = True) -> Problem:
     """The STORM-shaped step with the learned self-collision network in place
-    of the sphere pairs (random parameters of the published shape)."""
+    of the sphere pairs: the network fitted to the sphere model (trained), or
+    seeded random parameters of the same shape."""
     prob = config2(seed, n_particles=n_particles, horizon=horizon)
     prob.params.self_model = 1
-    prob.self_mlp = random_self_mlp(seed)
+    prob.self_mlp = panda_self_mlp() if trained else random_self_mlp(seed)
     return prob
 
 

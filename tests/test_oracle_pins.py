@@ -956,3 +956,21 @@ def test_self_model_selects_the_network(oracle_lib):
     for i in range(3):
         T = oracle_lib.fk(o.dh, r["q"][i, 0])
         assert o.cost_self(T) == pytest.approx(max(0.0, o.self_distance(r["q"][i, 0])), abs=1e-15)
+
+
+def test_trained_self_network_tracks_the_sphere_model(oracle_lib):
+    """The shipped network parameters (fitted by oracle/train_self_mlp.py to
+    the sphere model's signed link distance) predict it on configurations
+    the fit did not see: the sign (collision or not) almost always, the
+    distance within millimetres on average; every parameter is FP16-exact."""
+    prm = inputs.panda_self_mlp()
+    assert prm.shape == (inputs.SELF_MLP_SIZE,)
+    np.testing.assert_array_equal(prm.astype(np.float16).astype(np.float64), prm)
+    o = oracle_lib.Oracle(inputs.config_self_mlp(0, n_particles=8, horizon=4))
+    rng = np.random.default_rng(2024)
+    q = rng.uniform(inputs.PANDA_Q_MIN, inputs.PANDA_Q_MAX, size=(1500, 7))
+    d = np.array([o.self_distance(x) for x in q])
+    pred = np.array([oracle_lib.self_mlp(prm, x) for x in q])
+    assert (d > 0).mean() > 0.03  # some configurations collide
+    assert ((d > 0) == (pred > 0)).mean() >= 0.97
+    assert np.mean(np.abs(d - pred)) <= 0.005
