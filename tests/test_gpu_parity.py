@@ -593,15 +593,15 @@ def _flip_bound(prm, q):
                             np.max(np.abs(a2 * g2), axis=1))
 
 
-@pytest.mark.parametrize("seed,N", [(0, 64), (1, 500)])
-def test_self_collision_network(oracle_lib, seed, N):
+@pytest.mark.parametrize("seed,N,H", [(0, 64, 30), (1, 500, 30), (2, 1, 64), (3, 37, 7)])
+def test_self_collision_network(oracle_lib, seed, N, H):
     """The learned self-collision model (Eq. 13, jointNERF form) on the
     matrix cores against the oracle's FP64 network: max(0, d) at the
     kernel's own states within the FP16 error bound of each row, the other
     terms and the horizon cost unchanged around it."""
-    prob = inputs.config_self_mlp(seed, n_particles=N, horizon=30)
+    prob = inputs.config_self_mlp(seed, n_particles=N, horizon=H)
     o0 = oracle_lib.Oracle(prob)
-    q0s = o0.rollout(np.zeros((30, 7)), np.asarray(prob.params.sigma_init), o0.noise(0))["q"].reshape(-1, 7)
+    q0s = o0.rollout(np.zeros((H, 7)), np.asarray(prob.params.sigma_init), o0.noise(0))["q"].reshape(-1, 7)
     d0, _ = _net_forward_abs_bound(prob.self_mlp, q0s)
     prob.self_mlp[-1] = float(np.float32(prob.self_mlp[-1] - np.median(d0)))  # both signs occur
     p = prob.params
@@ -615,7 +615,7 @@ def test_self_collision_network(oracle_lib, seed, N):
         assert oracle_lib.self_mlp(prob.self_mlp, q[r]) == pytest.approx(d_ref[r], rel=1e-12, abs=1e-12)
     term = g["terms"][..., 6].reshape(-1)
     ref = np.maximum(d_ref, 0.0)
-    assert (d_ref > 0).mean() > 0.2 and (d_ref < 0).mean() > 0.2
+    assert (d_ref > 0).mean() > 0.1 and (d_ref < 0).mean() > 0.1
     # against the exact network: within the first-order rounding bound
     excess = np.abs(term - ref) - (2.0 * bound + 1e-6)
     assert np.max(excess) <= 0.0, "worst row exceeds its bound by %.3g" % np.max(excess)
