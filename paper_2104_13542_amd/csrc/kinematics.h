@@ -40,58 +40,96 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
 }
 
 // Flange velocity and acceleration (Eq. 8), xd = J qd and xdd = Jdot qd +
-// J qdd, by one outward pass over the joints instead of forming Jdot: w is
-// the angular velocity of the link that carries joint k's axis, so that
+// J qdd, by outward passes over the joints instead of forming Jdot: w is the
+// angular velocity of the link that carries joint k's axis, so that
 // zdot_k = w x z_k, and the origin o_k, fixed in that link, moves with
 // od_k = od_{k-1} + w x (o_k - o_{k-1}).  Column k of Jdot is then
-// [zdot_k x (p - o_k) + z_k x (pd - od_k); zdot_k].  Rows: linear, angular.
-__device__ __forceinline__ void task_space(const float z[kDof][3], const float o[kDof][3], const float pe[3],
-                                           const float qd[kDof], const float qdd[kDof], float xd[6], float xdd[6])
+// [zdot_k x (p - o_k) + z_k x (pd - od_k); zdot_k].  The first pass gives
+// the flange velocity pd; the second repeats the recursion and sums the
+// acceleration.  The frames are read from LDS as each pass needs them
+// (F = this lane's first frame entry, `stride` floats between entries: R
+// row-major then the origin, 12 entries per frame) in loops that are not
+// unrolled, which keeps the register footprint small.  Rows: linear, angular.
+__device__ __forceinline__ void task_space(const float *F, const int stride, const float qd[kDof],
+                                           const float qdd[kDof], float xd[6], float xdd[6])
 {
-    float w[3] = {0.0f, 0.0f, 0.0f}, od[3] = {0.0f, 0.0f, 0.0f};
-    float zd[kDof][3], odk[kDof][3];
+    auto axis = [&](int k, float zk[3]) {
+        zk[0] = F[(k * 12 + 2) * stride];
+        zk[1] = F[(k * 12 + 5) * stride];
+        zk[2] = F[(k * 12 + 8) * stride];
+    };
+    auto origin = [&](int k, float ok[3]) {
 #pragma unroll
+        for (int c = 0; c < 3; ++c) ok[c] = F[(k * 12 + 9 + c) * stride];
+    };
+    float pe[3];
+    origin(kFrames - 1, pe);
+    float w[3] = {0.0f, 0.0f, 0.0f}, od[3] = {0.0f, 0.0f, 0.0f}, prev[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll 1
     for (int k = 0; k < kDof; ++k) {
+        float zk[3], ok[3];
+        axis(k, zk);
+        origin(k, ok);
         if (k > 0) {
-            const float d[3] = {o[k][0] - o[k - 1][0], o[k][1] - o[k - 1][1], o[k][2] - o[k - 1][2]};
+            const float d[3] = {ok[0] - prev[0], ok[1] - prev[1], ok[2] - prev[2]};
             float t[3];
             cross3(w, d, t);
 #pragma unroll
             for (int c = 0; c < 3; ++c) od[c] += t[c];
         }
-        cross3(w, z[k], zd[k]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            odk[k][c] = od[c];
-            w[c] = fmaf(z[k][c], qd[k], w[c]);
+            w[c] = fmaf(zk[c], qd[k], w[c]);
+            prev[c] = ok[c];
         }
     }
     float pd[3];
     {
-        const float d[3] = {pe[0] - o[kDof - 1][0], pe[1] - o[kDof - 1][1], pe[2] - o[kDof - 1][2]};
+        const float d[3] = {pe[0] - prev[0], pe[1] - prev[1], pe[2] - prev[2]};
         cross3(w, d, pd);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pd[c] += od[c];
+        for (int c = 0; c < 3; ++c) {
+            pd[c] += od[c];
+            xd[c] = pd[c];
+            xd[3 + c] = w[c];
+        }
     }
     float lin[3] = {0.0f, 0.0f, 0.0f}, ang[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        w[c] = 0.0f;
+        od[c] = 0.0f;
+    }
+#pragma unroll 1
     for (int k = 0; k < kDof; ++k) {
-        const float r[3] = {pe[0] - o[k][0], pe[1] - o[k][1], pe[2] - o[k][2]};
-        const float dv[3] = {pd[0] - odk[k][0], pd[1] - odk[k][1], pd[2] - odk[k][2]};
+        float zk[3], ok[3];
+        axis(k, zk);
+        origin(k, ok);
+        if (k > 0) {
+            const float d[3] = {ok[0] - prev[0], ok[1] - prev[1], ok[2] - prev[2]};
+            float t[3];
+            cross3(w, d, t);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) od[c] += t[c];
+        }
+        float zd[3];
+        cross3(w, zk, zd);
+        const float r[3] = {pe[0] - ok[0], pe[1] - ok[1], pe[2] - ok[2]};
+        const float dv[3] = {pd[0] - od[0], pd[1] - od[1], pd[2] - od[2]};
         float t1[3], t2[3], jc[3];
-        cross3(zd[k], r, t1);
-        cross3(z[k], dv, t2);
-        cross3(z[k], r, jc);
+        cross3(zd, r, t1);
+        cross3(zk, dv, t2);
+        cross3(zk, r, jc);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             lin[c] = fmaf(t1[c] + t2[c], qd[k], fmaf(jc[c], qdd[k], lin[c]));
-            ang[c] = fmaf(zd[k][c], qd[k], fmaf(z[k][c], qdd[k], ang[c]));
+            ang[c] = fmaf(zd[c], qd[k], fmaf(zk[c], qdd[k], ang[c]));
+            w[c] = fmaf(zk[c], qd[k], w[c]);
+            prev[c] = ok[c];
         }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        xd[c] = pd[c];
-        xd[3 + c] = w[c];
         xdd[c] = lin[c];
         xdd[3 + c] = ang[c];
     }

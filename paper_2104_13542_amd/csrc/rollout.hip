@@ -25,8 +25,11 @@
 // counters, so they are fetched with scalar loads into SGPRs; every per-point
 // LDS array is [row][lane] (conflict-free).  Reductions run in a fixed order:
 // results are bitwise reproducible.
+#include <algorithm>
+
 #include "kinematics.h"
 #include "sampling.h"
+#include "selfnet.h"
 
 namespace storm {
 namespace {
@@ -122,6 +125,12 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     float *s_cn = s_sc + 14 * kLanes;       // [S][64]: |c|^2 of the sphere centres
     float *s_lim = s_cn + S * kLanes;       // [3][7][64]: squared joint, velocity, stop hinges per joint
     float *s_acc = s_lim + 3 * kDof * kLanes;  // [7][64]: joint accelerations (task-space form only)
+    // learned self-collision network inside the phases (task-space form,
+    // 16 waves): its first two hidden layers after the task rows, the last
+    // one over the frames, which are dead after phase C
+    _Float16 *s_n1 = reinterpret_cast<_Float16 *>(s_acc + kDof * kLanes);  // [64][kNetA1]
+    _Float16 *s_n2 = s_n1 + 64 * kNetA1;                                     // [64][kNetA2]
+    float *s_n3 = s_fr;                                                       // [64][kNetA3]
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -142,6 +151,20 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     const float dt_h = tab[kTabDt + h];
     const float vs_h = tab[kTabVstop + h];
     const float q0_j = x0[jw], v0_j = x0[kDof + jw];
+    // network: waves 8-15 take layer 1 in phase B and layer 3 in phase D,
+    // waves 0-7 layer 2 in phase C, wave 0 the output in phase E; layer 1's
+    // weight fragments are loaded now
+    const bool net = kTask && W == 16 && P.net_fused != 0u;
+    const half4_t *NF = reinterpret_cast<const half4_t *>(P.net_frag);
+    half4_t nb1[2];
+    float nbias1[2] = {0.0f, 0.0f};
+    if (net && wave >= 8) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            nb1[t] = NF[kNetFrag1 + (2 * (wave - 8) + t) * kLanes + lane];
+            nbias1[t] = P.net_bias[kNetBias1 + 16 * (2 * (wave - 8) + t) + (lane & 15)];
+        }
+    }
     // culling record of obstacle `lane` (first 64 obstacles) for phase D
     const float4 bound0 = (mask & STORM_COST_ENV) ? load_bound(P.obs_bound, lane, P.n_sph_obs + P.n_box_obs)
                                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -200,6 +223,33 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     __syncthreads();
 
     // ---- B: forward kinematics, one row of the frames per wave ----------------
+    half4_t nb2[16];
+    float nbias2 = 0.0f;
+    if (net && wave < 8) {  // layer 2's fragments, used in phase C
+#pragma unroll
+        for (int k = 0; k < 16; ++k) nb2[k] = NF[kNetFrag2 + (wave * 16 + k) * kLanes + lane];
+        nbias2 = P.net_bias[kNetBias2 + 16 * wave + (lane & 15)];
+    }
+    if (net && wave >= 8) {
+        // layer 1 from the sine and cosine rows of phase A1: feature f < 7 is
+        // sin q_f, 7 <= f < 14 is cos q_{f-7}, 14 and 15 are zero
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            half4_t a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int f = 4 * (lane >> 4) + j, row = 16 * m + (lane & 15);
+                a[j] = f < 2 * kDof ? (_Float16)s_sc[(2 * (f % kDof) + (f >= kDof ? 1 : 0)) * kLanes + row]
+                                    : (_Float16)0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+                d = __builtin_amdgcn_mfma_f32_16x16x16f16(a, nb1[t], d, 0, 0, 0);
+                net_store_relu_h(s_n1, kNetA1, m, 2 * (wave - 8) + t, lane, d, nbias1[t]);
+            }
+        }
+    }
     if (wave < 3) {
         const int row = wave;
         float r[3] = {row == 0 ? 1.0f : 0.0f, row == 1 ? 1.0f : 0.0f, row == 2 ? 1.0f : 0.0f};
@@ -310,7 +360,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                     qd[k] = s_v[k * kLanes + lane];
                     qdd[k] = s_acc[k * kLanes + lane];
                 }
-                task_space(z, o, pe, qd, qdd, xd, xdd);
+                task_space(s_fr + lane, kLanes, qd, qdd, xd, xdd);
                 if (valid)
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
@@ -321,6 +371,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             }
         }
     }
+    if (net && wave < 8) net_layer2(s_n1, s_n2, nb2, nbias2, wave, lane);
     __syncthreads();
 
     // ---- D: collision terms ---------------------------------------------------
@@ -329,6 +380,13 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // masks are OR-ed in SGPRs and the square roots (penetration depths) run
     // only when some lane of the wave touches one of them.
     float env = 0.0f, selfpen = 0.0f;
+    half4_t nb3[8];
+    float nbias3 = 0.0f;
+    if (net && wave >= 8) {  // layer 3's fragments, used after this wave's collision work
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nb3[k] = NF[kNetFrag3 + (((wave - 8) >> 1) * 8 + k) * kLanes + lane];
+        nbias3 = P.net_bias[kNetBias3 + 16 * ((wave - 8) >> 1) + (lane & 15)];
+    }
     if (mask & STORM_COST_ENV) {
         const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
         const STORM_CONST_AS float *box = uniform_ptr(P.box_obs);
@@ -482,6 +540,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             if (sp < s_end) round(sp, sp, tp, 0);
         }
     }
+    if (net && wave >= 8) net_layer3(s_n2, s_n3, nb3, nbias3, (wave - 8) >> 1, 2 * ((wave - 8) & 1), lane);
     s_penv[wave * kLanes + lane] = env;
     s_pself[wave * kLanes + lane] = selfpen;
 
@@ -507,6 +566,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             for (int w = 0; w < W; ++w) t[6] = fmaxf(t[6], s_pself[w * kLanes + lane]);
         if (mask & STORM_COST_ENV)
             for (int w = 0; w < W; ++w) t[7] += s_penv[w * kLanes + lane];
+        if (net) t[6] = fmaxf(net_output(s_n3, P.net_bias, lane), 0.0f);  // Eq. 13
         float c = P.w_pos * t[0];
         c = fmaf(P.w_rot, t[1], c);
         c = fmaf(P.a_joint, t[2], c);
@@ -593,11 +653,14 @@ __global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const Problem
     }
 }
 
-size_t rollout_lds_bytes(int S, int W, bool task = false)
+size_t rollout_lds_bytes(int S, int W, bool task = false, bool net = false)
 {
     return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof + 3 * kDof + (task ? kDof : 0)) * kLanes *
-           sizeof(float);
+               sizeof(float) +
+           (net ? kNetLdsBytes : 0);
 }
+
+constexpr int kMaxLds = 160 * 1024;
 
 }  // namespace
 
@@ -605,7 +668,7 @@ hipError_t set_rollout_lds_limit()
 {
     const int bytes16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16);
     const int bytes8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8);
-    const int task16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16, true);
+    const int task16 = (int)std::min(rollout_lds_bytes(STORM_MAX_SPHERES, 16, true, true), (size_t)kMaxLds);
     const int task8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8, true);
     const void *fns[6] = {reinterpret_cast<const void *>(&rollout_kernel<16, false>),
                           reinterpret_cast<const void *>(&rollout_kernel<8, false>),
@@ -619,6 +682,11 @@ hipError_t set_rollout_lds_limit()
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+bool selfnet_fits(int n_spheres, int waves)
+{
+    return waves == 16 && rollout_lds_bytes(n_spheres, 16, true, true) <= (size_t)kMaxLds;
 }
 
 hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int n_items, uint32_t *next,
@@ -644,7 +712,7 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
     // the task-space form only where it is asked for: the ball term, or the
     // flange velocity and acceleration outputs
     const bool task = (P.cost_mask & STORM_COST_BALL) || P.selfnet || out.xd != nullptr || out.xdd != nullptr;
-    const size_t lds = rollout_lds_bytes(R.n_spheres, waves, task);
+    const size_t lds = rollout_lds_bytes(R.n_spheres, waves, task, task && P.net_fused != 0u);
     const dim3 grid((unsigned)P.n_tiles);
     if (waves != 16 && waves != 8) return hipErrorInvalidValue;
     auto kernel = waves == 16 ? (task ? rollout_kernel<16, true> : rollout_kernel<16, false>)

@@ -1,0 +1,99 @@
+// Device helpers of the learned self-collision network (Sec. 3.2, Eq. 13,
+// the jointNERF form), shared by its stand-alone kernel and the rollout
+// kernel's fused form: MFMA operand types, the LDS row strides of the
+// activations and the fragment load / activation store of a 16 x 16 tile.
+#pragma once
+
+#include "storm_internal.h"
+
+namespace storm {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// LDS row strides (halves for FP16 rows, floats for the last hidden layer),
+// padded so that the 16 rows of an operand tile fall in different banks.
+constexpr int kNetA1 = kNetH1 + 8;
+constexpr int kNetA2 = kNetH2 + 8;
+constexpr int kNetA3 = kNetH3 + 4;
+// LDS bytes of the first two hidden layers' activations (64 rows).
+constexpr int kNetLdsBytes = 64 * (kNetA1 + kNetA2) * 2;
+
+// v_mfma_f32_16x16x16_f16 operands, lane l:
+//   A (16 x 16, rows x k):    A[l % 16][4 (l / 16) + j], j < 4
+//   B (16 x 16, k x columns): B[4 (l / 16) + j][l % 16]
+//   D (16 x 16):              D[4 (l / 16) + j][l % 16]
+__device__ __forceinline__ half4_t net_load_a(const _Float16 *s, int stride, int m, int ks, int lane)
+{
+    return *reinterpret_cast<const half4_t *>(s + (16 * m + (lane & 15)) * stride + 16 * ks + 4 * (lane >> 4));
+}
+
+// D tile (row block m, column block n) + bias, ReLU, stored as FP16 rows of
+// the next layer's input.
+__device__ __forceinline__ void net_store_relu_h(_Float16 *s, int stride, int m, int n, int lane, float4_t d,
+                                                 float bias)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        s[(16 * m + 4 * (lane >> 4) + j) * stride + 16 * n + (lane & 15)] = (_Float16)fmaxf(d[j] + bias, 0.0f);
+}
+
+// Same, FP32 rows (the last hidden layer, read by the output dot product).
+__device__ __forceinline__ void net_store_relu_f(float *s, int stride, int m, int n, int lane, float4_t d,
+                                                 float bias)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[(16 * m + 4 * (lane >> 4) + j) * stride + 16 * n + (lane & 15)] = fmaxf(d[j] + bias, 0.0f);
+}
+
+// Layer 2 column block n (16 units) for all 64 rows: 16 k-steps over the
+// 256 first-layer outputs in LDS.
+__device__ __forceinline__ void net_layer2(const _Float16 *s_a1, _Float16 *s_a2, const half4_t b2[16], float bias2,
+                                           int n, int lane)
+{
+    float4_t d[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) d[m] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            d[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(net_load_a(s_a1, kNetA1, m, s, lane), b2[s], d[m], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) net_store_relu_h(s_a2, kNetA2, m, n, lane, d[m], bias2);
+}
+
+// Layer 3 column block n, row blocks m0 and m0 + 1: 8 k-steps over the 128
+// second-layer outputs.
+__device__ __forceinline__ void net_layer3(const _Float16 *s_a2, float *s_a3, const half4_t b3[8], float bias3, int n,
+                                           int m0, int lane)
+{
+    float4_t d[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) d[r] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            d[r] = __builtin_amdgcn_mfma_f32_16x16x16f16(net_load_a(s_a2, kNetA2, m0 + r, s, lane), b3[s], d[r], 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) net_store_relu_f(s_a3, kNetA3, m0 + r, n, lane, d[r], bias3);
+}
+
+// Output layer for row `lane`: d = b4 + w4 . a3[lane].
+__device__ __forceinline__ float net_output(const float *s_a3, const float *__restrict__ bias, int lane)
+{
+    float dist = bias[kNetBias4];
+    const float *a3 = s_a3 + lane * kNetA3;
+#pragma unroll
+    for (int k = 0; k < kNetH3; k += 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(a3 + k);
+        dist = fmaf(bias[kNetW4 + k], v.x, dist);
+        dist = fmaf(bias[kNetW4 + k + 1], v.y, dist);
+        dist = fmaf(bias[kNetW4 + k + 2], v.z, dist);
+        dist = fmaf(bias[kNetW4 + k + 3], v.w, dist);
+    }
+    return dist;
+}
+
+}  // namespace storm

@@ -14,49 +14,25 @@
 // sphere model's) and, through a segmented scan over the steps, the horizon
 // cost C_i that the rollout kernel wrote.
 #include "sampling.h"
+#include "selfnet.h"
 #include "storm_internal.h"
 
 namespace storm {
 
 namespace {
 
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
 constexpr int kNetWaves = 8;
 constexpr int kNetThreads = kNetWaves * kLanes;
 constexpr int kIn = 16;  // 14 inputs padded to one k-step
-constexpr int kX = kIn;             // LDS row strides, in halves / floats
-constexpr int kA1 = kNetH1 + 8;
-constexpr int kA2 = kNetH2 + 8;
-constexpr int kA3 = kNetH3 + 4;
-
-// Row m of the tile: lanes hold 16-row by 16-column MFMA operands with
-//   A (16 x 16, rows x k):    lane l holds A[l % 16][4 (l / 16) + j], j < 4
-//   B (16 x 16, k x columns): lane l holds B[4 (l / 16) + j][l % 16]
-//   D (16 x 16):              lane l holds D[4 (l / 16) + j][l % 16]
-__device__ __forceinline__ half4_t load_a(const _Float16 *s, int stride, int m, int ks, int lane)
-{
-    return *reinterpret_cast<const half4_t *>(s + (16 * m + (lane & 15)) * stride + 16 * ks + 4 * (lane >> 4));
-}
-
-// D tile (m, column block n) + bias, ReLU, stored as FP16 rows of the next
-// layer's input.
-__device__ __forceinline__ void store_relu_h(_Float16 *s, int stride, int m, int n, int lane, float4_t d,
-                                             float bias)
-{
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        s[(16 * m + 4 * (lane >> 4) + j) * stride + 16 * n + (lane & 15)] = (_Float16)fmaxf(d[j] + bias, 0.0f);
-}
+constexpr int kX = kIn;  // LDS row stride of the encoding, in halves
 
 __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, const _Float16 *__restrict__ frag,
                                                               const float *__restrict__ bias, StepOut out)
 {
     __shared__ __attribute__((aligned(16))) _Float16 s_x[64 * kX];
-    __shared__ __attribute__((aligned(16))) _Float16 s_a1[64 * kA1];
-    __shared__ __attribute__((aligned(16))) _Float16 s_a2[64 * kA2];
-    __shared__ __attribute__((aligned(16))) float s_a3[64 * kA3];
+    __shared__ __attribute__((aligned(16))) _Float16 s_a1[64 * kNetA1];
+    __shared__ __attribute__((aligned(16))) _Float16 s_a2[64 * kNetA2];
+    __shared__ __attribute__((aligned(16))) float s_a3[64 * kNetA3];
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -107,66 +83,28 @@ __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, cons
     {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const half4_t a = load_a(s_x, kX, m, 0, lane);
+            const half4_t a = net_load_a(s_x, kX, m, 0, lane);
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
                 d = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b1[t], d, 0, 0, 0);
-                store_relu_h(s_a1, kA1, m, 2 * wave + t, lane, d, bias1[t]);
+                net_store_relu_h(s_a1, kNetA1, m, 2 * wave + t, lane, d, bias1[t]);
             }
         }
     }
     __syncthreads();
 
     // layer 2: 64 x 256 by 256 x 128; wave w: columns 16 w .. 16 w + 15
-    {
-        float4_t d[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) d[m] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                d[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(load_a(s_a1, kA1, m, s, lane), b2[s], d[m], 0, 0, 0);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) store_relu_h(s_a2, kA2, m, wave, lane, d[m], bias2);
-    }
+    net_layer2(s_a1, s_a2, b2, bias2, wave, lane);
     __syncthreads();
 
     // layer 3: 64 x 128 by 128 x 64; wave w: columns 16 (w / 2) .., rows 32 (w % 2) ..
-    {
-        const int n = wave >> 1;
-        float4_t d[2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) d[r] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-                d[r] = __builtin_amdgcn_mfma_f32_16x16x16f16(load_a(s_a2, kA2, 2 * (wave & 1) + r, s, lane), b3[s],
-                                                             d[r], 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int m = 2 * (wave & 1) + r;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                s_a3[(16 * m + 4 * (lane >> 4) + j) * kA3 + 16 * n + (lane & 15)] = fmaxf(d[r][j] + bias3, 0.0f);
-        }
-    }
+    net_layer3(s_a2, s_a3, b3, bias3, wave >> 1, 2 * (wave & 1), lane);
     __syncthreads();
 
     // output layer, cost term and horizon cost (wave 0, lane = row)
     if (wave == 0) {
-        float dist = bias[kNetBias4];
-        const float *a3 = s_a3 + lane * kA3;
-#pragma unroll
-        for (int k = 0; k < kNetH3; k += 4) {
-            const float4 v = *reinterpret_cast<const float4 *>(a3 + k);
-            dist = fmaf(bias[kNetW4 + k], v.x, dist);
-            dist = fmaf(bias[kNetW4 + k + 1], v.y, dist);
-            dist = fmaf(bias[kNetW4 + k + 2], v.z, dist);
-            dist = fmaf(bias[kNetW4 + k + 3], v.w, dist);
-        }
+        const float dist = net_output(s_a3, bias, lane);
         const float term = fmaxf(dist, 0.0f);  // Eq. 13
         const float dc = P.a_coll * term;
         const float added = segmented_scan(P.tables[kTabHw + h] * dc, h, H);

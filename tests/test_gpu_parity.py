@@ -593,13 +593,20 @@ def _flip_bound(prm, q):
                             np.max(np.abs(a2 * g2), axis=1))
 
 
-@pytest.mark.parametrize("seed,N,H", [(0, 64, 30), (1, 500, 30), (2, 1, 64), (3, 37, 7)])
-def test_self_collision_network(oracle_lib, seed, N, H):
+@pytest.mark.parametrize("seed,N,H,extra", [(0, 64, 30, 0), (1, 500, 30, 0), (2, 1, 64, 0), (3, 37, 7, 0),
+                                             (4, 150, 30, 12)])
+def test_self_collision_network(oracle_lib, seed, N, H, extra):
     """The learned self-collision model (Eq. 13, jointNERF form) on the
     matrix cores against the oracle's FP64 network: max(0, d) at the
     kernel's own states within the FP16 error bound of each row, the other
-    terms and the horizon cost unchanged around it."""
+    terms and the horizon cost unchanged around it.  With the Panda's 52
+    spheres the network runs inside the rollout kernel; with 64 (extra = 12
+    small flange spheres) its activations no longer fit beside the rollout's
+    in LDS and it runs as its own kernel after it."""
     prob = inputs.config_self_mlp(seed, n_particles=N, horizon=H)
+    if extra:
+        add = np.array([[8.0, 0.0, 0.0, 0.01 * k, 0.02] for k in range(extra)])
+        prob.spheres = np.concatenate([prob.spheres, add])
     o0 = oracle_lib.Oracle(prob)
     q0s = o0.rollout(np.zeros((H, 7)), np.asarray(prob.params.sigma_init), o0.noise(0))["q"].reshape(-1, 7)
     d0, _ = _net_forward_abs_bound(prob.self_mlp, q0s)
