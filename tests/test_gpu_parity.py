@@ -449,6 +449,7 @@ def test_task_space_velocity_and_acceleration(oracle_lib, cfg):
     (Jdot from its definition) at the kernel's own float32 states; the
     task-space form leaves the costs as the plain form computes them."""
     prob = inputs.config1(3, v0_random=True) if cfg == "config1" else inputs.config2(4, n_particles=100)
+    prob.params.n_null = 3  # null particles: qdd = 0, so xdd = Jdot qd
     p = prob.params
     g, ro, up, o, eps = run_pair(prob, oracle_lib, task_space=True)
     assert_states(g, ro)
@@ -466,14 +467,15 @@ def test_task_space_velocity_and_acceleration(oracle_lib, cfg):
     np.testing.assert_allclose(g2["q"], g["q"], rtol=0, atol=1e-6)
 
 
-@pytest.mark.parametrize("seed,N", [(0, 64), (1, 203)])
-def test_ball_on_tray(oracle_lib, seed, N):
+@pytest.mark.parametrize("seed,N,n_null", [(0, 64, 0), (1, 203, 0), (2, 97, 5)])
+def test_ball_on_tray(oracle_lib, seed, N, n_null):
     """The ball term (appendix on dynamic object balancing) against the
     oracle: the ball's in-plane trajectory under the rolled-out flange
     orientations, its distance from the tray centre, the running and
     horizon costs, and the update that follows."""
     prob = inputs.config_ball(seed, n_particles=N)
     prob.params.ball_center = (0.01, -0.015)
+    prob.params.n_null = n_null
     p = prob.params
     g, ro, up, o, eps = run_pair(prob, oracle_lib)
     assert_states(g, ro)
@@ -668,6 +670,39 @@ def test_self_collision_network_in_a_graph():
             r.update(shift=True, want_mean=False, cmd=cmd_e)
             torch.cuda.synchronize()
             assert torch.equal(cmd_g, cmd_e)
+        graph.close()
+    finally:
+        r.close()
+        rg.close()
+
+
+def test_per_step_covariance_graph_with_two_iterations():
+    """K = 2 iterations per control step with a per-step covariance: the
+    captured graph (two rollouts and updates, the shift after the second)
+    gives the eager sequence's commands and state, bit for bit."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(6, n_particles=150)
+    prob.params.cov_per_step = 1
+    r = storm.Rollout(prob)
+    rg = storm.Rollout(prob)
+    try:
+        goal = torch.tensor([1, 0, 0, 0, -1, 0, 0, 0, -1, 0.4, 0.1, 0.45], dtype=torch.float32, device="cuda")
+        x0 = r.x0.clone()
+        cmd_g = torch.empty(7, device="cuda")
+        cmd_e = torch.empty(7, device="cuda")
+        graph = rg.graph(x0, goal, cmd_g, iterations=2, shift=True)
+        for _ in range(3):
+            graph.launch()
+            for k in range(2):
+                r.step(goal, x0=x0)
+                r.update(shift=k == 1, want_mean=False, cmd=cmd_e)
+            torch.cuda.synchronize()
+            assert torch.equal(cmd_g, cmd_e)
+        me, se, ste = r.get_state()
+        mg, sg, stg = rg.get_state()
+        assert se.shape == (prob.params.horizon, 7)
+        assert np.array_equal(me, mg) and np.array_equal(se, sg) and ste == stg == 6
         graph.close()
     finally:
         r.close()
