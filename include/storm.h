@@ -201,8 +201,10 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
  * d_x0 [3][7] and d_goal [12] are read on the device.  d_noise (nullable)
  * replaces the sampled standard noise of every non-null particle.  d_C
  * (nullable) receives a copy of C [N].  dbg (nullable) selects extra
- * outputs.  A second step before the update replaces the first one's
- * controls and costs.  Errors: E_NULL, E_DEVICE. */
+ * outputs; asking for xd / xdd (or a problem with the ball term or the
+ * learned self-collision model) runs the task-space form of the rollout,
+ * which carries that extra work.  A second step before the update replaces
+ * the first one's controls and costs.  Errors: E_NULL, E_DEVICE. */
 int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_noise,
                            const storm_debug *dbg, float *d_C, void *stream);
 
