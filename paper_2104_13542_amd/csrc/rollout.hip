@@ -155,13 +155,15 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // waves 0-7 layer 2 in phase C, wave 0 the output in phase E; layer 1's
     // weight fragments are loaded now
     const bool net = kTask && W == 16 && P.net_fused != 0u;
-    const half4_t *NF = reinterpret_cast<const half4_t *>(P.net_frag);
+    const half4_t *NF1 = reinterpret_cast<const half4_t *>(P.net_frag + kNetFrag1);
+    const half8_t *NF2 = reinterpret_cast<const half8_t *>(P.net_frag + kNetFrag2);
+    const half8_t *NF3 = reinterpret_cast<const half8_t *>(P.net_frag + kNetFrag3);
     half4_t nb1[2];
     float nbias1[2] = {0.0f, 0.0f};
     if (net && wave >= 8) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            nb1[t] = NF[kNetFrag1 + (2 * (wave - 8) + t) * kLanes + lane];
+            nb1[t] = NF1[(2 * (wave - 8) + t) * kLanes + lane];
             nbias1[t] = P.net_bias[kNetBias1 + 16 * (2 * (wave - 8) + t) + (lane & 15)];
         }
     }
@@ -223,11 +225,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     __syncthreads();
 
     // ---- B: forward kinematics, one row of the frames per wave ----------------
-    half4_t nb2[16];
+    half8_t nb2[8];
     float nbias2 = 0.0f;
     if (net && wave < 8) {  // layer 2's fragments, used in phase C
 #pragma unroll
-        for (int k = 0; k < 16; ++k) nb2[k] = NF[kNetFrag2 + (wave * 16 + k) * kLanes + lane];
+        for (int k = 0; k < 8; ++k) nb2[k] = NF2[(wave * 8 + k) * kLanes + lane];
         nbias2 = P.net_bias[kNetBias2 + 16 * wave + (lane & 15)];
     }
     if (net && wave >= 8) {
@@ -380,11 +382,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // masks are OR-ed in SGPRs and the square roots (penetration depths) run
     // only when some lane of the wave touches one of them.
     float env = 0.0f, selfpen = 0.0f;
-    half4_t nb3[8];
+    half8_t nb3[4];
     float nbias3 = 0.0f;
     if (net && wave >= 8) {  // layer 3's fragments, used after this wave's collision work
 #pragma unroll
-        for (int k = 0; k < 8; ++k) nb3[k] = NF[kNetFrag3 + (((wave - 8) >> 1) * 8 + k) * kLanes + lane];
+        for (int k = 0; k < 4; ++k) nb3[k] = NF3[(((wave - 8) >> 1) * 4 + k) * kLanes + lane];
         nbias3 = P.net_bias[kNetBias3 + 16 * ((wave - 8) >> 1) + (lane & 15)];
     }
     if (mask & STORM_COST_ENV) {

@@ -9,6 +9,7 @@
 namespace storm {
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // LDS row strides (halves for FP16 rows, floats for the last hidden layer),
@@ -19,13 +20,22 @@ constexpr int kNetA3 = kNetH3 + 4;
 // LDS bytes of the first two hidden layers' activations (64 rows).
 constexpr int kNetLdsBytes = 64 * (kNetA1 + kNetA2) * 2;
 
-// v_mfma_f32_16x16x16_f16 operands, lane l:
-//   A (16 x 16, rows x k):    A[l % 16][4 (l / 16) + j], j < 4
-//   B (16 x 16, k x columns): B[4 (l / 16) + j][l % 16]
-//   D (16 x 16):              D[4 (l / 16) + j][l % 16]
+// MFMA operands, lane l (both layouts checked on the device):
+//   v_mfma_f32_16x16x16_f16 (layer 1, k = 16)
+//     A (16 x 16, rows x k):    A[l % 16][4 (l / 16) + j], j < 4
+//     B (16 x 16, k x columns): B[4 (l / 16) + j][l % 16]
+//   v_mfma_f32_16x16x32_f16 (layers 2 and 3, twice the k per instruction)
+//     A (16 x 32):              A[l % 16][8 (l / 16) + j], j < 8
+//     B (32 x 16):              B[8 (l / 16) + j][l % 16]
+//   D (16 x 16), both:          D[4 (l / 16) + j][l % 16]
 __device__ __forceinline__ half4_t net_load_a(const _Float16 *s, int stride, int m, int ks, int lane)
 {
     return *reinterpret_cast<const half4_t *>(s + (16 * m + (lane & 15)) * stride + 16 * ks + 4 * (lane >> 4));
+}
+
+__device__ __forceinline__ half8_t net_load_a8(const _Float16 *s, int stride, int m, int ks, int lane)
+{
+    return *reinterpret_cast<const half8_t *>(s + (16 * m + (lane & 15)) * stride + 32 * ks + 8 * (lane >> 4));
 }
 
 // D tile (row block m, column block n) + bias, ReLU, stored as FP16 rows of
@@ -46,36 +56,36 @@ __device__ __forceinline__ void net_store_relu_f(float *s, int stride, int m, in
     for (int j = 0; j < 4; ++j) s[(16 * m + 4 * (lane >> 4) + j) * stride + 16 * n + (lane & 15)] = fmaxf(d[j] + bias, 0.0f);
 }
 
-// Layer 2 column block n (16 units) for all 64 rows: 16 k-steps over the
-// 256 first-layer outputs in LDS.
-__device__ __forceinline__ void net_layer2(const _Float16 *s_a1, _Float16 *s_a2, const half4_t b2[16], float bias2,
+// Layer 2 column block n (16 units) for all 64 rows: 8 k-steps of 32 over
+// the 256 first-layer outputs in LDS.
+__device__ __forceinline__ void net_layer2(const _Float16 *s_a1, _Float16 *s_a2, const half8_t b2[8], float bias2,
                                            int n, int lane)
 {
     float4_t d[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) d[m] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            d[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(net_load_a(s_a1, kNetA1, m, s, lane), b2[s], d[m], 0, 0, 0);
+            d[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(net_load_a8(s_a1, kNetA1, m, s, lane), b2[s], d[m], 0, 0, 0);
 #pragma unroll
     for (int m = 0; m < 4; ++m) net_store_relu_h(s_a2, kNetA2, m, n, lane, d[m], bias2);
 }
 
-// Layer 3 column block n, row blocks m0 and m0 + 1: 8 k-steps over the 128
-// second-layer outputs.
-__device__ __forceinline__ void net_layer3(const _Float16 *s_a2, float *s_a3, const half4_t b3[8], float bias3, int n,
+// Layer 3 column block n, row blocks m0 and m0 + 1: 4 k-steps of 32 over
+// the 128 second-layer outputs.
+__device__ __forceinline__ void net_layer3(const _Float16 *s_a2, float *s_a3, const half8_t b3[4], float bias3, int n,
                                            int m0, int lane)
 {
     float4_t d[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) d[r] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int r = 0; r < 2; ++r)
-            d[r] = __builtin_amdgcn_mfma_f32_16x16x16f16(net_load_a(s_a2, kNetA2, m0 + r, s, lane), b3[s], d[r], 0, 0, 0);
+            d[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(net_load_a8(s_a2, kNetA2, m0 + r, s, lane), b3[s], d[r], 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 2; ++r) net_store_relu_f(s_a3, kNetA3, m0 + r, n, lane, d[r], bias3);
 }

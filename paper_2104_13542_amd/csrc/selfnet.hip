@@ -6,7 +6,8 @@
 //
 // One workgroup (8 waves) per 64-lane tile of the rollout (the same
 // (particle, step) rows): the three hidden layers are 64-row GEMMs on
-// v_mfma_f32_16x16x16_f16 (FP16 operands, FP32 accumulation), with the
+// v_mfma_f32_16x16x16_f16 (layer 1) and v_mfma_f32_16x16x32_f16 (FP16
+// operands, FP32 accumulation), with the
 // activations staged in LDS between layers and the weights read as
 // pre-packed per-lane fragments (one coalesced 512-byte load per wave and
 // fragment).  The output layer is a 64-term dot product per row on the
@@ -51,20 +52,23 @@ __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, cons
     __builtin_amdgcn_sched_barrier(0);  // keep that load ahead of the weight loads
 
     // every weight fragment this wave uses, loaded up front (88 VGPRs)
-    const half4_t *F = reinterpret_cast<const half4_t *>(frag);
     // (in the order of use, each layer's biases with its fragments)
-    half4_t b1[2], b2[16], b3[8];
+    const half4_t *F1 = reinterpret_cast<const half4_t *>(frag + kNetFrag1);
+    const half8_t *F2 = reinterpret_cast<const half8_t *>(frag + kNetFrag2);
+    const half8_t *F3 = reinterpret_cast<const half8_t *>(frag + kNetFrag3);
+    half4_t b1[2];
+    half8_t b2[8], b3[4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) b1[t] = F[kNetFrag1 + (2 * wave + t) * kLanes + lane];
+    for (int t = 0; t < 2; ++t) b1[t] = F1[(2 * wave + t) * kLanes + lane];
     const float bias1[2] = {bias[kNetBias1 + 16 * (2 * wave) + (lane & 15)],
                             bias[kNetBias1 + 16 * (2 * wave + 1) + (lane & 15)]};
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) b2[s] = F[kNetFrag2 + (wave * 16 + s) * kLanes + lane];
+    for (int s = 0; s < 8; ++s) b2[s] = F2[(wave * 8 + s) * kLanes + lane];
     const float bias2 = bias[kNetBias2 + 16 * wave + (lane & 15)];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b3[s] = F[kNetFrag3 + ((wave >> 1) * 8 + s) * kLanes + lane];
+    for (int s = 0; s < 4; ++s) b3[s] = F3[((wave >> 1) * 4 + s) * kLanes + lane];
     const float bias3 = bias[kNetBias3 + 16 * (wave >> 1) + (lane & 15)];
 
     // encoding [sin q, cos q, 0, 0] of the 64 rows
@@ -138,21 +142,22 @@ void pack_selfnet(const float *prm, std::vector<_Float16> &frag, std::vector<flo
     const float *W3 = b2 + kNetH2, *b3 = W3 + kNetH3 * kNetH2;
     const float *w4 = b3 + kNetH3, *b4 = w4 + kNetH3;
     frag.assign((size_t)kNetFragHalves, (_Float16)0.0f);
-    // fragment (column block t, k-step s) of B = W^T: lane l, element j is
-    // W[16 t + l % 16][16 s + 4 (l / 16) + j]
-    auto put = [&](int base, const float *W, int n_in, int n_tiles, int n_steps) {
+    // fragment (column block t, k-step s) of B = W^T with `per` halves per
+    // lane (k-steps of 4 per): lane l, element j is
+    // W[16 t + l % 16][4 per s + per (l / 16) + j]
+    auto put = [&](int base, const float *W, int n_in, int n_tiles, int n_steps, int per) {
         for (int t = 0; t < n_tiles; ++t)
             for (int s = 0; s < n_steps; ++s)
                 for (int l = 0; l < kLanes; ++l)
-                    for (int j = 0; j < 4; ++j) {
-                        const int o = 16 * t + (l & 15), k = 16 * s + 4 * (l >> 4) + j;
-                        frag[((size_t)base + ((size_t)t * n_steps + s) * kLanes + l) * 4 + j] =
+                    for (int j = 0; j < per; ++j) {
+                        const int o = 16 * t + (l & 15), k = 4 * per * s + per * (l >> 4) + j;
+                        frag[(size_t)base + (((size_t)t * n_steps + s) * kLanes + l) * per + j] =
                             (_Float16)(k < n_in ? W[o * n_in + k] : 0.0f);
                     }
     };
-    put(kNetFrag1, W1, kNetIn, kNetH1 / 16, 1);
-    put(kNetFrag2, W2, kNetH1, kNetH2 / 16, kNetH1 / 16);
-    put(kNetFrag3, W3, kNetH2, kNetH3 / 16, kNetH2 / 16);
+    put(kNetFrag1, W1, kNetIn, kNetH1 / 16, 1, 4);
+    put(kNetFrag2, W2, kNetH1, kNetH2 / 16, kNetH1 / 32, 8);
+    put(kNetFrag3, W3, kNetH2, kNetH3 / 16, kNetH2 / 32, 8);
     bias.assign((size_t)kNetBiasSize, 0.0f);
     for (int k = 0; k < kNetH1; ++k) bias[kNetBias1 + k] = b1[k];
     for (int k = 0; k < kNetH2; ++k) bias[kNetBias2 + k] = b2[k];

@@ -34,13 +34,14 @@ constexpr int kTabSig0 = 288;        // sigma_init^2 [7], appended by a per-step
 constexpr int kTabSize = 296;
 
 // Learned self-collision network (Eq. 13): layer widths, the packed FP16
-// weight fragments (offsets in units of 4 halves: per column block, k-step
-// and lane) and the FP32 block of biases and output weights.
+// weight fragments (offsets in halves: per column block, k-step and lane, 4
+// halves per lane for layer 1's k-steps of 16, 8 for layers 2 and 3's
+// k-steps of 32) and the FP32 block of biases and output weights.
 constexpr int kNetIn = 14, kNetH1 = 256, kNetH2 = 128, kNetH3 = 64;
-constexpr int kNetFrag1 = 0;                                  // 16 column blocks x 1 k-step
-constexpr int kNetFrag2 = kNetFrag1 + (kNetH1 / 16) * 1 * 64;  // 8 x 16
-constexpr int kNetFrag3 = kNetFrag2 + (kNetH2 / 16) * 16 * 64;  // 4 x 8
-constexpr int kNetFragHalves = (kNetFrag3 + (kNetH3 / 16) * 8 * 64) * 4;
+constexpr int kNetFrag1 = 0;                                        // 16 column blocks x 1 k-step x 4
+constexpr int kNetFrag2 = kNetFrag1 + (kNetH1 / 16) * 1 * 64 * 4;   // 8 x 8 x 8
+constexpr int kNetFrag3 = kNetFrag2 + (kNetH2 / 16) * 8 * 64 * 8;   // 4 x 4 x 8
+constexpr int kNetFragHalves = kNetFrag3 + (kNetH3 / 16) * 4 * 64 * 8;
 constexpr int kNetBias1 = 0, kNetBias2 = 256, kNetBias3 = 384, kNetW4 = 448, kNetBias4 = 512;
 constexpr int kNetBiasSize = 516;
 static_assert(kNetH1 * kNetIn + kNetH1 + kNetH2 * kNetH1 + kNetH2 + kNetH3 * kNetH2 + 2 * kNetH3 + 1 ==
