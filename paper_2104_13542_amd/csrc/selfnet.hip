@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, cons
     const float qv = P.qbuf[((size_t)jq * N + (valid ? i : 0)) * H + h];
     __builtin_amdgcn_sched_barrier(0);  // keep that load ahead of the weight loads
 
-    // every weight fragment this wave uses, loaded up front (88 VGPRs)
+    // every weight fragment this wave uses, loaded up front (52 VGPRs)
     // (in the order of use, each layer's biases with its fragments)
     const half4_t *F1 = reinterpret_cast<const half4_t *>(frag + kNetFrag1);
     const half8_t *F2 = reinterpret_cast<const half8_t *>(frag + kNetFrag2);
