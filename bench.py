@@ -307,22 +307,15 @@ def selfnet_bench(seed, steps, warmup):
     """The STORM-shaped step with the learned self-collision network (Eq. 13,
     jointNERF form, on the matrix cores) in place of the sphere pairs, and
     the same problem with the sphere pairs."""
-    import numpy as np
-
     from paper_2104_13542_amd import inputs
 
     out = {"workload": "N=500 (250 Halton + B-spline, 250 Gaussian), H=30, all cost terms, 30 sphere + 20 cuboid "
                        "obstacles; self-collision by the network [sin q, cos q] -> 256 -> 128 -> 64 -> 1 (ReLU), "
-                       "FP16 operands, FP32 accumulation; parameters fitted to the sphere model's signed link distance",
+                       "FP16 weights, activations as FP16 (hi, lo) pairs, FP32 accumulation, as a kernel after the "
+                       "rollout; parameters fitted to the sphere model's signed link distance",
            "network_flops_per_step": 2 * (14 * 256 + 256 * 128 + 128 * 64 + 64) * 500 * 30}
     out.update(_variant_step(inputs.config_self_mlp(seed), steps, warmup))
     out["sphere_pairs"] = _variant_step(inputs.config2(seed), steps, warmup)
-    # a 64-sphere model (12 small flange spheres added): the network's
-    # activations no longer fit beside the rollout's in LDS, so it runs as
-    # its own kernel after the rollout
-    big = inputs.config_self_mlp(seed)
-    big.spheres = np.concatenate([big.spheres, [[8.0, 0.0, 0.0, 0.01 * k, 0.02] for k in range(12)]])
-    out["stand_alone_form_64_spheres"] = _variant_step(big, steps, warmup)
     return out
 
 

@@ -144,8 +144,9 @@ typedef struct storm_params {
        pairs, the term being the largest penetration.  1: the learned network
        (the paper's jointNERF form) whose parameters storm_robot.self_mlp
        holds: the term is max(0, d) for its predicted distance d, evaluated
-       on the matrix cores with FP16 operands and FP32 accumulation.  Plain
-       contexts only. */
+       by a kernel after the rollout on the matrix cores: FP16 weights, each
+       activation carried as a pair of FP16 values (hi, lo) and FP32
+       accumulation, which gives d to FP32 rounding.  Plain contexts only. */
     int32_t self_model;
 } storm_params;
 
@@ -162,7 +163,8 @@ typedef struct storm_robot {
     const float *spheres;                     /* host [n_spheres][5] */
     /* Learned self-collision network (used with storm_params.self_model = 1;
        may be NULL otherwise): host [STORM_SELF_MLP_SIZE] finite floats, copied
-       at init.  Input [sin q_1..7, cos q_1..7], ReLU layers of 256, 128 and
+       at init; the weight matrices W1, W2 and W3 must hold values that FP16
+       represents exactly (else init returns STORM_E_PARAM).  Input [sin q_1..7, cos q_1..7], ReLU layers of 256, 128 and
        64 units, one linear output; in order W1 [256][14], b1 [256],
        W2 [128][256], b2 [128], W3 [64][128], b3 [64], w4 [64], b4 (weight
        matrices [out][in]). */

@@ -274,6 +274,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         if (!robot->self_mlp) return STORM_E_NULL;
         for (int k = 0; k < STORM_SELF_MLP_SIZE; ++k)
             if (!finite_f(robot->self_mlp[k])) return STORM_E_PARAM;
+        if (!storm::selfnet_weights_fp16(robot->self_mlp)) return STORM_E_PARAM;
     }
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -331,7 +332,6 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     // self-collision term to the network pass
     P.selfnet = (params->self_model == 1 && (params->cost_mask & STORM_COST_SELF)) ? 1u : 0u;
     if (P.selfnet) P.cost_mask &= ~STORM_COST_SELF;
-    P.net_fused = P.selfnet && storm::selfnet_fits(robot->n_spheres, c->waves) ? 1u : 0u;
     P.seed_lo = (uint32_t)params->seed;
     P.seed_hi = (uint32_t)(params->seed >> 32);
     P.beta = params->beta;
@@ -390,7 +390,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &adam, (size_t)2 * H * STORM_DOF));
     STORM_TRY(dalloc(c, &ball, (size_t)8));
     if (P.selfnet) {
-        if (!P.net_fused) STORM_TRY(dalloc(c, &qbuf, (size_t)STORM_DOF * N * H));
+        STORM_TRY(dalloc(c, &qbuf, (size_t)STORM_DOF * N * H));
         STORM_TRY(dalloc(c, &c->net_frag, net_frag.size()));
         STORM_TRY(dalloc(c, &c->net_bias, net_bias.size()));
         STORM_TRY(hipMemcpyAsync(c->net_frag, net_frag.data(), sizeof(_Float16) * net_frag.size(),
@@ -479,7 +479,7 @@ static hipError_t enqueue_rollout(storm_ctx ctx, const float *d_x0, const float 
                                   const StepOut &out, hipStream_t s)
 {
     hipError_t e = storm::launch_rollout(ctx->P, ctx->R, d_x0, d_goal, d_noise, out, ctx->waves, s);
-    if (e == hipSuccess && ctx->P.selfnet && !ctx->P.net_fused)
+    if (e == hipSuccess && ctx->P.selfnet)
         e = storm::launch_selfnet(ctx->P, ctx->net_frag, ctx->net_bias, out, s);
     return e;
 }

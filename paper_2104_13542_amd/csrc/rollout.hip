@@ -14,25 +14,32 @@
 //                  hinges (Eq. 10-11)
 //   B   waves 0-2  forward kinematics (Eq. 8), one row of the eight frames
 //                  per wave, to LDS
+//       wave W-1   the hinge norms over the joints (Eq. 10-11)
 //   C   waves 0..W-3  world centres of the body spheres to LDS
 //       wave W-2   manipulability (Eq. 12)
-//       wave W-1   the hinge norms (Eq. 10-11) and pose (Eq. 9)
+//       wave W-1   pose (Eq. 9)
 //   D   all waves  environment (spheres x obstacles) and self-collision
 //                  (sphere pairs) split over waves
 //   E   wave 0     weighted running cost (Eq. 15), horizon sum (Eq. 2) as a
 //                  segmented DPP scan
 // Obstacle, sphere and pair records are indexed by wave-uniform loop
 // counters, so they are fetched with scalar loads into SGPRs; every per-point
-// LDS array is [row][lane] (conflict-free).  Reductions run in a fixed order:
-// results are bitwise reproducible.
+// LDS array is [row][lane] (conflict-free), and rows whose lifetimes do not
+// overlap share space (about 80 KB per workgroup with 52 spheres, so that the
+// batched form holds two workgroups per CU).  Reductions run in a fixed
+// order: results are bitwise reproducible.
 #include <algorithm>
 
 #include "kinematics.h"
 #include "sampling.h"
-#include "selfnet.h"
 
 namespace storm {
 namespace {
+
+// Rows of the sphere-centre block, which also holds the noise, sine/cosine
+// and hinge rows of phases A0-B (8 + 14 + 21) before the centres exist.
+__host__ __device__ constexpr int rollout_cen_rows(int S) { return 3 * S > 43 ? 3 * S : 43; }
+static_assert(2 * 16 <= 96, "the collision partials of 16 waves fit over the frame rows");
 
 // Wavefront-wide maximum of a non-negative float: IEEE bit patterns of
 // non-negative floats order like unsigned integers, so the maximum runs on
@@ -112,25 +119,26 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                                              const float *__restrict__ x0, const float *__restrict__ goal,
                                              const float *__restrict__ noise, const StepOut &out, float *smem)
 {
+    // LDS rows of 64 floats, overlaid where their lifetimes do not meet
+    // (rollout_lds_bytes), so that two workgroups of the batched form fit on
+    // one CU:
+    //   frames [96]              B - C,  then the collision partials [2W]  D - E
+    //   terms [kTerms]           B - E
+    //   |c|^2 [S], centres [3S]  C - D;  before them noise [8] A0 - A1,
+    //                            sin/cos [14] and hinges [21] A1 - B
+    //   velocities, accelerations [14]  A1 - C (task-space form only)
     const int S = R.n_spheres;
-    float *s_eps = smem;                    // [8][64]
-    float *s_q = s_eps + 8 * kLanes;        // [7][64]
-    float *s_v = s_q + kDof * kLanes;       // [7][64]
-    float *s_fr = s_v + kDof * kLanes;      // [8 frames][12][64]: R row-major, p
-    float *s_cen = s_fr + 96 * kLanes;      // [S][3][64]
-    float *s_penv = s_cen + 3 * S * kLanes; // [W][64]
-    float *s_pself = s_penv + W * kLanes;   // [W][64]
-    float *s_terms = s_pself + W * kLanes;  // [kTerms][64]
-    float *s_sc = s_terms + kTerms * kLanes;  // [7][2][64]: sin q_j, cos q_j
-    float *s_cn = s_sc + 14 * kLanes;       // [S][64]: |c|^2 of the sphere centres
-    float *s_lim = s_cn + S * kLanes;       // [3][7][64]: squared joint, velocity, stop hinges per joint
-    float *s_acc = s_lim + 3 * kDof * kLanes;  // [7][64]: joint accelerations (task-space form only)
-    // learned self-collision network inside the phases (task-space form,
-    // 16 waves): its first two hidden layers after the task rows, the last
-    // one over the frames, which are dead after phase C
-    _Float16 *s_n1 = reinterpret_cast<_Float16 *>(s_acc + kDof * kLanes);  // [64][kNetA1]
-    _Float16 *s_n2 = s_n1 + 64 * kNetA1;                                     // [64][kNetA2]
-    float *s_n3 = s_fr;                                                       // [64][kNetA3]
+    float *s_fr = smem;                        // [8 frames][12][64]: R row-major, p
+    float *s_penv = s_fr;                      // [W][64] (over the frames, after phase C)
+    float *s_pself = s_penv + W * kLanes;      // [W][64]
+    float *s_terms = s_fr + 96 * kLanes;       // [kTerms][64]
+    float *s_cn = s_terms + kTerms * kLanes;   // [S][64]: |c|^2 of the sphere centres
+    float *s_cen = s_cn + S * kLanes;          // [S][3][64]
+    float *s_eps = s_cen;                      // [8][64] (before the centres)
+    float *s_sc = s_eps + 8 * kLanes;          // [7][2][64]: sin q_j, cos q_j
+    float *s_lim = s_sc + 14 * kLanes;         // [3][7][64]: squared joint, velocity, stop hinges per joint
+    float *s_v = s_cen + rollout_cen_rows(S) * kLanes;  // [7][64] (task-space form only)
+    float *s_acc = s_v + kDof * kLanes;                  // [7][64]
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -151,22 +159,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     const float dt_h = tab[kTabDt + h];
     const float vs_h = tab[kTabVstop + h];
     const float q0_j = x0[jw], v0_j = x0[kDof + jw];
-    // network: waves 8-15 take layer 1 in phase B and layer 3 in phase D,
-    // waves 0-7 layer 2 in phase C, wave 0 the output in phase E; layer 1's
-    // weight fragments are loaded now
-    const bool net = kTask && W == 16 && P.net_fused != 0u;
-    const half4_t *NF1 = reinterpret_cast<const half4_t *>(P.net_frag + kNetFrag1);
-    const half8_t *NF2 = reinterpret_cast<const half8_t *>(P.net_frag + kNetFrag2);
-    const half8_t *NF3 = reinterpret_cast<const half8_t *>(P.net_frag + kNetFrag3);
-    half4_t nb1[2];
-    float nbias1[2] = {0.0f, 0.0f};
-    if (net && wave >= 8) {
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            nb1[t] = NF1[(2 * (wave - 8) + t) * kLanes + lane];
-            nbias1[t] = P.net_bias[kNetBias1 + 16 * (2 * (wave - 8) + t) + (lane & 15)];
-        }
-    }
     // culling record of obstacle `lane` (first 64 obstacles) for phase D
     const float4 bound0 = (mask & STORM_COST_ENV) ? load_bound(P.obs_bound, lane, P.n_sph_obs + P.n_box_obs)
                                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -197,8 +189,7 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         if (live) u = fmaf(sig_j, e, mu_j);
         const float v = v0_j + segmented_scan(dt_h * u, h, H);
         const float q = q0_j + segmented_scan(dt_h * v, h, H);
-        s_q[j * kLanes + lane] = q;
-        s_v[j * kLanes + lane] = v;
+        if (kTask) s_v[j * kLanes + lane] = v;
         // this joint's squared joint, velocity and stop hinges (Eq. 10-11),
         // summed over the joints in phase C
         const float hj = hinge_box(q, tab[kTabJlo + j], tab[kTabJhi + j]);
@@ -225,33 +216,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     __syncthreads();
 
     // ---- B: forward kinematics, one row of the frames per wave ----------------
-    half8_t nb2[8];
-    float nbias2 = 0.0f;
-    if (net && wave < 8) {  // layer 2's fragments, used in phase C
-#pragma unroll
-        for (int k = 0; k < 8; ++k) nb2[k] = NF2[(wave * 8 + k) * kLanes + lane];
-        nbias2 = P.net_bias[kNetBias2 + 16 * wave + (lane & 15)];
-    }
-    if (net && wave >= 8) {
-        // layer 1 from the sine and cosine rows of phase A1: feature f < 7 is
-        // sin q_f, 7 <= f < 14 is cos q_{f-7}, 14 and 15 are zero
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            half4_t a;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int f = 4 * (lane >> 4) + j, row = 16 * m + (lane & 15);
-                a[j] = f < 2 * kDof ? (_Float16)s_sc[(2 * (f % kDof) + (f >= kDof ? 1 : 0)) * kLanes + row]
-                                    : (_Float16)0.0f;
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
-                d = __builtin_amdgcn_mfma_f32_16x16x16f16(a, nb1[t], d, 0, 0, 0);
-                net_store_relu_h(s_n1, kNetA1, m, 2 * (wave - 8) + t, lane, d, nbias1[t]);
-            }
-        }
-    }
     if (wave < 3) {
         const int row = wave;
         float r[3] = {row == 0 ? 1.0f : 0.0f, row == 1 ? 1.0f : 0.0f, row == 2 ? 1.0f : 0.0f};
@@ -267,6 +231,16 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
 #pragma unroll
             for (int c = 0; c < 3; ++c) s_fr[(f * 12 + row * 3 + c) * kLanes + lane] = r[c];
             s_fr[(f * 12 + 9 + row) * kLanes + lane] = p;
+        }
+    } else if (wave == W - 1) {
+        // Eq. 10-11: norms over the joints of the hinges formed in phase A1
+        // (here, so that the hinge rows are free for the centres of phase C)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kDof; ++j) acc += s_lim[(k * kDof + j) * kLanes + lane];
+            s_terms[(2 + k) * kLanes + lane] = fast_sqrt(acc);
         }
     }
     __syncthreads();
@@ -302,14 +276,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             }
         }
     } else if (wave == W - 1) {
-        // Eq. 10-11: norms over the joints of the hinges formed in phase A1
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kDof; ++j) acc += s_lim[(k * kDof + j) * kLanes + lane];
-            s_terms[(2 + k) * kLanes + lane] = fast_sqrt(acc);
-        }
         if (mask & STORM_COST_POSE) {
             // Eq. 9: rotation error |diag(alpha_rot)(I - R_g^T R)|_F and position
             // error |diag(alpha_pos) R_g^T (p - p_g)|.
@@ -373,7 +339,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             }
         }
     }
-    if (net && wave < 8) net_layer2(s_n1, s_n2, nb2, nbias2, wave, lane);
     __syncthreads();
 
     // ---- D: collision terms ---------------------------------------------------
@@ -382,13 +347,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // masks are OR-ed in SGPRs and the square roots (penetration depths) run
     // only when some lane of the wave touches one of them.
     float env = 0.0f, selfpen = 0.0f;
-    half8_t nb3[4];
-    float nbias3 = 0.0f;
-    if (net && wave >= 8) {  // layer 3's fragments, used after this wave's collision work
-#pragma unroll
-        for (int k = 0; k < 4; ++k) nb3[k] = NF3[(((wave - 8) >> 1) * 4 + k) * kLanes + lane];
-        nbias3 = P.net_bias[kNetBias3 + 16 * ((wave - 8) >> 1) + (lane & 15)];
-    }
     if (mask & STORM_COST_ENV) {
         const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
         const STORM_CONST_AS float *box = uniform_ptr(P.box_obs);
@@ -542,7 +500,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             if (sp < s_end) round(sp, sp, tp, 0);
         }
     }
-    if (net && wave >= 8) net_layer3(s_n2, s_n3, nb3, nbias3, (wave - 8) >> 1, 2 * ((wave - 8) & 1), lane);
     s_penv[wave * kLanes + lane] = env;
     s_pself[wave * kLanes + lane] = selfpen;
 
@@ -568,7 +525,6 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             for (int w = 0; w < W; ++w) t[6] = fmaxf(t[6], s_pself[w * kLanes + lane]);
         if (mask & STORM_COST_ENV)
             for (int w = 0; w < W; ++w) t[7] += s_penv[w * kLanes + lane];
-        if (net) t[6] = fmaxf(net_output(s_n3, P.net_bias, lane), 0.0f);  // Eq. 13
         float c = P.w_pos * t[0];
         c = fmaf(P.w_rot, t[1], c);
         c = fmaf(P.a_joint, t[2], c);
@@ -655,14 +611,11 @@ __global__ __launch_bounds__(W * kLanes) void rollout_batch_kernel(const Problem
     }
 }
 
-size_t rollout_lds_bytes(int S, int W, bool task = false, bool net = false)
+size_t rollout_lds_bytes(int S, int W, bool task = false)
 {
-    return (size_t)(8 + 2 * kDof + 96 + 4 * S + 2 * W + kTerms + 2 * kDof + 3 * kDof + (task ? kDof : 0)) * kLanes *
-               sizeof(float) +
-           (net ? kNetLdsBytes : 0);
+    (void)W;  // the 2 W collision partials sit over the 96 frame rows
+    return (size_t)(96 + kTerms + S + rollout_cen_rows(S) + (task ? 2 * kDof : 0)) * kLanes * sizeof(float);
 }
-
-constexpr int kMaxLds = 160 * 1024;
 
 }  // namespace
 
@@ -670,7 +623,7 @@ hipError_t set_rollout_lds_limit()
 {
     const int bytes16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16);
     const int bytes8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8);
-    const int task16 = (int)std::min(rollout_lds_bytes(STORM_MAX_SPHERES, 16, true, true), (size_t)kMaxLds);
+    const int task16 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 16, true);
     const int task8 = (int)rollout_lds_bytes(STORM_MAX_SPHERES, 8, true);
     const void *fns[6] = {reinterpret_cast<const void *>(&rollout_kernel<16, false>),
                           reinterpret_cast<const void *>(&rollout_kernel<8, false>),
@@ -684,11 +637,6 @@ hipError_t set_rollout_lds_limit()
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-bool selfnet_fits(int n_spheres, int waves)
-{
-    return waves == 16 && rollout_lds_bytes(n_spheres, 16, true, true) <= (size_t)kMaxLds;
 }
 
 hipError_t launch_rollout_batch(const ProblemDev *probs, const int2 *items, int n_items, uint32_t *next,
@@ -714,7 +662,7 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
     // the task-space form only where it is asked for: the ball term, or the
     // flange velocity and acceleration outputs
     const bool task = (P.cost_mask & STORM_COST_BALL) || P.selfnet || out.xd != nullptr || out.xdd != nullptr;
-    const size_t lds = rollout_lds_bytes(R.n_spheres, waves, task, task && P.net_fused != 0u);
+    const size_t lds = rollout_lds_bytes(R.n_spheres, waves, task);
     const dim3 grid((unsigned)P.n_tiles);
     if (waves != 16 && waves != 8) return hipErrorInvalidValue;
     auto kernel = waves == 16 ? (task ? rollout_kernel<16, true> : rollout_kernel<16, false>)

@@ -7,8 +7,8 @@
 // One workgroup (8 waves) per 64-lane tile of the rollout (the same
 // (particle, step) rows): the three hidden layers are 64-row GEMMs on
 // v_mfma_f32_16x16x16_f16 (layer 1) and v_mfma_f32_16x16x32_f16 (FP16
-// operands, FP32 accumulation), with the
-// activations staged in LDS between layers and the weights read as
+// weights, activations as FP16 (hi, lo) pairs, FP32 accumulation), with
+// the activations staged in LDS between layers and the weights read as
 // pre-packed per-lane fragments (one coalesced 512-byte load per wave and
 // fragment).  The output layer is a 64-term dot product per row on the
 // vector units; the term then joins the running cost (weight a_coll, as the
@@ -24,16 +24,23 @@ namespace {
 
 constexpr int kNetWaves = 8;
 constexpr int kNetThreads = kNetWaves * kLanes;
-constexpr int kIn = 16;  // 14 inputs padded to one k-step
-constexpr int kX = kIn;  // LDS row stride of the encoding, in halves
+constexpr int kIn = 16;      // 14 inputs padded to one k-step
+constexpr int kX = 2 * kIn;  // LDS row stride of the encoding in halves: hi (16), lo (16)
+// LDS: encoding, first and second hidden layers; the last hidden layer's
+// FP32 rows reuse the first layer's space (dead once layer 2 has run)
+constexpr int kOffA1 = 64 * kX * 2;
+constexpr int kOffA2 = kOffA1 + 64 * kNetA1 * 2;
+constexpr int kNetLds = kOffA2 + 64 * kNetA2 * 2;
+static_assert(64 * kNetA3 * 4 <= 64 * kNetA1 * 2, "last hidden layer fits in the first layer's space");
 
 __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, const _Float16 *__restrict__ frag,
                                                               const float *__restrict__ bias, StepOut out)
 {
-    __shared__ __attribute__((aligned(16))) _Float16 s_x[64 * kX];
-    __shared__ __attribute__((aligned(16))) _Float16 s_a1[64 * kNetA1];
-    __shared__ __attribute__((aligned(16))) _Float16 s_a2[64 * kNetA2];
-    __shared__ __attribute__((aligned(16))) float s_a3[64 * kNetA3];
+    __shared__ __attribute__((aligned(16))) unsigned char s_lds[kNetLds];
+    _Float16 *s_x = reinterpret_cast<_Float16 *>(s_lds);
+    _Float16 *s_a1 = reinterpret_cast<_Float16 *>(s_lds + kOffA1);
+    _Float16 *s_a2 = reinterpret_cast<_Float16 *>(s_lds + kOffA2);
+    float *s_a3 = reinterpret_cast<float *>(s_lds + kOffA1);
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -71,28 +78,32 @@ __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, cons
     for (int s = 0; s < 4; ++s) b3[s] = F3[((wave >> 1) * 4 + s) * kLanes + lane];
     const float bias3 = bias[kNetBias3 + 16 * (wave >> 1) + (lane & 15)];
 
-    // encoding [sin q, cos q, 0, 0] of the 64 rows
+    // encoding [sin q, cos q, 0, 0] of the 64 rows, as (hi, lo) pairs
     if (wave < kDof) {
         float sn, cs;
         sincosf(valid ? qv : 0.0f, &sn, &cs);
-        s_x[lane * kX + wave] = (_Float16)sn;
-        s_x[lane * kX + kDof + wave] = (_Float16)cs;
+        _Float16 *r = s_x + lane * kX;
+        split_half(sn, r[wave], r[kIn + wave]);
+        split_half(cs, r[kDof + wave], r[kIn + kDof + wave]);
     } else if (wave == kDof) {
-        s_x[lane * kX + 14] = (_Float16)0.0f;
-        s_x[lane * kX + 15] = (_Float16)0.0f;
+        _Float16 *r = s_x + lane * kX;
+        r[14] = r[15] = r[kIn + 14] = r[kIn + 15] = (_Float16)0.0f;
     }
     __syncthreads();
 
-    // layer 1: 64 x 16 by 16 x 256; wave w: columns 32 w .. 32 w + 31
+    // layer 1: 64 x 16 by 16 x 256 for hi and for lo; wave w: columns
+    // 32 w .. 32 w + 31
     {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const half4_t a = net_load_a(s_x, kX, m, 0, lane);
+            const half4_t ahi = net_load_a(s_x, kX, m, 0, lane);
+            const half4_t alo = net_load_a(s_x + kIn, kX, m, 0, lane);
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 float4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
-                d = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b1[t], d, 0, 0, 0);
-                net_store_relu_h(s_a1, kNetA1, m, 2 * wave + t, lane, d, bias1[t]);
+                d = __builtin_amdgcn_mfma_f32_16x16x16f16(ahi, b1[t], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x16f16(alo, b1[t], d, 0, 0, 0);
+                net_store_relu_h(s_a1, kNetA1, kNetH1, m, 2 * wave + t, lane, d, bias1[t]);
             }
         }
     }
@@ -102,7 +113,8 @@ __global__ __launch_bounds__(kNetThreads) void selfnet_kernel(ProblemDev P, cons
     net_layer2(s_a1, s_a2, b2, bias2, wave, lane);
     __syncthreads();
 
-    // layer 3: 64 x 128 by 128 x 64; wave w: columns 16 (w / 2) .., rows 32 (w % 2) ..
+    // layer 3: 64 x 128 by 128 x 64; wave w: columns 16 (w / 2) .., rows 32
+    // (w % 2) ..; its FP32 output rows go where layer 1's were
     net_layer3(s_a2, s_a3, b3, bias3, wave >> 1, 2 * (wave & 1), lane);
     __syncthreads();
 
@@ -133,8 +145,20 @@ hipError_t launch_selfnet(const ProblemDev &P, const _Float16 *frag, const float
     return hipGetLastError();
 }
 
-// Pack the network's parameters (weights [out][in], FP32) into the per-lane
-// FP16 fragments the kernel loads, and the biases and output weights (FP32).
+bool selfnet_weights_fp16(const float *prm)
+{
+    const float *W1 = prm, *W2 = W1 + kNetH1 * kNetIn + kNetH1, *W3 = W2 + kNetH2 * kNetH1 + kNetH2;
+    auto exact = [](const float *W, int n) {
+        for (int k = 0; k < n; ++k)
+            if ((float)(_Float16)W[k] != W[k]) return false;
+        return true;
+    };
+    return exact(W1, kNetH1 * kNetIn) && exact(W2, kNetH2 * kNetH1) && exact(W3, kNetH3 * kNetH2);
+}
+
+// Pack the network's parameters (weights [out][in], FP32 holding FP16
+// values) into the per-lane FP16 fragments the kernel loads, and the biases
+// and output weights (FP32).
 void pack_selfnet(const float *prm, std::vector<_Float16> &frag, std::vector<float> &bias)
 {
     const float *W1 = prm, *b1 = W1 + kNetH1 * kNetIn;

@@ -79,8 +79,7 @@ struct ProblemDev {
     float *adam_m, *adam_v; // [H][7] Adam moments of the refinement
     float *ball;            // [8]: ball position, velocity (world frame) at the current state, pad
     float *qbuf;            // [7][N][H] joint positions of the last step (stand-alone network pass)
-    uint32_t selfnet;       // the self-collision term comes from the learned network
-    uint32_t net_fused;     // ... evaluated inside the rollout kernel (else by its own kernel after it)
+    uint32_t selfnet;       // the self-collision term comes from the learned network (its own kernel)
     const _Float16 *net_frag;  // packed network weights (pack_selfnet)
     const float *net_bias;
 };
@@ -139,9 +138,9 @@ hipError_t launch_rollout(const ProblemDev &P, const RobotDev &R, const float *x
 // Raise the dynamic-LDS limit of the rollout kernels to what the largest
 // sphere model needs (idempotent).
 hipError_t set_rollout_lds_limit();
-// Whether the learned self-collision network fits inside the rollout kernel
-// (16 waves, its activations in the LDS left by n_spheres body spheres).
-bool selfnet_fits(int n_spheres, int waves);
+// Whether the learned self-collision network's weight matrices (W1, W2, W3
+// of storm_robot.self_mlp) hold FP16 values only, as its kernel requires.
+bool selfnet_weights_fp16(const float *prm);
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream);
 // Learned self-collision term: after the rollout, adds a_coll max(0, d) to

@@ -56,10 +56,15 @@ def _args(storm, prob=None):
 
 
 def _init(storm, sp, rb, sc):
+    """storm_rollout_init's status; a context it creates (where a device is
+    present) is destroyed again."""
     h = ctypes.c_void_p()
-    return storm.lib().storm_rollout_init(ctypes.byref(h), ctypes.byref(sp) if sp is not None else None,
-                                          ctypes.byref(rb) if rb is not None else None,
-                                          ctypes.byref(sc) if sc is not None else None, None)
+    rc = storm.lib().storm_rollout_init(ctypes.byref(h), ctypes.byref(sp) if sp is not None else None,
+                                        ctypes.byref(rb) if rb is not None else None,
+                                        ctypes.byref(sc) if sc is not None else None, None)
+    if h.value:
+        storm.lib().storm_rollout_destroy(h)
+    return rc
 
 
 def test_init_validation(storm):
@@ -116,6 +121,24 @@ def test_self_network_validation(storm):
     bad[1000] = float("nan")
     rb2, k2 = storm.make_robot(prob.spheres, self_mlp=bad)
     assert _init(storm, sp, rb2, sc) == E.STORM_E_PARAM
+    # weight matrices must hold FP16 values (biases and output weights may not)
+    lay = dict((name, (int(np.prod(shape)))) for name, shape in inputs.SELF_MLP_LAYOUT)
+    off = {}
+    k = 0
+    for name, shape in inputs.SELF_MLP_LAYOUT:
+        off[name] = k
+        k += lay[name]
+    for name, ok in (("W1", False), ("W2", False), ("W3", False), ("b1", True), ("w4", True), ("b4", True)):
+        prm = prob.self_mlp.copy()
+        v = np.float32(prm[off[name]])
+        prm[off[name]] = float(np.nextafter(v, np.float32(np.inf)))  # an FP32 value FP16 cannot hold
+        assert np.float16(prm[off[name]]).astype(np.float32) != np.float32(prm[off[name]])
+        rb4, k4 = storm.make_robot(prob.spheres, self_mlp=prm)
+        got = _init(storm, sp, rb4, sc)
+        if ok:
+            assert got != E.STORM_E_PARAM, name  # passes validation (then needs a device)
+        else:
+            assert got == E.STORM_E_PARAM, name
     params = (storm.storm_params * 1)(sp)
     rb3, k3 = storm.make_robot(prob.spheres, self_mlp=prob.self_mlp)
     b = ctypes.c_void_p()
