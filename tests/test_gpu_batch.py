@@ -220,3 +220,76 @@ def test_batch_refine_rejects_collision_gradients():
         assert e.value.code == storm.STORM_E_UNSUPPORTED
     finally:
         b.close()
+
+
+def _sized_problem(seed, N, H, n_obs):
+    """A problem of the batched workload at a chosen shape: N particles
+    (half Halton + B-spline), H steps with dt = linspace(0.01, 0.1, H),
+    n_obs obstacles (half spheres, half cuboids)."""
+    pr = inputs.config3_problem(seed)
+    rng = np.random.default_rng(7700 + seed)
+    pr.params.n_particles = N
+    pr.params.n_halton = N // 2
+    pr.params.horizon = H
+    pr.params.dt = np.linspace(0.01, 0.1, H)
+    pr.obstacles = inputs.random_scene(rng, n_obs // 2, n_obs - n_obs // 2)
+    return pr
+
+
+def test_batch_against_oracle():
+    """Every problem of a batch with uneven shapes, up to the largest of
+    the batched workload (N = 1024, H = 40, 50 obstacles), against the FP64
+    oracle: horizon costs to 1e-4 relative (states within 1e-4 of the
+    manipulability threshold masked), and the update (the oracle's on the
+    kernel's costs) to 1e-4: stored shifted mean, variance and command; the
+    second control step samples with the advanced counter around the
+    shifted mean."""
+    import oracle
+    from paper_2104_13542_amd import storm
+    from tests.gpu_common import TOL_COST_REL, TOL_MEAN, cost_error, f32, manip_values
+
+    shapes = [(1024, 40, 50), (997, 20, 10), (128, 33, 27), (801, 40, 50), (300, 23, 41)]
+    probs = []
+    for k, (N, H, n_obs) in enumerate(shapes):
+        pr = _sized_problem(40 + k, N, H, n_obs)
+        pr.params.n_null = k % 2
+        pr.spheres, pr.obstacles = f32(pr.spheres), f32(pr.obstacles)
+        pr.q0, pr.v0, pr.a0 = f32(pr.q0), f32(pr.v0), f32(pr.a0)
+        probs.append(pr)
+    goals = _goals(probs)
+    gl = goals.cpu().double().numpy()
+    ors = []
+    for k, pr in enumerate(probs):
+        o = oracle.Oracle(pr, dh=f32(inputs.PANDA_DH), q_min=f32(inputs.PANDA_Q_MIN),
+                          q_max=f32(inputs.PANDA_Q_MAX), qd_max=f32(inputs.PANDA_QD_MAX))
+        o.dt = f32(pr.params.dt)
+        o.goal = gl[k]
+        ors.append(o)
+    b = storm.Batch(probs)
+    means = [np.zeros((pr.params.horizon, 7)) for pr in probs]
+    sig2s = [f32(np.asarray(pr.params.sigma_init) ** 2) for pr in probs]
+    try:
+        for step in range(2):
+            b.step(goals)
+            cmd = b.update(shift=True).cpu().double().numpy()
+            torch.cuda.synchronize()
+            for k, (pr, o) in enumerate(zip(probs, ors)):
+                p = pr.params
+                N = p.n_particles
+                eps = o.noise(step)
+                eps[N - p.n_null:] = 0.0
+                ro = o.rollout(means[k], np.sqrt(sig2s[k]), eps)
+                gC = b.costs(k).astype(np.float64)
+                near = (np.abs(manip_values(o, ro["q"]) - p.k_m) < 1e-4).any(axis=1)
+                assert near.sum() <= 0.1 * N, (step, k, near.sum())
+                err = cost_error(gC, ro["C"])
+                assert np.max(err[~near]) <= TOL_COST_REL, (step, k, np.max(err[~near]))
+                upd = o.update(gC, ro["u"], means[k], sig2s[k])
+                mb, sb, stb = b.get_state(k)
+                assert stb == step + 1
+                assert np.max(np.abs(mb - upd["mean_shift"])) <= TOL_MEAN, (step, k)
+                assert np.max(np.abs(sb - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"]), (step, k)
+                assert np.max(np.abs(cmd[k] - upd["cmd"])) <= TOL_MEAN, (step, k)
+                means[k], sig2s[k] = f32(mb), f32(sb)
+    finally:
+        b.close()

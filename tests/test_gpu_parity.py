@@ -46,15 +46,27 @@ def test_fk_parity(oracle_lib):
     pose = pose.cpu().double().numpy()
     manip = manip.cpu().double().numpy()
     dh = f32(inputs.PANDA_DH)
+    # m = sqrt(det A), A = J J^T (6 x 6, symmetric positive definite), from
+    # FP32 frames, products and L D L^T.  A relative perturbation g of A
+    # moves log det A by at most 6 g kappa (Weyl: |d lambda_i| <= g
+    # lambda_max, divided by lambda_i >= lambda_min), so |dm| / m <=
+    # 3 g kappa to first order, kappa = lambda_max / lambda_min: the error
+    # scales with m kappa, not with 1 / m.  The FP32 path's worst case over
+    # these configurations is 0.06 x 2^-24 kappa m beyond a 2e-6 floor (the
+    # rounding of m itself); the limit is 0.5 x 2^-24 kappa m + 2e-6.
+    worst = 0.0
     for k in range(n):
-        T = oracle_lib.fk(dh, q[k])[7]
-        ref = np.concatenate([T[:3, :3].reshape(-1), T[:3, 3]])
+        T = oracle_lib.fk(dh, q[k])
+        ref = np.concatenate([T[7][:3, :3].reshape(-1), T[7][:3, 3]])
         assert np.max(np.abs(pose[k] - ref)) < 2e-6
-        m = oracle_lib.manipulability(oracle_lib.jacobian(oracle_lib.fk(dh, q[k])))
-        # FP32 L D L^T of J J^T: det(J J^T) = m^2 carries ~1e-8 absolute
-        # rounding, so m = sqrt(det) is resolved to ~1e-8 / (2 m) away from
-        # singularities and to sqrt(1e-8) = 1e-4 next to them.
-        assert abs(manip[k] - m) <= max(1e-4 * min(1.0, 1e-3 / max(m, 1e-12)), 2e-6)
+        J = oracle_lib.jacobian(T)
+        m = oracle_lib.manipulability(J)
+        ev = np.linalg.eigvalsh(J @ J.T)
+        kappa = ev[-1] / ev[0]
+        dm = abs(manip[k] - m)
+        worst = max(worst, max(dm - 2e-6, 0.0) / (2.0 ** -24 * kappa * m))
+        assert dm <= 0.5 * 2.0 ** -24 * kappa * m + 2e-6, (k, m, kappa, dm)
+    print("largest |dm| / (2^-24 kappa m) beyond 2e-6: %.3g (limit 0.5)" % worst)
     # empty batch is a no-op
     storm.fk(torch.zeros((0, 7), device="cuda"))
 
@@ -156,12 +168,22 @@ def test_config2_full(oracle_lib, seed):
     # collision terms are exercised by this scene
     assert np.any(ro["terms"][..., 6] > 0) or np.any(ro["terms"][..., 7] > 0)
     p = prob.params
-    upd = o.update(g["C"], g["u"], np.zeros((p.horizon, 7)), f32(np.asarray(p.sigma_init) ** 2))
+    sig2_0 = f32(np.asarray(p.sigma_init) ** 2)
+    upd = o.update(g["C"], g["u"], np.zeros((p.horizon, 7)), sig2_0)
     assert np.max(np.abs(g["mean"] - upd["mean"])) <= TOL_MEAN
     assert np.max(np.abs(g["sigma2"] - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"])
-    if clean.all():
-        bound = _update_bound(ro, up, g["C"], p.beta)
-        assert np.all(np.abs(g["mean"] - up["mean"]) <= TOL_MEAN + 2.0 * bound)
+    # end to end: the oracle's own update, except that a particle with a
+    # state within 1e-4 of the manipulability threshold (whose cost may
+    # legitimately differ by the jump of the term) takes the kernel's C
+    n_masked = int((~clean).sum())
+    print("config 2 seed %d: %d particle(s) masked at the manipulability threshold" % (seed, n_masked))
+    C_ref = np.where(clean, ro["C"], g["C"])
+    up_h = o.update(C_ref, ro["u"], np.zeros((p.horizon, 7)), sig2_0)
+    ro_h = dict(ro, C=C_ref)
+    bound = _update_bound(ro_h, up_h, g["C"], p.beta)
+    assert np.all(np.abs(g["mean"] - up_h["mean"]) <= TOL_MEAN + 2.0 * bound)
+    if n_masked == 0:
+        assert np.array_equal(C_ref, ro["C"])
 
 
 def test_config2_override_and_halton_table(oracle_lib):
@@ -551,103 +573,69 @@ def _net_parts(prm):
     return parts
 
 
-def _net_forward_abs_bound(prm, q, fp16=False):
-    """Rows q [R][7]: the network's output d in FP64 (with fp16=True, the
-    encoding and the first two hidden layers' outputs rounded to FP16 as the
-    kernel stores them), and a first-order bound on the error of the kernel's
-    evaluation: unit roundoff u = 2^-11 on those roundings (the weights are
-    FP16-exact), about K 2^-24 relative per FP32 sum of K terms; ReLU is
-    1-Lipschitz, so an error e in a layer's input moves its output by at most
-    |W| e."""
-    P = _net_parts(prm)
-    r16 = (lambda a: a.astype(np.float16).astype(np.float64)) if fp16 else (lambda a: a)
-    u, acc = 2.0 ** -11, 2.0 ** -24
-    x = r16(np.concatenate([np.sin(q), np.cos(q)], axis=1))
-    a1 = r16(np.maximum(x @ P["W1"].T + P["b1"], 0.0))
-    a2 = r16(np.maximum(a1 @ P["W2"].T + P["b2"], 0.0))
-    a3 = np.maximum(a2 @ P["W3"].T + P["b3"], 0.0)
-    d = a3 @ P["w4"] + P["b4"][0]
-    A1, A2, A3 = np.abs(P["W1"]), np.abs(P["W2"]), np.abs(P["W3"])
-    e1 = (u * np.abs(x) + 1e-6) @ A1.T + u * a1 + 16 * acc * (np.abs(x) @ A1.T)
-    e2 = e1 @ A2.T + u * a2 + 256 * acc * (a1 @ A2.T)
-    e3 = e2 @ A3.T + 128 * acc * (a2 @ A3.T)
-    ed = e3 @ np.abs(P["w4"]) + 64 * acc * (a3 @ np.abs(P["w4"]))
-    return d, ed
-
-
-def _flip_bound(prm, q):
-    """Per row, the largest change of d when one FP16-rounded value (an
-    encoding entry or a hidden output of the first two layers) lands one unit
-    in the last place (at most 2^-10 |value|) away: that unit's derivative of
-    d, through the ReLUs active at the row, times the change."""
+def _net_forward(prm, q):
+    """The network's output d in FP64 for rows q [R][7] (numpy, from the
+    layout of the flat parameter array)."""
     P = _net_parts(prm)
     x = np.concatenate([np.sin(q), np.cos(q)], axis=1)
-    z1 = x @ P["W1"].T + P["b1"]
-    a1 = np.maximum(z1, 0.0)
-    z2 = a1 @ P["W2"].T + P["b2"]
-    a2 = np.maximum(z2, 0.0)
-    z3 = a2 @ P["W3"].T + P["b3"]
-    g2 = (P["w4"] * (z3 > 0)) @ P["W3"]  # dd/da2
-    g1 = (g2 * (z2 > 0)) @ P["W2"]  # dd/da1
-    g0 = (g1 * (z1 > 0)) @ P["W1"]  # dd/dx
-    ulp = 2.0 ** -10
-    return ulp * np.maximum(np.maximum(np.max(np.abs(x * g0), axis=1), np.max(np.abs(a1 * g1), axis=1)),
-                            np.max(np.abs(a2 * g2), axis=1))
+    a1 = np.maximum(x @ P["W1"].T + P["b1"], 0.0)
+    a2 = np.maximum(a1 @ P["W2"].T + P["b2"], 0.0)
+    a3 = np.maximum(a2 @ P["W3"].T + P["b3"], 0.0)
+    return a3 @ P["w4"] + P["b4"][0]
+
+
+# The kernel carries every activation as an FP16 (hi, lo) pair with FP16
+# weights and FP32 accumulation: its d agrees with the FP64 network to FP32
+# rounding (at most 8e-8 m measured over these shapes).  An FP16-only
+# evaluation errs by up to 2e-4 m on these states and fails this bound.
+TOL_NET = 1e-6
 
 
 @pytest.mark.parametrize("seed,N,H,extra", [(0, 64, 30, 0), (1, 500, 30, 0), (2, 1, 64, 0), (3, 37, 7, 0),
                                              (4, 150, 30, 12)])
 def test_self_collision_network(oracle_lib, seed, N, H, extra):
     """The learned self-collision model (Eq. 13, jointNERF form) on the
-    matrix cores against the oracle's FP64 network: max(0, d) at the
-    kernel's own states within the FP16 error bound of each row, the other
-    terms and the horizon cost unchanged around it.  With the Panda's 52
-    spheres the network runs inside the rollout kernel; with 64 (extra = 12
-    small flange spheres) its activations no longer fit beside the rollout's
-    in LDS and it runs as its own kernel after it."""
+    matrix cores against the FP64 oracle: max(0, d) at the kernel's own
+    states to TOL_NET (m), and the running and horizon costs of the
+    oracle's rollout with the network term to 1e-4 relative.  extra = 12
+    adds small flange spheres (a 64-sphere model: the sphere count does not
+    change the network pass)."""
     prob = inputs.config_self_mlp(seed, n_particles=N, horizon=H)
     if extra:
         add = np.array([[8.0, 0.0, 0.0, 0.01 * k, 0.02] for k in range(extra)])
         prob.spheres = np.concatenate([prob.spheres, add])
     o0 = oracle_lib.Oracle(prob)
     q0s = o0.rollout(np.zeros((H, 7)), np.asarray(prob.params.sigma_init), o0.noise(0))["q"].reshape(-1, 7)
-    d0, _ = _net_forward_abs_bound(prob.self_mlp, q0s)
+    d0 = _net_forward(prob.self_mlp, q0s)
     prob.self_mlp[-1] = float(np.float32(prob.self_mlp[-1] - np.median(d0)))  # both signs occur
     p = prob.params
     g, ro, up, o, eps = run_pair(prob, oracle_lib)
     assert_states(g, ro)
-    live = np.arange(p.n_particles)
     q = g["q"].reshape(-1, 7)
-    d_ref, bound = _net_forward_abs_bound(prob.self_mlp, q)
+    d_ref = _net_forward(prob.self_mlp, q)
     # the FP64 network of the oracle agrees with the numpy forward pass
     for r in range(0, q.shape[0], 97):
         assert oracle_lib.self_mlp(prob.self_mlp, q[r]) == pytest.approx(d_ref[r], rel=1e-12, abs=1e-12)
     term = g["terms"][..., 6].reshape(-1)
     ref = np.maximum(d_ref, 0.0)
-    assert (d_ref > 0).mean() > 0.1 and (d_ref < 0).mean() > 0.1
-    # against the exact network: within the first-order rounding bound
-    excess = np.abs(term - ref) - (2.0 * bound + 1e-6)
-    assert np.max(excess) <= 0.0, "worst row exceeds its bound by %.3g" % np.max(excess)
-    # against the same roundings taken in FP64: only the FP32 sums differ,
-    # which can move a rounded value by one unit in the last place; allow
-    # four such moves in a row
-    d16, _ = _net_forward_abs_bound(prob.self_mlp, q, fp16=True)
-    tol16 = 4.0 * _flip_bound(prob.self_mlp, q) + 1e-5
-    err16 = np.abs(term - np.maximum(d16, 0.0))
-    assert np.all(err16 <= tol16), (np.max(err16 - tol16), np.max(tol16))
-    # and closer to it than to the exact network, on average
-    assert np.mean(err16) < np.mean(np.abs(ref - np.maximum(d16, 0.0)))
-    # everything else in the running cost is the oracle's
-    other_g = g["c"] - p.a_coll * g["terms"][..., 6]
-    other_o = ro["c"] - p.a_coll * ro["terms"][..., 6]
+    if N * H >= 1000:
+        assert (d_ref > 0).mean() > 0.1 and (d_ref < 0).mean() > 0.1
+    err = np.abs(term - ref)
+    print("network term: max |error| %.3g m over %d rows" % (np.max(err), err.size))
+    assert np.max(err) <= TOL_NET, "max |d error| %.3g m" % np.max(err)
+    # the oracle's rollout with the network term: running and horizon costs
     m = manip_values(o, ro["q"])
     near = np.abs(m - p.k_m) < 1e-4
-    err = np.abs(other_g - other_o) / np.maximum(np.abs(ro["c"]), COST_FLOOR)
-    assert np.max(np.where(near, 0.0, err)) <= TOL_COST_REL
-    # the horizon cost is the weighted sum of the running costs it reports
-    hw = np.ones(p.horizon)
-    np.testing.assert_allclose(g["C"], (g["c"] * hw).sum(axis=1), rtol=2e-5, atol=1e-3)
-    assert live.size == g["C"].shape[0]
+    errc = cost_error(g["c"], ro["c"])
+    assert np.max(np.where(near, 0.0, errc)) <= TOL_COST_REL, "running cost %.3g" % np.max(errc[~near])
+    clean = ~near.any(axis=1)
+    assert clean.sum() >= 0.9 * p.n_particles
+    assert np.max(cost_error(g["C"], ro["C"])[clean]) <= TOL_COST_REL
+    # the network term at the oracle's states, weighted, within the cost bar
+    dt6 = np.abs(g["terms"][..., 6] - ro["terms"][..., 6]) * p.a_coll
+    assert np.max(np.where(near, 0.0, dt6) / np.maximum(np.abs(ro["c"]), COST_FLOOR)) <= TOL_COST_REL
+    upd = o.update(g["C"], g["u"], np.zeros((p.horizon, 7)), f32(np.asarray(p.sigma_init) ** 2))
+    assert np.max(np.abs(g["mean"] - upd["mean"])) <= TOL_MEAN
 
 
 def test_self_collision_network_in_a_graph():
@@ -707,3 +695,75 @@ def test_per_step_covariance_graph_with_two_iterations():
     finally:
         r.close()
         rg.close()
+
+
+@pytest.mark.parametrize("cfg", ["config1", "config2"])
+def test_two_iterations_against_oracle_chain(oracle_lib, cfg):
+    """K = 2 iterations in one control step (Alg. 1, inner loop): rollout,
+    update without a shift, a second rollout from the unshifted mean with
+    the noise counter one further, update, then the shift.  Each iteration
+    is compared with the oracle fed the same mean and variance: states to
+    1e-5, running and horizon costs to 1e-4 relative, the updated mean and
+    variance (the oracle's update on the kernel's costs) to 1e-4; the first
+    iteration also end to end."""
+    from paper_2104_13542_amd import storm
+    from tests.gpu_common import device_goal
+
+    if cfg == "config1":
+        prob = inputs.config1(5, v0_random=True)
+        prob.params.n_null = 2
+    else:
+        prob = inputs.config2(8, n_particles=200)
+    p = prob.params
+    N, H = p.n_particles, p.horizon
+    prob.spheres, prob.obstacles = f32(prob.spheres), f32(prob.obstacles)
+    prob.q0, prob.v0, prob.a0 = f32(prob.q0), f32(prob.v0), f32(prob.a0)
+    o = oracle_lib.Oracle(prob, dh=f32(inputs.PANDA_DH), q_min=f32(inputs.PANDA_Q_MIN),
+                          q_max=f32(inputs.PANDA_Q_MAX), qd_max=f32(inputs.PANDA_QD_MAX))
+    o.dt = f32(p.dt)
+    o.goal = f32(o.goal)
+    r = storm.Rollout(prob)
+    goal = device_goal(o)
+    mean = np.zeros((H, 7))
+    sig2 = f32(np.asarray(p.sigma_init) ** 2)
+    try:
+        for k in range(2):
+            out = r.step(goal, debug=True)
+            cmd, mean_new, sig_new = r.update(shift=(k == 1))
+            torch.cuda.synchronize()
+            g = {key: v.detach().cpu().double().numpy() for key, v in out.items()}
+            for key in ("u", "q", "v", "a"):
+                g[key] = g[key].transpose(1, 2, 0)
+            g["terms"] = g["terms"].transpose(1, 2, 0)
+            eps = o.noise(k)  # the counter advances with every update
+            eps[N - p.n_null:] = 0.0
+            ro = o.rollout(mean, np.sqrt(sig2), eps)
+            if cfg == "config1":
+                assert_states(g, ro)
+                assert np.max(cost_error(g["c"], ro["c"])) <= TOL_COST_REL
+                assert np.max(cost_error(g["C"], ro["C"])) <= TOL_COST_REL
+            else:
+                _config2_checks(g, ro, o, prob)
+            upd = o.update(g["C"], g["u"], mean, sig2)
+            gm = mean_new.cpu().double().numpy()
+            gs = sig_new.cpu().double().numpy()
+            assert np.max(np.abs(gm - upd["mean"])) <= TOL_MEAN, k
+            assert np.max(np.abs(gs - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"]), k
+            if k == 0 and cfg == "config1":
+                up = o.update(ro["C"], ro["u"], mean, sig2)
+                bound = _update_bound(ro, up, g["C"], p.beta)
+                assert np.all(np.abs(gm - up["mean"]) <= TOL_MEAN + 2.0 * bound)
+            mean_s, sig_s, step = r.get_state()
+            assert step == k + 1
+            if k == 0:
+                # no shift between the iterations: the stored mean is mu'
+                np.testing.assert_array_equal(mean_s, mean_new.cpu().numpy())
+            else:
+                np.testing.assert_array_equal(mean_s[:-1], mean_new.cpu().numpy()[1:])
+                assert np.all(mean_s[-1] == 0)
+                np.testing.assert_allclose(cmd.cpu().double().numpy(), upd["cmd"], atol=TOL_MEAN)
+                np.testing.assert_allclose(mean_s, f32(upd["mean_shift"]), atol=TOL_MEAN)
+            # the next iteration samples around the kernel's (unshifted) mean
+            mean, sig2 = f32(gm), f32(gs)
+    finally:
+        r.close()
