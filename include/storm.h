@@ -262,6 +262,21 @@ int32_t storm_rollout_set_ball(storm_ctx ctx, const float *d_ball, void *stream)
 int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_mean,
                            const float *d_noise, float *d_grad, float *d_J, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * gradient and expected cost as storm_rollout_grad, same arguments, layout
+ * and errors, bitwise equal results, but the adjoint's per-chunk partial
+ * sums go to a static scratch array of the library (0.9 MB per device,
+ * [512][7][64] + [512] floats, enough for every context; its device address
+ * is looked up once per device by storm_rollout_init) instead of the
+ * context's buffers.  Allocates nothing.  Every call on one device shares
+ * that device's array: calls that may overlap on one device (other streams,
+ * other threads, other contexts) race and must be ordered by the caller.
+ * E_RANGE if a context's partials would not fit (cannot happen for contexts
+ * storm_rollout_init accepts). */
+int32_t storm_rollout_grad_noalloc(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_mean,
+                                   const float *d_noise, float *d_grad, float *d_J, void *stream);
+
 /* Gradient refinement of the stored mean (the differentiable form):
  * `iterations` Adam steps (Kingma and Ba 2015: beta1 0.9, beta2 0.999,
  * eps 1e-8, moments restarted at each call) of learning rate lr on J above,

@@ -4,11 +4,47 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "storm_internal.h"
 
 using namespace storm;
+
+// Scratch of storm_rollout_grad_noalloc: the adjoint's partial gradients
+// [kAdjChunks][7][kMaxH] and partial horizon-cost sums [kAdjChunks] of any
+// context (its chunk count is at most kAdjChunks), 0.9 MB per device, held
+// until the process ends.  Host code never uses this name as an address: the
+// device address of each device's copy comes from hipGetSymbolAddress, once
+// per device, in storm_rollout_init.
+namespace {
+constexpr size_t kNoallocGradFloats = (size_t)kAdjChunks * STORM_DOF * kMaxH;
+constexpr size_t kNoallocFloats = kNoallocGradFloats + (size_t)kAdjChunks;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up on the
+// first call for that device), or nullptr if it cannot be had.
+float *scratch_on_current_device(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[device] = static_cast<float *>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -283,6 +319,11 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     c->params = *params;
     c->params.dt = nullptr;
     if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return STORM_E_DEVICE;
+    }
+    c->scratch = scratch_on_current_device(c->device);
+    if (!c->scratch) {
         delete c;
         return STORM_E_DEVICE;
     }
@@ -701,6 +742,27 @@ int32_t storm_rollout_grad(storm_ctx ctx, const float *d_x0, const float *d_goal
     if (ctx->error != STORM_OK) return ctx->error;
     if (ctx->P.grad_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
     if (storm::launch_grad(ctx->P, ctx->R, d_x0, d_goal, d_mean, d_noise, d_grad, d_J, 0, 0.0f, nullptr, 0,
+                           static_cast<hipStream_t>(stream)) != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    return STORM_OK;
+}
+
+int32_t storm_rollout_grad_noalloc(storm_ctx ctx, const float *d_x0, const float *d_goal, const float *d_mean,
+                                   const float *d_noise, float *d_grad, float *d_J, void *stream)
+{
+    if (!ctx || !d_x0 || !d_goal || !d_mean) return STORM_E_NULL;
+    if (ctx->error != STORM_OK) return ctx->error;
+    if (ctx->P.grad_mask & ~kDiffMask) return STORM_E_UNSUPPORTED;
+    ProblemDev P = ctx->P;
+    const size_t chunks = (size_t)(P.n_tiles < kAdjChunks ? P.n_tiles : kAdjChunks);
+    if (chunks * STORM_DOF * kMaxH > kNoallocGradFloats || P.H > kMaxH) return STORM_E_RANGE;
+    // the partials go to this device's static scratch instead of the
+    // context's own buffers; everything else is the context's
+    P.grad_part = ctx->scratch;
+    P.cost_part = ctx->scratch + kNoallocGradFloats;
+    if (storm::launch_grad(P, ctx->R, d_x0, d_goal, d_mean, d_noise, d_grad, d_J, 0, 0.0f, nullptr, 0,
                            static_cast<hipStream_t>(stream)) != hipSuccess) {
         ctx->error = STORM_E_DEVICE;
         return STORM_E_DEVICE;

@@ -198,6 +198,7 @@ struct storm_ctx_s {
     storm::RobotDev R{};
     _Float16 *net_frag = nullptr;  // learned self-collision weights (packed), when self_model = 1
     float *net_bias = nullptr;
+    float *scratch = nullptr;    // this device's static scratch (storm_rollout_grad_noalloc)
     std::vector<void *> allocs;  // every device allocation of this context
 };
 

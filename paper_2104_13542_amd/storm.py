@@ -87,7 +87,7 @@ EXPORTS = (
     "storm_batch_init", "storm_batch_step", "storm_batch_update", "storm_batch_graph_create",
     "storm_batch_set_config", "storm_batch_get_config", "storm_batch_autotune", "storm_batch_get_state",
     "storm_batch_set_state", "storm_batch_costs", "storm_batch_destroy", "storm_plant_step",
-    "storm_rollout_grad", "storm_rollout_refine", "storm_rollout_graph_create_refine",
+    "storm_rollout_grad", "storm_rollout_grad_noalloc", "storm_rollout_refine", "storm_rollout_graph_create_refine",
     "storm_batch_refine", "storm_batch_graph_create_refine", "storm_rollout_set_ball",
 )
 
@@ -135,6 +135,7 @@ def lib():
         L.storm_batch_destroy.argtypes = [vp]
         L.storm_plant_step.argtypes = [vp, vp, i32, ctypes.c_float, vp]
         L.storm_rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.storm_rollout_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.storm_rollout_refine.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, i32, vp]
         L.storm_rollout_graph_create_refine.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp,
                                                         ctypes.POINTER(vp)]

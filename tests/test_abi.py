@@ -200,6 +200,8 @@ def test_call_validation_before_device(storm):
     assert L.storm_rollout_status(None, None, None) == E.STORM_E_NULL
     assert L.storm_rollout_get_state(None, None, None, None, None) == E.STORM_E_NULL
     assert L.storm_rollout_set_state(None, None, None, None, None) == E.STORM_E_NULL
+    assert L.storm_rollout_grad(None, None, None, None, None, None, None, None) == E.STORM_E_NULL
+    assert L.storm_rollout_grad_noalloc(None, None, None, None, None, None, None, None) == E.STORM_E_NULL
     rb, keep = storm.make_robot(None)
     assert L.storm_fk(None, None, 1, None, None, None) == E.STORM_E_NULL
     assert L.storm_fk(ctypes.byref(rb), None, -1, None, None, None) == E.STORM_E_RANGE
