@@ -62,13 +62,15 @@ def flops_per_particle_step(mask, n_spheres, n_pairs, n_sph_obs, n_box_obs):
     return f
 
 
-def measured_traffic():
-    """HBM bytes per rollout launch from the committed rocprofv3 counter
-    summary, if it was taken on the kernel source as it is now (else None)."""
+def measured_counters():
+    """Hardware-counter figures per rollout launch from the committed
+    rocprofv3 summary (HBM bytes from FETCH_SIZE + WRITE_SIZE, copy-calibrated,
+    and executed FP32 FLOPs from SQ_INSTS_VALU_FLOPS_FP32), if they were taken
+    on the kernel source as it is now (else None)."""
     import hashlib
 
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "rollout_kernel_traffic.json")))
+        rec = json.load(open(os.path.join(ROOT, "profiles", "rollout_kernel_counters.json")))
     except (OSError, ValueError):
         return None
     src = b""
@@ -76,7 +78,7 @@ def measured_traffic():
         src += open(os.path.join(ROOT, "paper_2104_13542_amd", "csrc", f), "rb").read()
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
 
 
 def self_pair_count(spheres):
@@ -89,9 +91,22 @@ def self_pair_count(spheres):
     return n
 
 
-def cpu_baseline(prob, budget_s):
-    """FP64 oracle (single thread, as it stands) on whole steps of the same
-    workload until budget_s seconds have elapsed."""
+def _host_cpu():
+    model = "unknown CPU"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def _oracle_serial(prob, budget_s):
+    """Whole steps (noise, rollout, update, shift) of the FP64 oracle as it
+    stands, on one thread, until budget_s seconds have elapsed: (steps,
+    seconds)."""
     import numpy as np
 
     import oracle
@@ -108,24 +123,109 @@ def cpu_baseline(prob, budget_s):
         steps += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
-            break
-    model = "unknown CPU"
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                model = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {
+            return steps, el
+
+
+_CHUNK_ORACLES = {}
+
+
+def _oracle_chunk(args):
+    """Rollout of particles [a, b) of the problem by the oracle, in a worker
+    process (the oracle bound to that slice is built once per worker)."""
+    import copy
+
+    import oracle
+
+    prob, a, b, mean, sigma, eps = args
+    key = (id(prob), a, b)
+    o = _CHUNK_ORACLES.get(key)
+    if o is None:
+        pr = copy.deepcopy(prob)
+        p = pr.params
+        N = p.n_particles
+        p.n_particles = b - a
+        p.n_halton = min(max(p.n_halton - a, 0), b - a)
+        p.n_null = max(0, b - max(a, N - p.n_null))
+        o = oracle.Oracle(pr)
+        _CHUNK_ORACLES[key] = o
+    r = o.rollout(mean, sigma, eps, want_terms=False)
+    return r["C"], r["u"]
+
+
+def _oracle_parallel(prob, budget_s, workers):
+    """The same whole steps with the rollout split over `workers` processes
+    by particle ranges; the noise and the update run in this process, the
+    costs and controls are joined in particle order, so the arithmetic is
+    the single-threaded oracle's."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+
+    p = prob.params
+    N = p.n_particles
+    o = oracle.Oracle(prob)
+    bounds = [(N * k // workers, N * (k + 1) // workers) for k in range(workers)]
+    bounds = [(a, b) for a, b in bounds if b > a]
+    mean = np.zeros((p.horizon, 7))
+    sig2 = np.asarray(p.sigma_init, dtype=np.float64) ** 2
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(bounds)) as pool:
+        # one untimed step builds each worker's oracle
+        steps, t0, el = 0, None, 0.0
+        while True:
+            eps = o.noise(steps)
+            sig = np.sqrt(sig2)
+            parts = pool.map(_oracle_chunk, [(prob, a, b, mean, sig, eps[a:b]) for a, b in bounds],
+                             chunksize=1)
+            C = np.concatenate([c for c, _ in parts])
+            u = np.concatenate([uu for _, uu in parts])
+            up = o.update(C, u, mean, sig2)
+            mean, sig2 = up["mean_shift"], up["sigma2_shift"]
+            steps += 1
+            if t0 is None:
+                t0, steps = time.perf_counter(), 0
+                continue
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                return steps, el
+
+
+def cpu_baseline(seed, budget_s):
+    """The FP64 oracle as it stands on the host cores: whole steps of the
+    N=500, H=30 workload on one thread (`value`) and with the rollout over
+    all available cores (processes over particle ranges, joined in particle
+    order), and whole steps of the N=64, H=16 and N=1024, H=30 workloads on
+    one thread; budget_s seconds for the first, shorter samples for the
+    rest."""
+    from paper_2104_13542_amd import inputs
+
+    cores = len(os.sched_getaffinity(0))
+    prob = inputs.config2(seed)
+    p = prob.params
+    steps, el = _oracle_serial(prob, budget_s)
+    out = {
         "value": p.n_particles * p.horizon * steps / el,
         "unit": "rollout-steps/s",
         "cores": 1,
-        "host": "%s, %d cores available to the process" % (model, len(os.sched_getaffinity(0))),
+        "host": "%s, %d cores available to the process" % (_host_cpu(), cores),
         "kind": "oracle",
         "sample": "%d whole steps (noise + rollout + update) of the N=%d H=%d workload, %.1f s, 1 thread"
                   % (steps, p.n_particles, p.horizon, el),
     }
+    if cores > 1:
+        steps, el = _oracle_parallel(prob, 0.6 * budget_s, cores)
+        out["all_cores"] = {
+            "value": p.n_particles * p.horizon * steps / el, "unit": "rollout-steps/s", "cores": cores,
+            "sample": "%d whole steps of the same workload, %.1f s: noise and update on one thread, the rollout "
+                      "over %d processes by particle ranges" % (steps, el, cores)}
+    for name, pr in (("config1_N64_H16", inputs.config1(seed)), ("config4_N1024_H30", inputs.config4(seed))):
+        steps, el = _oracle_serial(pr, 0.2 * budget_s)
+        out[name] = {"value": pr.params.n_particles * pr.params.horizon * steps / el, "unit": "rollout-steps/s",
+                     "cores": 1, "ms_per_step": 1e3 * el / steps,
+                     "sample": "%d whole steps, %.1f s, 1 thread" % (steps, el)}
+    return out
 
 
 def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
@@ -429,12 +529,64 @@ def differentiable_bench(steps, latency_steps, warmup):
     }
 
 
-def large_bench(n_problems, steps, latency_steps, warmup, plain_steps):
+def tracking_sanity(n_problems, steps):
+    """Closed-loop sanity: n_problems STORM-shaped problems (N=500, H=30,
+    every cost term, no obstacles) start near the Panda's ready pose with a
+    static goal pose reachable from it (FK of the ready pose moved by up to
+    0.4 rad per joint); the batched graph and the plant (Eq. 7, 0.01 s per
+    step) run `steps` control steps.  Reports the flange's position and
+    rotation errors at the end."""
+    import numpy as np
+    import torch
+
+    from paper_2104_13542_amd import inputs, storm
+
+    probs = []
+    for k in range(n_problems):
+        rng = np.random.default_rng(9100 + k)
+        pr = inputs.config2(9100 + k)
+        pr.obstacles = np.zeros((0, inputs.OBSTACLE_STRIDE))
+        pr.q0 = inputs.PANDA_READY + rng.uniform(-0.1, 0.1, 7)
+        pr.q_goal = inputs.PANDA_READY + rng.uniform(-0.4, 0.4, 7)
+        probs.append(pr)
+    qg = torch.tensor(np.stack([pr.q_goal for pr in probs]), dtype=torch.float32, device="cuda")
+    goals = storm.fk(qg)[0].contiguous()
+    b = storm.Batch(probs)
+    x0 = b.x0.clone()
+    cmd = torch.zeros((n_problems, 7), dtype=torch.float32, device="cuda")
+    graph = b.graph(x0, goals, cmd, iterations=1, shift=True)
+    pose0 = storm.fk(x0[:, :7].contiguous())[0]
+    err0 = torch.linalg.norm(pose0[:, 9:12] - goals[:, 9:12], dim=1).cpu().numpy()
+    for _ in range(steps):
+        graph.launch()
+        storm.plant_step(x0, cmd, 0.01)
+    pose = storm.fk(x0[:, :7].contiguous())[0]
+    torch.cuda.synchronize()
+    err = torch.linalg.norm(pose[:, 9:12] - goals[:, 9:12], dim=1).cpu().numpy()
+    Re = pose[:, :9].reshape(-1, 3, 3)
+    Rg = goals[:, :9].reshape(-1, 3, 3)
+    cosang = (((Rg * Re).sum(dim=(1, 2)) - 1.0) / 2.0).clamp(-1.0, 1.0)
+    rot = torch.rad2deg(torch.arccos(cosang)).cpu().numpy()
+    graph.close()
+    b.close()
+    return {
+        "workload": "%d problems, N=500 (250 Halton + B-spline, 250 Gaussian), H=30, every cost term, no "
+                    "obstacles; start within 0.1 rad of the ready pose, static goal = FK(ready pose + U(-0.4, "
+                    "0.4) rad per joint); batched graph + plant, %d control steps of 0.01 s" % (n_problems, steps),
+        "start_position_error_m": {"median": float(np.median(err0)), "max": float(np.max(err0))},
+        "final_position_error_m": {"median": float(np.median(err)), "max": float(np.max(err))},
+        "final_rotation_error_deg": {"median": float(np.median(rot)), "max": float(np.max(rot))},
+        "within_1cm": int(np.sum(err < 0.01)),
+    }
+
+
+def large_bench(n_problems, steps, latency_steps, warmup, plain_steps, loop_steps=2000):
     """Large workload: n_problems problems of N=4096, H=64 with 100 obstacles
     (every cost term for MPPI, pose + joint-limit terms refined by 3 Adam
     steps of the batched adjoint), in closed loop against a goal moving along
     y (0.3 m amplitude, 0.2 Hz), 0.01 s per control step; against one
-    captured graph per problem."""
+    captured graph per problem.  The closed loop runs loop_steps control
+    steps in all (the timed, latency and untimed parts)."""
     import numpy as np
     import torch
 
@@ -485,8 +637,20 @@ def large_bench(n_problems, steps, latency_steps, warmup, plain_steps):
         lat.append((time.perf_counter() - t0) * 1e3)
         storm.plant_step(x0, cmd, dt)
     lat = np.array(lat)
+    # the rest of the closed loop, untimed, sampling the position error of
+    # every problem every 20 steps over the last 5 s of simulated time
+    errs = []
+    for k in range(warmup + steps + latency_steps, loop_steps):
+        set_goal(k)
+        graph.launch()
+        storm.plant_step(x0, cmd, dt)
+        if k >= loop_steps - 500 and (loop_steps - 1 - k) % 20 == 0:
+            pose = storm.fk(x0[:, :7].contiguous())[0]
+            errs.append(torch.linalg.norm(pose[:, 9:12] - goals[:, 9:12], dim=1).cpu().numpy())
     pose = storm.fk(x0[:, :7].contiguous())[0]
     err = torch.linalg.norm(pose[:, 9:12] - goals[:, 9:12], dim=1).cpu().numpy()
+    errs = np.concatenate(errs) if errs else err
+    total_steps = max(loop_steps, warmup + steps + latency_steps)
     graph.close()
     b.close()
 
@@ -526,8 +690,10 @@ def large_bench(n_problems, steps, latency_steps, warmup, plain_steps):
         "problems_per_s": n_problems * 1e3 / ms,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "steps": int(len(lat)), "closed_loop": True},
-        "closed_loop_steps": warmup + steps + latency_steps,
-        "position_error_m": {"median": float(np.median(err)), "max": float(np.max(err))},
+        "closed_loop_steps": total_steps,
+        "position_error_m": {"final_median": float(np.median(err)), "final_max": float(np.max(err)),
+                             "last_5s_p50": float(np.percentile(errs, 50)),
+                             "last_5s_p90": float(np.percentile(errs, 90))},
         "autotuned": best,
         "plain_per_problem": {
             "ms_per_step": plain_ms,
@@ -553,6 +719,10 @@ def main():
     ap.add_argument("--diff-steps", type=int, default=200, help="differentiable-form steps (0 = skip)")
     ap.add_argument("--large-problems", type=int, default=64, help="large workload size (0 = skip)")
     ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--large-loop-steps", type=int, default=2000,
+                    help="control steps of the large workload's closed loop in all")
+    ap.add_argument("--sanity-steps", type=int, default=400,
+                    help="closed-loop steps of the reachable-goal tracking check (0 = skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (hardware-counter calibration)")
     args = ap.parse_args()
@@ -655,6 +825,8 @@ def main():
     n_pairs = self_pair_count(prob.spheres)
     fpp = flops_per_particle_step(p.cost_mask, n_sph, n_pairs, n_so, n_bo)
     achieved = fpp * N * H / (rollout_ms * 1e-3) / 1e12
+    ctr = measured_counters()
+    executed = None if ctr is None else ctr["valu_flops_fp32_per_launch"] / (rollout_ms * 1e-3) / 1e12
 
     line = {
         "metric": METRIC,
@@ -691,9 +863,14 @@ def main():
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
             "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "flops_per_launch": fpp * N * H,
+            "flops_count": "brute-force equivalent: every sphere pair and sphere-obstacle pair tested",
             "avg_launch_us": rollout_ms * 1e3,
-            "traffic": measured_traffic(),
+            "traffic": None if ctr is None else ctr["fetch_bytes_per_launch"] + ctr["write_bytes_per_launch"],
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "executed_tflops": executed,
+            "executed_frac_unpacked_peak": None if executed is None else executed / PEAK_FP32_UNPACKED_TFLOPS,
+            "executed_count": "rocprofv3 SQ_INSTS_VALU_FLOPS_FP32 x 64 per launch (committed summary) over the "
+                              "launch time above; the kernels use no packed FP32 instructions",
         },
     }
     if args.copy_calibration_mb > 0:
@@ -725,10 +902,13 @@ def main():
         progress("differentiable workload done")
     if args.large_problems > 0:
         line["large"] = large_bench(args.large_problems, args.large_steps, args.large_steps, warmup=20,
-                                    plain_steps=5)
+                                    plain_steps=5, loop_steps=args.large_loop_steps)
         progress("large workload done")
+    if args.sanity_steps > 0:
+        line["tracking_sanity"] = tracking_sanity(16, args.sanity_steps)
+        progress("tracking sanity done")
     if args.cpu_budget > 0:
-        line["cpu_baseline"] = cpu_baseline(inputs.config2(args.seed), args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(args.seed, args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 
