@@ -26,6 +26,13 @@ if ROOT not in sys.path:
 
 METRIC = "rollout-steps/s & MPC-step p50/p99 latency, batched vs plain, N=500 H=30"
 
+# Floor of the sampling variance in the closed-loop runs (a parameter the
+# paper leaves open): without one, the update's variance shrinks by
+# (1 - alpha_sigma) per step under near one-hot weights and the controller
+# stops exploring; 1e-3 lets the reachable-goal check settle below a
+# millimetre, where 1e-4 leaves 2-6 cm.
+CLOSED_LOOP_SIGMA2_MIN = 1e-3
+
 # MI355X published peaks.
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # packed FP32 vector
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # one FP32 op per lane per cycle (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
@@ -238,6 +245,8 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
     from paper_2104_13542_amd import inputs, storm
 
     probs = [inputs.config3_problem(p) for p in range(n_problems)]
+    for pr in probs:
+        pr.params.sigma2_min = CLOSED_LOOP_SIGMA2_MIN
     work = sum(pr.params.n_particles * pr.params.horizon for pr in probs)
     qg = torch.tensor(np.stack([pr.q_goal for pr in probs]), dtype=torch.float32, device="cuda")
     goals = storm.fk(qg)[0].contiguous()
@@ -534,8 +543,8 @@ def tracking_sanity(n_problems, steps):
     every cost term, no obstacles) start near the Panda's ready pose with a
     static goal pose reachable from it (FK of the ready pose moved by up to
     0.4 rad per joint); the batched graph and the plant (Eq. 7, 0.01 s per
-    step) run `steps` control steps.  Reports the flange's position and
-    rotation errors at the end."""
+    step) run `steps` control steps, with the closed-loop variance floor.
+    Reports the flange's position and rotation errors at the end."""
     import numpy as np
     import torch
 
@@ -548,6 +557,7 @@ def tracking_sanity(n_problems, steps):
         pr.obstacles = np.zeros((0, inputs.OBSTACLE_STRIDE))
         pr.q0 = inputs.PANDA_READY + rng.uniform(-0.1, 0.1, 7)
         pr.q_goal = inputs.PANDA_READY + rng.uniform(-0.4, 0.4, 7)
+        pr.params.sigma2_min = CLOSED_LOOP_SIGMA2_MIN
         probs.append(pr)
     qg = torch.tensor(np.stack([pr.q_goal for pr in probs]), dtype=torch.float32, device="cuda")
     goals = storm.fk(qg)[0].contiguous()
@@ -572,7 +582,8 @@ def tracking_sanity(n_problems, steps):
     return {
         "workload": "%d problems, N=500 (250 Halton + B-spline, 250 Gaussian), H=30, every cost term, no "
                     "obstacles; start within 0.1 rad of the ready pose, static goal = FK(ready pose + U(-0.4, "
-                    "0.4) rad per joint); batched graph + plant, %d control steps of 0.01 s" % (n_problems, steps),
+                    "0.4) rad per joint); batched graph + plant, %d control steps of 0.01 s, sigma^2 floor %g"
+                    % (n_problems, steps, CLOSED_LOOP_SIGMA2_MIN),
         "start_position_error_m": {"median": float(np.median(err0)), "max": float(np.max(err0))},
         "final_position_error_m": {"median": float(np.median(err)), "max": float(np.max(err))},
         "final_rotation_error_deg": {"median": float(np.median(rot)), "max": float(np.max(rot))},
@@ -595,6 +606,7 @@ def large_bench(n_problems, steps, latency_steps, warmup, plain_steps, loop_step
     probs = [inputs.config5_problem(p) for p in range(n_problems)]
     for pr in probs:
         pr.params.grad_mask = inputs.COST_POSE | inputs.COST_JOINT
+        pr.params.sigma2_min = CLOSED_LOOP_SIGMA2_MIN
     work = sum(pr.params.n_particles * pr.params.horizon for pr in probs)
     qg = torch.tensor(np.stack([pr.q_goal for pr in probs]), dtype=torch.float32, device="cuda")
     base = storm.fk(qg)[0].contiguous()

@@ -506,7 +506,14 @@ class Batch:
 
 class ExpectedCost(torch.autograd.Function):
     """J(mean) = (1/N) sum_i C_i(mean + sigma eps_i) with the last step's
-    noise held fixed; backward is the hand-written adjoint kernel."""
+    noise held fixed, differentiated by the hand-written adjoint kernel.
+
+    One adjoint launch yields both J and its gradient (the reverse pass
+    recomputes the states it needs; no forward-only path is cheaper than a
+    full rollout), so forward runs it and keeps the gradient, which belongs
+    to the inputs of that forward call; backward only scales it by the
+    incoming gradient.  A forward whose result is never differentiated still
+    pays for the reverse pass."""
 
     @staticmethod
     def forward(ctx, mean, rollout, goal, x0=None, noise=None):
