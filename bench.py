@@ -235,6 +235,44 @@ def cpu_baseline(seed, budget_s):
     return out
 
 
+def problem_flops(pr):
+    """Brute-force-equivalent FP32 FLOPs of one rollout of a problem."""
+    import numpy as np
+
+    from paper_2104_13542_amd import inputs
+
+    kinds = pr.obstacles[:, 0] if len(pr.obstacles) else np.zeros(0)
+    return pr.params.n_particles * pr.params.horizon * flops_per_particle_step(
+        pr.params.cost_mask, pr.spheres.shape[0], self_pair_count(pr.spheres),
+        int(np.sum(kinds == inputs.OBS_SPHERE)), int(np.sum(kinds == inputs.OBS_CUBOID)))
+
+
+def batch_rollout_roofline(b, goals, x0, probs, reps):
+    """The persistent rollout kernel alone: `reps` launches back to back on
+    the current stream between HIP events, priced with the brute-force
+    FLOPs of every problem."""
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    b.step(goals, x0=x0)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        b.step(goals, x0=x0)
+    end.record()
+    torch.cuda.synchronize()
+    b.update()  # leave the batch in its usual state
+    torch.cuda.synchronize()
+    us = start.elapsed_time(end) / reps * 1e3
+    flops = sum(problem_flops(pr) for pr in probs)
+    tf = flops / (us * 1e-6) / 1e12
+    return {"kernel": "rollout_batch_kernel", "bound": "alu", "avg_launch_us": us, "flops_per_launch": flops,
+            "achieved": tf, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_VECTOR_TFLOPS,
+            "frac_unpacked_peak": tf / PEAK_FP32_UNPACKED_TFLOPS,
+            "flops_count": "brute-force equivalent, summed over the problems"}
+
+
 def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
     """Batched form: n_problems problems of the uneven batched workload in one
     persistent launch per control step (graph-captured), against the plain
@@ -278,6 +316,7 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
         storm.plant_step(x0, cmd, 0.01)
     lat = np.array(lat)
     graph.close()
+    roof = batch_rollout_roofline(b, goals, x0, probs, 20)
     b.close()
 
     # plain form: one captured graph per problem, launched one after another
@@ -319,6 +358,7 @@ def batched_bench(n_problems, steps, latency_steps, warmup, tune_reps):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "steps": int(len(lat)), "closed_loop": True},
         "autotuned": best,
+        "roofline": roof,
         "plain_per_problem": {
             "rollout_steps_per_s": work * 1e3 / plain_ms,
             "problems_per_s": n_problems * 1e3 / plain_ms,
@@ -664,6 +704,7 @@ def large_bench(n_problems, steps, latency_steps, warmup, plain_steps, loop_step
     errs = np.concatenate(errs) if errs else err
     total_steps = max(loop_steps, warmup + steps + latency_steps)
     graph.close()
+    roof = batch_rollout_roofline(b, goals, x0, probs, 5)
     b.close()
 
     plains = [storm.Rollout(pr) for pr in probs]
@@ -707,6 +748,7 @@ def large_bench(n_problems, steps, latency_steps, warmup, plain_steps, loop_step
                              "last_5s_p50": float(np.percentile(errs, 50)),
                              "last_5s_p90": float(np.percentile(errs, 90))},
         "autotuned": best,
+        "rollout_roofline": roof,
         "plain_per_problem": {
             "ms_per_step": plain_ms,
             "problems_per_s": n_problems * 1e3 / plain_ms,

@@ -154,11 +154,13 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // Per-joint inputs of phase A1, loaded up front so that their latency
     // overlaps the noise generation.
     const int jw = wave < kDof ? wave : 0;
+    // (vector loads throughout, so that the first barrier waits for none of
+    // them: the state and the policy come fresh from the previous kernels)
     const float mu_j = live ? P.mean[h * kDof + jw] : 0.0f;
-    const float sig_j = sqrtf(P.cov_step ? P.sigma2[h * kDof + jw] : P.sigma2[jw]);
+    const float sig_j = sqrtf(P.cov_step ? P.sigma2[h * kDof + jw] : vector_load_f32(P.sigma2 + jw));
     const float dt_h = tab[kTabDt + h];
     const float vs_h = tab[kTabVstop + h];
-    const float q0_j = x0[jw], v0_j = x0[kDof + jw];
+    const float q0_j = vector_load_f32(x0 + jw), v0_j = vector_load_f32(x0 + kDof + jw);
     // culling record of obstacle `lane` (first 64 obstacles) for phase D
     const float4 bound0 = (mask & STORM_COST_ENV) ? load_bound(P.obs_bound, lane, P.n_sph_obs + P.n_box_obs)
                                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);

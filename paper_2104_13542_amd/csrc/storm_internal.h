@@ -117,6 +117,17 @@ __device__ __forceinline__ T load_uniform(const T *p)
     return v;
 }
 
+// A 32-bit word read by a vector (buffer) load even where its address is
+// wave-uniform: workgroup barriers wait for outstanding scalar and LDS
+// traffic only, so a value needed after a barrier, fetched this way early,
+// does not hold the barrier up for its memory latency.
+__device__ __forceinline__ uint32_t vector_load_u32(const void *p)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 4, 0x00020000);
+    return __builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0);
+}
+__device__ __forceinline__ float vector_load_f32(const float *p) { return __uint_as_float(vector_load_u32(p)); }
+
 // Hardware square root (v_sqrt_f32, 1 ulp) for norms and distances.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
