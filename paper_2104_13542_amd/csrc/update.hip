@@ -35,7 +35,7 @@ constexpr int kWaves = kThreads / kLanes;
 constexpr int kList = 4096;   // capacity of the nonzero-weight list
 constexpr int kChunk = 8192;  // weights staged in LDS per chunk (dense path)
 constexpr int kUnroll = 8;    // independent loads in flight per thread
-constexpr int kRegU = 32;     // controls per thread held in registers (register path)
+constexpr int kRegU = 32;     // most controls per thread held in registers (register path)
 
 // Full-wave reductions through DPP lane moves (quad permutes, half-row and
 // row mirrors, then the row broadcasts that carry each row's result into the
@@ -86,18 +86,41 @@ __device__ __forceinline__ float block_min(float v, float *s_wave, int lane, int
     return m;
 }
 
+// Workgroup LDS of the update, declared once per kernel.
+struct UpdateLds {
+    float buf[kChunk];  // register path: weights; list: indices, then weights; dense: a chunk
+    float red[2 * kThreads];
+    float wave[kWaves];
+    float wsum[kWaves];
+    int count[kWaves];
+    float mold[kMaxH];
+};
+
+// Controls per thread of the register path for N particles over `rows`
+// rows: the smallest of 8, 16 and 32 that holds them (0: other paths).
+__host__ __device__ inline int update_slots(int N, int H)
+{
+    const int rows = kThreads / H;
+    if (N > 2 * kThreads) return 0;
+    for (int k = 8; k <= kRegU; k *= 2)
+        if (N <= k * rows && k * rows <= kChunk) return k;
+    return 0;
+}
+
 // `cov` is P.cov_step, passed apart so that the plain kernel can fix it at
-// compile time.
+// compile time; kSlots the register path's controls per thread
+// (update_slots), 32 when that path is not taken.
+template <int kSlots>
 __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, float *__restrict__ mean_out,
                                              float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift,
-                                             const bool cov)
+                                             const bool cov, UpdateLds &L)
 {
-    __shared__ float s_buf[kChunk];  // register path: weights; list: indices, then weights; dense: a chunk
-    __shared__ float s_red[2 * kThreads];
-    __shared__ float s_wave[kWaves];
-    __shared__ float s_wsum[kWaves];
-    __shared__ int s_count[kWaves];
-    __shared__ float s_mold[kMaxH];
+    float *s_buf = L.buf;
+    float *s_red = L.red;
+    float *s_wave = L.wave;
+    float *s_wsum = L.wsum;
+    int *s_count = L.count;
+    float *s_mold = L.mold;
 
     const int t = threadIdx.x;
     const int lane = t & (kLanes - 1), wave = __builtin_amdgcn_readfirstlane(t / kLanes);
@@ -112,7 +135,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     const int r = t / H, h = t - r * H;
     const bool in_rows = r < rows;
     const float *__restrict__ U = P.u + (size_t)j * N * H + h;
-    const bool regs = N <= kRegU * rows && N <= 2 * kThreads && kRegU * rows <= kChunk;
+    const bool regs = N <= kSlots * rows && N <= 2 * kThreads && kSlots * rows <= kChunk;
     const float nib = -1.0f / beta;
 
     // register path: the costs, then every control load, all in flight at
@@ -120,7 +143,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
     // joint's N H values: slots past the last particle read 0 and cost no
     // address arithmetic (the load returns the raw 32 bits).
     float c0 = INFINITY, c1 = INFINITY;
-    float uu[kRegU];
+    float uu[kSlots];
     if (regs) {
         if (t < N) c0 = C[t];
         if (t + kThreads < N) c1 = C[t + kThreads];
@@ -128,10 +151,15 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             const_cast<float *>(P.u + (size_t)j * N * H), (short)0, N * H * (int)sizeof(float), 0x00020000);
         const int stride = rows * H * (int)sizeof(float);
 #pragma unroll
-        for (int k = 0; k < kRegU; ++k)
+        for (int k = 0; k < kSlots; ++k)
             uu[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ub, t * 4 + k * stride, 0, 0));
     }
     const float mu = in_rows ? P.mean[h * kDof + j] : 0.0f;
+    // the tail's parameters, fetched now with the first loads (kernel
+    // arguments read where they are first used would add a memory round
+    // trip to the tail)
+    const float alpha_mu = P.alpha_mu, alpha_sigma = P.alpha_sigma, sigma2_min = P.sigma2_min;
+    asm volatile("" : : "s"(alpha_mu), "s"(alpha_sigma), "s"(sigma2_min));
 
     float S0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
     int any_nonfinite = 0;
@@ -157,7 +185,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
         const float w1 = t + kThreads < N ? expf((c1 - cmin) * nib) : 0.0f;
         s_buf[t] = w0;
         s_buf[t + kThreads] = w1;
-        for (int i = 2 * kThreads + t; i < kRegU * rows; i += kThreads) s_buf[i] = 0.0f;  // slots past N
+        for (int i = 2 * kThreads + t; i < kSlots * rows; i += kThreads) s_buf[i] = 0.0f;  // slots past N
         const float sw = wave_sum(w0 + w1);
         if (lane == 0) s_wsum[wave] = sw;
         __syncthreads();
@@ -168,7 +196,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
         float a1[4] = {0.0f, 0.0f, 0.0f, 0.0f}, a2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (in_rows && ok) {
 #pragma unroll
-            for (int k = 0; k < kRegU; ++k) {
+            for (int k = 0; k < kSlots; ++k) {
                 const float d = uu[k] - mu;
                 const float wd = s_buf[r + k * rows] * d;
                 a1[k & 3] += wd;
@@ -301,7 +329,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             muo = s_mold[lane];
         }
         const float m1 = s1 * inv_S0, m2 = s2 * inv_S0;
-        const float delta = P.alpha_mu * m1;
+        const float delta = alpha_mu * m1;
         const float mu_new = ok ? muo + delta : muo;
         const float var = lane < H ? fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f) : 0.0f;  // about mu'
         const float acc = wave_sum(var);
@@ -312,7 +340,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             if (!cov) {
                 const float old = P.sigma2[j];
                 float s2n = old;
-                if (ok) s2n = fmaxf(fmaf(P.alpha_sigma, acc / (float)H - old, old), P.sigma2_min);
+                if (ok) s2n = fmaxf(fmaf(alpha_sigma, acc / (float)H - old, old), sigma2_min);
                 P.sigma2[j] = s2n;
                 if (sigma2_out) sigma2_out[j] = s2n;
             }
@@ -330,7 +358,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             // Eq. 5 per step: lane h updates sigma^2[h][j] from the variance at
             // step h; the shift moves it one step, sigma_init^2 appended
             const float old = lane < H ? P.sigma2[lane * kDof + j] : 0.0f;
-            const float s2n = ok ? fmaxf(fmaf(P.alpha_sigma, var - old, old), P.sigma2_min) : old;
+            const float s2n = ok ? fmaxf(fmaf(alpha_sigma, var - old, old), sigma2_min) : old;
             const float s2_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s2n), 0x130, 0xf, 0xf,
                                                                              true));  // wave_shl:1
             if (lane < H) {
@@ -344,12 +372,13 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
 // The fields the first loads depend on come first, as scalar arguments, so
 // that they are preloaded into SGPRs; the rest of the problem follows in P.
 // kCov: one variance per (step, joint) instead of one per joint.
-template <bool kCov>
+template <bool kCov, int kSlots>
 __global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, float *mean, float *sigma2, int32_t N,
                                                           int32_t H, float beta, ProblemDev P,
                                                           float *__restrict__ mean_out, float *__restrict__ sigma2_out,
                                                           float *__restrict__ cmd, int shift)
 {
+    __shared__ UpdateLds L;
     ProblemDev Q = P;
     Q.C = C;
     Q.u = u;
@@ -358,16 +387,24 @@ __global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, fl
     Q.N = N;
     Q.H = H;
     Q.beta = beta;
-    update_joint(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift, kCov);
+    update_joint<kSlots>(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift, kCov, L);
 }
 
 // Workgroup (p, j) of a batch; commands go to cmd[p][7].
 __global__ __launch_bounds__(kThreads) void update_batch_kernel(const ProblemDev *__restrict__ probs,
                                                                 float *__restrict__ cmd, int shift)
 {
+    __shared__ UpdateLds L;
     const int p = blockIdx.x / kDof, j = blockIdx.x - p * kDof;
     const ProblemDev P = load_uniform(probs + p);
-    update_joint(P, j, nullptr, nullptr, cmd + (size_t)p * kDof, shift, P.cov_step != 0u);
+    const int slots = update_slots(P.N, P.H);
+    float *c = cmd + (size_t)p * kDof;
+    if (slots == 8)
+        update_joint<8>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, L);
+    else if (slots == 16)
+        update_joint<16>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, L);
+    else
+        update_joint<32>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, L);
 }
 
 }  // namespace
@@ -382,12 +419,15 @@ hipError_t launch_update_batch(const ProblemDev *probs, int n_problems, float *c
 hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out, float *cmd, int shift,
                          hipStream_t stream)
 {
-    if (P.cov_step)
-        hipLaunchKernelGGL(update_kernel<true>, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2,
-                           P.N, P.H, P.beta, P, mean_out, sigma2_out, cmd, shift);
-    else
-        hipLaunchKernelGGL(update_kernel<false>, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2,
-                           P.N, P.H, P.beta, P, mean_out, sigma2_out, cmd, shift);
+    const int slots = update_slots(P.N, P.H);
+    auto kernel = P.cov_step ? (slots == 8    ? update_kernel<true, 8>
+                                : slots == 16 ? update_kernel<true, 16>
+                                              : update_kernel<true, 32>)
+                             : (slots == 8    ? update_kernel<false, 8>
+                                : slots == 16 ? update_kernel<false, 16>
+                                              : update_kernel<false, 32>);
+    hipLaunchKernelGGL(kernel, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2, P.N, P.H, P.beta, P,
+                       mean_out, sigma2_out, cmd, shift);
     return hipGetLastError();
 }
 
