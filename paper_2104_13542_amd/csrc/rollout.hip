@@ -58,6 +58,9 @@ __device__ __forceinline__ float wave_max_nonneg(float x)
     return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)b, 63));
 }
 
+// LDS copy of the goal (R row-major, p) and the cost weights, by index.
+constexpr int kParArot = 12, kParApos = 15, kParW = 18, kParKm = 25, kParCount = 26;
+
 // Lane 0's value, as a wave-uniform (SGPR) float.
 __device__ __forceinline__ float uniform_lane0(float x)
 {
@@ -164,6 +167,22 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // culling record of obstacle `lane` (first 64 obstacles) for phase D
     const float4 bound0 = (mask & STORM_COST_ENV) ? load_bound(P.obs_bound, lane, P.n_sph_obs + P.n_box_obs)
                                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // the goal and the cost weights that phases C and E read, staged in
+    // LDS by the last wave while the noise is drawn (read where they are
+    // used, as scalar loads, they would add a memory round trip to those
+    // serial phases)
+    __shared__ float s_par[kParCount];
+    if (wave == W - 1 && lane < kParCount) {
+        const float wts[kParCount - 12] = {P.alpha_rot[0], P.alpha_rot[1], P.alpha_rot[2], P.alpha_pos[0],
+                                           P.alpha_pos[1], P.alpha_pos[2], P.w_pos,        P.w_rot,
+                                           P.a_joint,      P.a_vel,        P.a_stop,       P.a_manip,
+                                           P.a_coll,       P.k_m};
+        float v = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kParCount - 12; ++k) v = lane == 12 + k ? wts[k] : v;
+        const float g = goal[lane < 12 ? lane : 0];
+        s_par[lane] = lane < 12 ? g : v;
+    }
 
     // ---- A0: standard noise ------------------------------------------------
     if (wave < 2) {
@@ -292,14 +311,14 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
             for (int r = 0; r < 3; ++r) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const float m = fmaf(goal[0 * 3 + r], Re[0 * 3 + c],
-                                         fmaf(goal[1 * 3 + r], Re[1 * 3 + c], goal[2 * 3 + r] * Re[2 * 3 + c]));
-                    const float e = P.alpha_rot[r] * ((r == c ? 1.0f : 0.0f) - m);
+                    const float m = fmaf(s_par[0 * 3 + r], Re[0 * 3 + c],
+                                         fmaf(s_par[1 * 3 + r], Re[1 * 3 + c], s_par[2 * 3 + r] * Re[2 * 3 + c]));
+                    const float e = s_par[kParArot + r] * ((r == c ? 1.0f : 0.0f) - m);
                     rot2 = fmaf(e, e, rot2);
                 }
-                const float l = fmaf(goal[0 * 3 + r], pe[0] - goal[9],
-                                     fmaf(goal[1 * 3 + r], pe[1] - goal[10], goal[2 * 3 + r] * (pe[2] - goal[11])));
-                const float e = P.alpha_pos[r] * l;
+                const float l = fmaf(s_par[0 * 3 + r], pe[0] - s_par[9],
+                                     fmaf(s_par[1 * 3 + r], pe[1] - s_par[10], s_par[2 * 3 + r] * (pe[2] - s_par[11])));
+                const float e = s_par[kParApos + r] * l;
                 pos2 = fmaf(e, e, pos2);
             }
             s_terms[0 * kLanes + lane] = fast_sqrt(pos2);
@@ -521,19 +540,20 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         if (mask & STORM_COST_STOP) t[4] = s_terms[4 * kLanes + lane];
         if (mask & STORM_COST_MANIP) {
             const float m = s_terms[5 * kLanes + lane];
-            t[5] = m < P.k_m ? 1.0f - m : 0.0f;
+            t[5] = m < s_par[kParKm] ? 1.0f - m : 0.0f;
         }
         if (mask & STORM_COST_SELF)
             for (int w = 0; w < W; ++w) t[6] = fmaxf(t[6], s_pself[w * kLanes + lane]);
         if (mask & STORM_COST_ENV)
             for (int w = 0; w < W; ++w) t[7] += s_penv[w * kLanes + lane];
-        float c = P.w_pos * t[0];
-        c = fmaf(P.w_rot, t[1], c);
-        c = fmaf(P.a_joint, t[2], c);
-        c = fmaf(P.a_vel, t[3], c);
-        c = fmaf(P.a_stop, t[4], c);
-        c = fmaf(P.a_manip, t[5], c);
-        c = fmaf(P.a_coll, t[6] + t[7], c);
+        const float *wc = s_par + kParW;  // w_pos, w_rot, a_joint, a_vel, a_stop, a_manip, a_coll
+        float c = wc[0] * t[0];
+        c = fmaf(wc[1], t[1], c);
+        c = fmaf(wc[2], t[2], c);
+        c = fmaf(wc[3], t[3], c);
+        c = fmaf(wc[4], t[4], c);
+        c = fmaf(wc[5], t[5], c);
+        c = fmaf(wc[6], t[6] + t[7], c);
         if (kTask && (mask & STORM_COST_BALL)) {
             t[8] = s_terms[8 * kLanes + lane];
             c = fmaf(P.w_ball, t[8], c);
