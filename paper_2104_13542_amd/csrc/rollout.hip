@@ -5,8 +5,9 @@
 // ppt = floor(64 / H) whole particles, lane = particle_in_tile * H + step.
 // One workgroup of W wavefronts owns one tile; the waves split the work of
 // the tile's 64 (particle, step) points and exchange data through LDS:
-//   A0  waves 0-1  standard noise: one Philox4x32-10 call gives four normals
-//                  (joints 4k..4k+3); or the Halton table; or the override
+//   A0  waves 0-3  standard noise: one Philox4x32-10 call gives four normals
+//                  (joints 4k..4k+3), each wave the Box-Muller pair of one
+//                  half of a call; or the Halton table; or the override
 //   A1  waves 0-6  one joint each: u = mu + sigma eps, then the two
 //                  segmented prefix sums of the triple integrator (Eq. 7) as
 //                  wavefront DPP scans over the particle's lanes, the joint's
@@ -185,13 +186,18 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     }
 
     // ---- A0: standard noise ------------------------------------------------
-    if (wave < 2) {
-        const int j0 = wave * 4;
-        float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // waves 0-3, one per SIMD: wave w makes the normal pair w / 2 of Philox
+    // call w % 2, i.e. joints 4 (w % 2) + 2 (w / 2) and the next (the
+    // Philox call is repeated by the two waves that share it; its Box-Muller
+    // half is not)
+    if (wave < 4) {
+        const int k = wave & 1, half = wave >> 1;
+        const int j0 = 4 * k + 2 * half;
+        float e[2] = {0.0f, 0.0f};
         const uint32_t counter = *P.step;
-        if (live) standard_noise4(P, noise, wave, i, h, counter, e);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) s_eps[(j0 + m) * kLanes + lane] = e[m];
+        if (live) standard_noise2(P, noise, k, half, i, h, counter, e);
+        s_eps[j0 * kLanes + lane] = e[0];
+        s_eps[(j0 + 1) * kLanes + lane] = e[1];
         if (tile == 0 && threadIdx.x == 0) *P.last_step = counter;
     }
     __syncthreads();

@@ -140,5 +140,29 @@ __device__ __forceinline__ void standard_noise4(const ProblemDev &P, const float
     }
 }
 
+// Standard noise of joints 4k + 2 half and 4k + 2 half + 1 for one (particle,
+// step) point: the same values as standard_noise4's e[2 half], e[2 half + 1]
+// (the Philox call of k, then the Box-Muller transform of its half).
+__device__ __forceinline__ void standard_noise2(const ProblemDev &P, const float *__restrict__ noise, int k, int half,
+                                                int i, int h, uint32_t counter, float e[2])
+{
+    const int j0 = 4 * k + 2 * half;
+    if (noise != nullptr) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) e[m] = j0 + m < kDof ? noise[((size_t)(j0 + m) * P.N + i) * P.H + h] : 0.0f;
+    } else if (i < P.n_halton) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            e[m] = j0 + m < kDof ? P.halton[((size_t)(j0 + m) * P.n_halton + i) * P.H + h] : 0.0f;
+    } else {
+        uint32_t c0 = (uint32_t)i, c1 = (uint32_t)h, c2 = (uint32_t)k, c3 = counter;
+        philox4x32_10(c0, c1, c2, c3, P.seed_lo, P.seed_hi);
+        if (half == 0)
+            box_muller(c0, c1, e[0], e[1]);
+        else
+            box_muller(c2, c3, e[0], e[1]);
+    }
+}
+
 }  // namespace
 }  // namespace storm
