@@ -293,3 +293,60 @@ def test_batch_against_oracle():
                 means[k], sig2s[k] = f32(mb), f32(sb)
     finally:
         b.close()
+
+
+def test_batch_variants_against_oracle():
+    """Batched problems with the comb-filtered Gaussian noise (Sec. 3.3),
+    a per-(step, joint) covariance (Eq. 5 kept per step) and null
+    particles, beside a plain one, against the FP64 oracle: horizon costs
+    to 1e-4 relative (threshold-masked), and the shifted mean and the
+    variance (per step where kept per step) to 1e-4 on the kernel's costs."""
+    import oracle
+    from paper_2104_13542_amd import storm
+    from tests.gpu_common import TOL_COST_REL, TOL_MEAN, cost_error, f32, manip_values
+
+    probs = []
+    for k, (N, H, n_obs, comb, cov, nn) in enumerate([(300, 30, 20, 1, 0, 0), (181, 24, 14, 0, 1, 3),
+                                                       (257, 37, 31, 1, 1, 2), (96, 20, 10, 0, 0, 0)]):
+        pr = _sized_problem(60 + k, N, H, n_obs)
+        pr.params.comb_filter = comb
+        pr.params.comb = (0.4, 0.4, 0.2)
+        pr.params.cov_per_step = cov
+        pr.params.n_null = nn
+        pr.spheres, pr.obstacles = f32(pr.spheres), f32(pr.obstacles)
+        pr.q0, pr.v0, pr.a0 = f32(pr.q0), f32(pr.v0), f32(pr.a0)
+        probs.append(pr)
+    goals = _goals(probs)
+    gl = goals.cpu().double().numpy()
+    b = storm.Batch(probs)
+    try:
+        b.step(goals)
+        b.update(shift=True)
+        torch.cuda.synchronize()
+        for k, pr in enumerate(probs):
+            p = pr.params
+            N, H = p.n_particles, p.horizon
+            o = oracle.Oracle(pr, dh=f32(inputs.PANDA_DH), q_min=f32(inputs.PANDA_Q_MIN),
+                              q_max=f32(inputs.PANDA_Q_MAX), qd_max=f32(inputs.PANDA_QD_MAX))
+            o.dt = f32(p.dt)
+            o.goal = gl[k]
+            sig2 = f32(np.asarray(p.sigma_init) ** 2)
+            if p.cov_per_step:
+                sig2 = np.ascontiguousarray(np.broadcast_to(sig2, (H, 7)))
+            eps = o.noise(0)
+            eps[N - p.n_null:] = 0.0
+            ro = o.rollout(np.zeros((H, 7)), np.sqrt(sig2), eps)
+            gC = b.costs(k).astype(np.float64)
+            near = (np.abs(manip_values(o, ro["q"]) - p.k_m) < 1e-4).any(axis=1)
+            assert near.sum() <= 0.1 * N
+            err = cost_error(gC, ro["C"])
+            assert np.max(err[~near]) <= TOL_COST_REL, (k, np.max(err[~near]))
+            upd = o.update(gC, ro["u"], np.zeros((H, 7)), sig2)
+            mb, sb, stb = b.get_state(k)
+            assert stb == 1
+            assert np.max(np.abs(mb - upd["mean_shift"])) <= TOL_MEAN, k
+            ref_s = upd["sigma2_shift"] if p.cov_per_step else upd["sigma2"]
+            assert sb.shape == ref_s.shape
+            assert np.max(np.abs(sb - ref_s)) <= 1e-4 * np.max(ref_s), k
+    finally:
+        b.close()
