@@ -390,9 +390,7 @@ def _variant_step(prob, steps, warmup, iterations=1, setup=None):
     graph = r.graph(x0, goal, cmd, iterations=iterations, shift=True)
 
     def eager_step():
-        for k in range(iterations):
-            r.step(goal, x0=x0, C=C)
-            r.update(shift=k == iterations - 1, want_mean=False, cmd=cmd)
+        r.control(x0, goal, cmd, iterations=iterations, shift=True)
 
     for _ in range(warmup):
         graph.launch()
@@ -819,8 +817,9 @@ def main():
     graph = r.graph(x0, goal, cmd, iterations=1, shift=True)
 
     def eager_step():
-        r.step(goal, x0=x0, C=C)
-        r.update(shift=True, want_mean=False, cmd=cmd)
+        # one call of the interface per control step: the rollout and update
+        # kernels launched eagerly (storm_rollout_control)
+        r.control(x0, goal, cmd, iterations=1, shift=True)
 
     for _ in range(args.warmup):
         graph.launch()
@@ -851,7 +850,7 @@ def main():
     rollout_ms = start.elapsed_time(end) / K
     r.update(shift=True, want_mean=False, cmd=cmd)
 
-    # eager (two launches per step from the host) for comparison
+    # eager (one interface call, two kernel launches per step) for comparison
     torch.cuda.synchronize()
     start.record()
     for _ in range(K):

@@ -287,6 +287,17 @@ int32_t storm_rollout_grad_noalloc(storm_ctx ctx, const float *d_x0, const float
 int32_t storm_rollout_refine(storm_ctx ctx, const float *d_x0, const float *d_goal, int32_t iterations, float lr,
                              float *d_cmd, int32_t shift, void *stream);
 
+/* One whole control step of Alg. 1 in a single call, launched eagerly:
+ * `iterations` (K >= 1) rounds of storm_rollout_step + storm_rollout_update
+ * on `stream`, the shift applied after the last round only, reading d_x0
+ * [3][7] and d_goal [12] and writing d_cmd [7] (device memory).  Enqueues
+ * exactly the kernels a graph of storm_rollout_graph_create would, with one
+ * crossing of the interface per control step instead of 2K, and leaves no
+ * step pending.  Allocates nothing.  Errors: E_NULL, E_RANGE
+ * (iterations < 1), E_DEVICE. */
+int32_t storm_rollout_control(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                              int32_t iterations, int32_t shift, void *stream);
+
 /* Opaque handle of an instantiated HIP graph of one control step. */
 typedef struct storm_graph_s *storm_graph;
 

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -187,42 +188,74 @@ std::vector<storm::SelfGroup> storm::self_groups(const storm_robot *robot)
     return g;
 }
 
-// Self-collision work split.  The kernel tests a group against two partners
-// s per round at the same cost whatever the group's count, so the rounds
-// (ceil(s_end / 2) per group, group-major) are cut into `waves` nearly equal
-// parts at whole rounds; each part is written as items (t_first | count << 8,
-// group, s_begin, s_end) with s_begin even.  Returns the pair count; off[w] ..
-// off[w + 1] are wave w's items.
-int storm::self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off)
+// Self-collision work items: one per (group, partner body), partners
+// [s_begin, s_end) the spheres of that body, written as eight integers
+// (t_first | count << 8, group, s_begin, s_end, a_t, a_s, bits of reach2, 0).
+// Broad phase: a_t is the sphere of the group, a_s the sphere of the partner
+// body, about whose centres the balls of radius R_t = max |c_t - c_a_t| + r_t
+// and R_s (likewise) hold every sphere of each side (each anchor chosen to
+// make its radius smallest); reach2 = (R_t + R_s + 1 mm)^2 rounded up.  Where
+// the anchors' centres are farther apart than R_t + R_s, no pair of the item
+// touches, and the millimetre covers the FP32 rounding of the centres
+// (micrometres within the robot's reach).  The rollout workgroup's waves take
+// the items from a queue in this order: most rounds (pairs of partners)
+// first.  Returns the pair count.
+int storm::self_segments(const storm_robot *robot, std::vector<int> &items)
 {
     const std::vector<SelfGroup> groups = self_groups(robot);
-    long long rounds = 0, pairs = 0;
-    for (const SelfGroup &g : groups) {
-        rounds += (g.s_end + 1) / 2;
-        pairs += (long long)g.count * g.s_end;
-    }
-    seg.clear();
-    off.assign(waves + 1, 0);
-    for (int w = 0; w < waves; ++w) {
-        off[w] = (int)seg.size() / 4;
-        const long long k0 = rounds * w / waves, k1 = rounds * (w + 1) / waves;
-        long long base = 0;
-        for (int gi = 0; gi < (int)groups.size(); ++gi) {
-            const SelfGroup &g = groups[gi];
-            const long long r = (g.s_end + 1) / 2;
-            // rounds base .. base + r - 1 are this group's; take those in [k0, k1)
-            const long long ra = k0 > base ? (k0 - base < r ? k0 - base : r) : 0;
-            const long long rb = k1 > base ? (k1 - base < r ? k1 - base : r) : 0;
-            if (ra < rb) {
-                seg.push_back(g.t_first | (g.count << 8));
-                seg.push_back(gi);
-                seg.push_back((int)(2 * ra));
-                seg.push_back((int)(2 * rb < g.s_end ? 2 * rb : g.s_end));
+    const float *sp = robot->spheres;
+    auto anchor = [&](int lo, int hi, double &radius) {
+        int best = lo;
+        radius = INFINITY;
+        for (int k = lo; k < hi; ++k) {
+            double r = 0.0;
+            for (int m = lo; m < hi; ++m) {
+                const double dx = (double)sp[5 * m + 1] - sp[5 * k + 1], dy = (double)sp[5 * m + 2] - sp[5 * k + 2],
+                             dz = (double)sp[5 * m + 3] - sp[5 * k + 3];
+                r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz) + (double)sp[5 * m + 4]);
             }
-            base += r;
+            if (r < radius) {
+                radius = r;
+                best = k;
+            }
+        }
+        return best;
+    };
+    struct Item {
+        int v[8];
+        int rounds, order;
+    };
+    std::vector<Item> list;
+    long long pairs = 0;
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        const SelfGroup &g = groups[gi];
+        pairs += (long long)g.count * g.s_end;
+        double rt = 0.0;
+        const int at = anchor(g.t_first, g.t_first + g.count, rt);
+        for (int lo = 0; lo < g.s_end;) {
+            int hi = lo + 1;
+            while (hi < g.s_end && (int)sp[5 * hi] == (int)sp[5 * lo]) ++hi;
+            double rs = 0.0;
+            const int as = anchor(lo, hi, rs);
+            const double reach = rt + rs + 1.0e-3;
+            const float reach2 = nextafterf((float)(reach * reach), INFINITY);
+            Item it{};
+            it.v[0] = g.t_first | (g.count << 8);
+            it.v[1] = gi;
+            it.v[2] = lo;
+            it.v[3] = hi;
+            it.v[4] = at;
+            it.v[5] = as;
+            memcpy(&it.v[6], &reach2, sizeof(float));
+            it.rounds = (hi - lo + 1) / 2;
+            it.order = (int)list.size();
+            list.push_back(it);
+            lo = hi;
         }
     }
-    off[waves] = (int)seg.size() / 4;
+    std::stable_sort(list.begin(), list.end(), [](const Item &x, const Item &y) { return x.rounds > y.rounds; });
+    items.clear();
+    for (const Item &it : list) items.insert(items.end(), it.v, it.v + 8);
     return (int)pairs;
 }
 
@@ -348,13 +381,13 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         }
     const float comb[3] = {params->comb_filter ? params->comb[0] : 1.0f, params->comb_filter ? params->comb[1] : 0.0f,
                            params->comb_filter ? params->comb[2] : 0.0f};
-    std::vector<int> seg, seg_off;
-    const int n_pairs = storm::self_segments(robot, c->waves, seg, seg_off);
+    std::vector<int> seg;
+    const int n_pairs = storm::self_segments(robot, seg);
     std::vector<_Float16> net_frag;
     std::vector<float> net_bias;
     if (params->self_model == 1) storm::pack_selfnet(robot->self_mlp, net_frag, net_bias);
     const std::vector<float> thr = storm::self_thresholds(robot, reach_bound(robot));
-    const int n_seg = (int)seg.size() / 4;
+    const int n_seg = (int)seg.size() / 8;
 
     ProblemDev &P = c->P;
     P.N = N;
@@ -401,8 +434,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     float *tables, *halton, *box_obs, *mean, *sigma2, *u, *C, *dt_raw, *lim_raw, *sig_raw, *obs_raw, *sph_raw_d;
     float *self_thr, *grad_part, *cost_part, *grad, *adam, *ball, *qbuf = nullptr;
     float4 *sph_obs, *obs_bound, *sph_local;
-    int32_t *sph_body, *self_off;
-    int4 *self_seg;
+    int32_t *sph_body, *self_seg;
     uint32_t *counters;
     hipError_t e = hipSuccess;
 #define STORM_TRY(expr)        \
@@ -442,8 +474,7 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
     STORM_TRY(dalloc(c, &sph_local, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &sph_body, (size_t)robot->n_spheres));
     STORM_TRY(dalloc(c, &self_thr, thr.size()));
-    STORM_TRY(dalloc(c, &self_seg, (size_t)n_seg));
-    STORM_TRY(dalloc(c, &self_off, seg_off.size()));
+    STORM_TRY(dalloc(c, &self_seg, (size_t)8 * n_seg));
     // staging copies of the host inputs (freed at destroy with the rest)
     STORM_TRY(dalloc(c, &dt_raw, (size_t)H));
     STORM_TRY(dalloc(c, &lim_raw, (size_t)3 * STORM_DOF));
@@ -468,7 +499,6 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
                                      hipMemcpyHostToDevice, s));
         if (n_seg > 0)
             STORM_TRY(hipMemcpyAsync(self_seg, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice, s));
-        STORM_TRY(hipMemcpyAsync(self_off, seg_off.data(), sizeof(int) * seg_off.size(), hipMemcpyHostToDevice, s));
         if (!thr.empty())
             STORM_TRY(hipMemcpyAsync(self_thr, thr.data(), sizeof(float) * thr.size(), hipMemcpyHostToDevice, s));
         P.tables = tables;
@@ -495,8 +525,8 @@ int32_t storm_rollout_init(storm_ctx *out, const storm_params *params, const sto
         c->R.sph_local = sph_local;
         c->R.sph_body = sph_body;
         c->R.self_thr = self_thr;
-        c->R.self_seg = self_seg;
-        c->R.self_off = self_off;
+        c->R.self_items = self_seg;
+        c->R.n_self_items = n_seg;
         STORM_TRY(storm::launch_init_tables(P, dt_raw, lim_raw, params->acc_stop, params->gamma, params->w_term,
                                             params->k_jl, params->k_vl, sig_raw, comb, params->n_knots, obs_raw,
                                             n_obs,
@@ -721,6 +751,28 @@ int32_t create_graph(storm_ctx ctx, const float *d_x0, const float *d_goal, floa
     return STORM_OK;
 }
 }  // namespace
+
+int32_t storm_rollout_control(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
+                              int32_t iterations, int32_t shift, void *stream)
+{
+    if (!ctx || !d_x0 || !d_goal || !d_cmd) return STORM_E_NULL;
+    if (iterations < 1) return STORM_E_RANGE;
+    if (ctx->error != STORM_OK) return ctx->error;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StepOut none{};
+    hipError_t e = hipSuccess;
+    for (int k = 0; e == hipSuccess && k < iterations; ++k) {
+        e = enqueue_rollout(ctx, d_x0, d_goal, nullptr, none, s);
+        if (e == hipSuccess)
+            e = storm::launch_update(ctx->P, nullptr, nullptr, d_cmd, k == iterations - 1 && shift != 0, s);
+    }
+    if (e != hipSuccess) {
+        ctx->error = STORM_E_DEVICE;
+        return STORM_E_DEVICE;
+    }
+    ctx->pending = false;
+    return STORM_OK;
+}
 
 int32_t storm_rollout_graph_create(storm_ctx ctx, const float *d_x0, const float *d_goal, float *d_cmd,
                                    int32_t iterations, int32_t shift, void *stream, storm_graph *out)

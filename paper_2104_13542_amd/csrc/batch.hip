@@ -19,7 +19,7 @@ struct storm_batch_s {
     int n_problems = 0;
     int n_cu = 0;
     std::vector<storm_ctx> ctxs;  // per-problem workspace, tables and policy state
-    RobotDev R8{}, R16{};          // robot constants with self-collision segments for 8 / 16 waves
+    RobotDev R{};                  // robot constants (problem 0's: every problem shares the robot)
     ProblemDev *d_probs = nullptr; // [P] descriptors
     int2 *d_items_cost = nullptr;  // work queue, most expensive tiles first
     int2 *d_items_plain = nullptr; // work queue in problem order
@@ -53,24 +53,6 @@ void free_batch(storm_batch b)
     b->allocs.clear();
 }
 
-// Robot constants of problem 0 with the self-collision split for `waves`.
-hipError_t robot_for_waves(storm_batch b, const storm_robot *robot, int waves, RobotDev &R)
-{
-    R = b->ctxs[0]->R;
-    std::vector<int> seg, off;
-    self_segments(robot, waves, seg, off);
-    int4 *d_seg = nullptr;
-    int32_t *d_off = nullptr;
-    hipError_t e = balloc(b, &d_seg, seg.size() / 4);
-    if (e == hipSuccess) e = balloc(b, &d_off, off.size());
-    if (e == hipSuccess && !seg.empty())
-        e = hipMemcpy(d_seg, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice);
-    R.self_seg = d_seg;
-    R.self_off = d_off;
-    return e;
-}
-
 // Estimated VALU work of one tile of problem p (the scheduler's sort key),
 // in instructions per wave: the per-point kinematics, the environment broad
 // phase (wave ball per sphere, one 64-obstacle chunk per pass) plus the few
@@ -88,7 +70,7 @@ double tile_cost(const ProblemDev &P, int n_spheres, int n_pairs)
 
 int32_t launch_batch_step(storm_batch b, const float *d_x0, const float *d_goal, hipStream_t s)
 {
-    const RobotDev &R = b->cfg.waves == 16 ? b->R16 : b->R8;
+    const RobotDev &R = b->R;
     const int2 *items = b->cfg.cost_order ? b->d_items_cost : b->d_items_plain;
     const hipError_t e =
         launch_rollout_batch(b->d_probs, items, b->n_items, b->d_next, R, d_x0, d_goal, b->cfg.waves, b->cfg.grid, s);
@@ -127,7 +109,7 @@ int32_t batch_graph(storm_batch b, const float *d_x0, const float *d_goal, float
         if (e == hipSuccess) e = launch_update_batch(b->d_probs, b->n_problems, d_cmd, last_shift, s);
     }
     if (e == hipSuccess && refine_iters > 0)
-        e = launch_refine_batch(b->d_probs, b->n_problems, b->d_adj_items, b->n_adj_items, b->R16, d_x0, d_goal,
+        e = launch_refine_batch(b->d_probs, b->n_problems, b->d_adj_items, b->n_adj_items, b->R, d_x0, d_goal,
                                 refine_iters, lr, d_cmd, shift != 0, s);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &graph);
@@ -195,8 +177,7 @@ int32_t storm_batch_init(storm_batch *out, int32_t n_problems, const storm_param
         b->n_cu = prop.multiProcessorCount;
         b->cfg.grid = 2 * b->n_cu;
     }
-    if (e == hipSuccess) e = robot_for_waves(b, robot, 8, b->R8);
-    if (e == hipSuccess) e = robot_for_waves(b, robot, 16, b->R16);
+    if (e == hipSuccess) b->R = b->ctxs[0]->R;
 
     // descriptors and the work queues
     std::vector<ProblemDev> probs(n_problems);
@@ -296,7 +277,7 @@ int32_t storm_batch_refine(storm_batch b, const float *d_x0, const float *d_goal
     if (!(lr >= 0.0f) || !isfinite(lr)) return STORM_E_PARAM;
     if (b->error != STORM_OK) return b->error;
     if (!b->differentiable) return STORM_E_UNSUPPORTED;
-    if (launch_refine_batch(b->d_probs, b->n_problems, b->d_adj_items, b->n_adj_items, b->R16, d_x0, d_goal,
+    if (launch_refine_batch(b->d_probs, b->n_problems, b->d_adj_items, b->n_adj_items, b->R, d_x0, d_goal,
                             iterations, lr, d_cmd, shift != 0, static_cast<hipStream_t>(stream)) != hipSuccess) {
         b->error = STORM_E_DEVICE;
         return STORM_E_DEVICE;

@@ -19,8 +19,9 @@
 //   C   waves 0..W-3  world centres of the body spheres to LDS
 //       wave W-2   manipulability (Eq. 12)
 //       wave W-1   pose (Eq. 9)
-//   D   all waves  environment (spheres x obstacles) and self-collision
-//                  (sphere pairs) split over waves
+//   D   all waves  environment (spheres x obstacles) split over waves, then
+//                  self-collision (sphere pairs) as items taken from a queue,
+//                  each behind a broad-phase test
 //   E   wave 0     weighted running cost (Eq. 15), horizon sum (Eq. 2) as a
 //                  segmented DPP scan
 // Obstacle, sphere and pair records are indexed by wave-uniform loop
@@ -173,6 +174,8 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     // used, as scalar loads, they would add a memory round trip to those
     // serial phases)
     __shared__ float s_par[kParCount];
+    __shared__ int s_self_next;  // head of the self-collision item queue (phase D)
+    if (wave == W - 1 && lane == kParCount) s_self_next = 0;
     if (wave == W - 1 && lane < kParCount) {
         const float wts[kParCount - 12] = {P.alpha_rot[0], P.alpha_rot[1], P.alpha_rot[2], P.alpha_pos[0],
                                            P.alpha_pos[1], P.alpha_pos[2], P.w_pos,        P.w_rot,
@@ -460,12 +463,30 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
         // slots of a short group repeat its last sphere against a threshold
         // of -1e30, and the round after the last partner of an odd count
         // repeats that partner.
-        const STORM_CONST_AS int32_t *segs = uniform_ptr(reinterpret_cast<const int32_t *>(R.self_seg));
-        const STORM_CONST_AS int32_t *off = uniform_ptr(R.self_off);
+        //
+        // Work comes as items (one group against the spheres of one partner
+        // body) from a queue in LDS, so that waves done early with the
+        // environment term take more.  Broad phase per item: one sphere of
+        // each side (the anchors) with the radius about it that holds all of
+        // that side's spheres; where the anchors are farther apart than the
+        // two radii at every lane, no pair of the item touches and the item
+        // is skipped (its penetrations are all negative: the maximum is the
+        // same).
+        const STORM_CONST_AS int32_t *items = uniform_ptr(R.self_items);
         const STORM_CONST_AS float *thr = uniform_ptr(R.self_thr);
-        const int g1 = off[wave + 1];
-        for (int g = off[wave]; g < g1; ++g) {
-            const int code = segs[4 * g], grp = segs[4 * g + 1], s_begin = segs[4 * g + 2], s_end = segs[4 * g + 3];
+        const int n_items = R.n_self_items;
+        for (;;) {
+            int g = 0;
+            if (lane == 0) g = atomicAdd(&s_self_next, 1);
+            g = __builtin_amdgcn_readfirstlane(g);
+            if (g >= n_items) break;
+            const STORM_CONST_AS int32_t *it = items + 8 * g;
+            const int code = it[0], grp = it[1], s_begin = it[2], s_end = it[3], at = it[4], as = it[5];
+            const float reach2 = __int_as_float(it[6]);
+            const float ax = s_cen[(at * 3 + 0) * kLanes + lane] - s_cen[(as * 3 + 0) * kLanes + lane];
+            const float ay = s_cen[(at * 3 + 1) * kLanes + lane] - s_cen[(as * 3 + 1) * kLanes + lane];
+            const float az = s_cen[(at * 3 + 2) * kLanes + lane] - s_cen[(as * 3 + 2) * kLanes + lane];
+            if (__builtin_amdgcn_ballot_w64(fmaf(ax, ax, fmaf(ay, ay, az * az)) < reach2) == 0) continue;
             const int t_first = code & 255, count = code >> 8;
             float mx[4], my[4], mz[4], nt[4];
 #pragma unroll

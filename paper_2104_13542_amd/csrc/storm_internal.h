@@ -87,12 +87,11 @@ struct ProblemDev {
 // Robot constants, passed by value (kernel-argument segment, wave-uniform).
 struct RobotDev {
     float ca[kFrames], sa[kFrames], a[kFrames], d[kFrames];  // DH: cos/sin alpha_{k-1}, a_{k-1}, d_k
-    int32_t n_spheres, n_pairs, pad0, pad1;
+    int32_t n_spheres, n_pairs, n_self_items, pad0;
     const float4 *sph_local;  // [S] body-frame centre (x, y, z), radius
     const int32_t *sph_body;  // [S] frame index 0..7 the sphere is attached to
     const float *self_thr;    // [groups][S][8] expanded pair test thresholds (4), contact distances (4)
-    const int4 *self_seg;     // self-collision items (t_first | count << 8, group, s_begin, s_end)
-    const int32_t *self_off;  // [W + 1] segment range of each wave of the rollout workgroup
+    const int32_t *self_items;  // [n_self_items][8] self-collision work items (self_segments)
 };
 
 // Wave-uniform reads through the constant address space: the backend turns
@@ -183,9 +182,9 @@ hipError_t launch_refine_batch(const ProblemDev *probs, int n_problems, const in
                                float *cmd, int shift, hipStream_t stream);
 hipError_t launch_fk(const RobotDev &R, const float *q, int n, float *pose, float *manip, hipStream_t stream);
 
-// Self-collision work split of the robot's sphere pairs over `waves`
-// wavefronts: segments (s, t_begin, t_end, 0) and per-wave offsets
-// off[0..waves]; returns the pair count.
+// Self-collision work items of the robot's sphere pairs, eight integers
+// each (the rollout's queue; defined with its layout in the interface unit);
+// returns the pair count.
 // Self-collision groups: the spheres of one body in runs of up to four,
 // (t_first, count), whose partners are the spheres s < s_end on bodies at
 // least two earlier in the chain.
@@ -193,7 +192,7 @@ struct SelfGroup {
     int t_first, count, s_end;
 };
 std::vector<SelfGroup> self_groups(const storm_robot *robot);
-int self_segments(const storm_robot *robot, int waves, std::vector<int> &seg, std::vector<int> &off);
+int self_segments(const storm_robot *robot, std::vector<int> &items);
 std::vector<float> self_thresholds(const storm_robot *robot, double reach);
 
 }  // namespace storm

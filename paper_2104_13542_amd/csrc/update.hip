@@ -74,6 +74,27 @@ __device__ __forceinline__ float wave_min(float x)
     return __int_as_float(ordered(__builtin_amdgcn_readlane(b, 63)));
 }
 
+// x moved into VGPRs at this point (a wave-uniform value the compiler
+// would otherwise keep, or reload, as a scalar).
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// The same for a pointer, kept a global-memory pointer so that accesses
+// through it stay global (not flat) instructions.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> global_in_vgpr(T *p)
+{
+    global_ptr<T> g = (global_ptr<T>)p;
+    asm volatile("" : "+v"(g));
+    return g;
+}
+
 // Minimum of v over the workgroup (all threads get it).
 __device__ __forceinline__ float block_min(float v, float *s_wave, int lane, int wave)
 {
@@ -113,7 +134,8 @@ __host__ __device__ inline int update_slots(int N, int H)
 template <int kSlots>
 __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, float *__restrict__ mean_out,
                                              float *__restrict__ sigma2_out, float *__restrict__ cmd, int shift,
-                                             const bool cov, UpdateLds &L)
+                                             const bool cov, const float alpha_mu, const float alpha_sigma,
+                                             const float sigma2_min, UpdateLds &L)
 {
     float *s_buf = L.buf;
     float *s_red = L.red;
@@ -155,11 +177,21 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             uu[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ub, t * 4 + k * stride, 0, 0));
     }
     const float mu = in_rows ? P.mean[h * kDof + j] : 0.0f;
-    // the tail's parameters, fetched now with the first loads (kernel
-    // arguments read where they are first used would add a memory round
-    // trip to the tail)
-    const float alpha_mu = P.alpha_mu, alpha_sigma = P.alpha_sigma, sigma2_min = P.sigma2_min;
-    asm volatile("" : : "s"(alpha_mu), "s"(alpha_sigma), "s"(sigma2_min));
+    // What the tail reads is fetched now, with the first loads, since each
+    // would add a memory round trip to the tail: the old variances and the
+    // noise counter through vector loads (waited for only where they are
+    // used); the scalars go into VGPRs, because the kernel runs at its SGPR
+    // limit and the compiler would otherwise reload each from the kernel
+    // arguments there, one scalar-memory round trip after another.
+    const float sig_old = cov ? (t < H ? vector_load_f32(P.sigma2 + t * kDof + j) : 0.0f) : vector_load_f32(P.sigma2 + j);
+    const float sig_init = cov && shift ? vector_load_f32(P.tables + kTabSig0 + j) : 0.0f;
+    const uint32_t step0 = vector_load_u32(P.step);
+    const global_ptr<float> mean_p = global_in_vgpr(P.mean), sigma2_p = global_in_vgpr(P.sigma2);
+    const global_ptr<float> cmd_p = global_in_vgpr(cmd), mean_out_p = global_in_vgpr(mean_out),
+                            sigma2_out_p = global_in_vgpr(sigma2_out);
+    const global_ptr<uint32_t> step_p = global_in_vgpr(P.step);
+    shift = in_vgpr(shift);
+    const float a_mu = in_vgpr(alpha_mu), a_sigma = in_vgpr(alpha_sigma), s2_min = in_vgpr(sigma2_min);
 
     float S0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
     int any_nonfinite = 0;
@@ -329,7 +361,7 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
             muo = s_mold[lane];
         }
         const float m1 = s1 * inv_S0, m2 = s2 * inv_S0;
-        const float delta = alpha_mu * m1;
+        const float delta = a_mu * m1;
         const float mu_new = ok ? muo + delta : muo;
         const float var = lane < H ? fmaxf(fmaf(delta, delta - 2.0f * m1, m2), 0.0f) : 0.0f;  // about mu'
         const float acc = wave_sum(var);
@@ -337,46 +369,52 @@ __device__ __forceinline__ void update_joint(const ProblemDev &P, const int j, f
         const float mu_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(mu_new), 0x130, 0xf, 0xf,
                                                                          true));  // wave_shl:1
         if (lane == 0) {
-            if (!cov) {
-                const float old = P.sigma2[j];
-                float s2n = old;
-                if (ok) s2n = fmaxf(fmaf(alpha_sigma, acc / (float)H - old, old), sigma2_min);
-                P.sigma2[j] = s2n;
-                if (sigma2_out) sigma2_out[j] = s2n;
-            }
-            cmd[j] = mu_new;
             if (j == 0) {
-                *P.step = *P.step + 1u;
+                // the increment here, not at the load (where it would wait for
+                // every load in flight), and before the other stores (whose
+                // completion a wait for the load would otherwise include)
+                uint32_t next = step0;
+                asm volatile("" : "+v"(next));
+                *step_p = next + 1u;
                 if (!ok) atomicOr(P.status, any_nonfinite ? STORM_FLAG_NONFINITE_COST : STORM_FLAG_ZERO_WEIGHT);
             }
+            if (!cov) {
+                float s2n = sig_old;
+                if (ok) s2n = fmaxf(fmaf(a_sigma, acc / (float)H - sig_old, sig_old), s2_min);
+                sigma2_p[j] = s2n;
+                if (sigma2_out_p) sigma2_out_p[j] = s2n;
+            }
+            cmd_p[j] = mu_new;
         }
         if (lane < H) {
-            if (mean_out) mean_out[lane * kDof + j] = mu_new;
-            P.mean[lane * kDof + j] = shift ? (lane + 1 < H ? mu_next : 0.0f) : mu_new;
+            if (mean_out_p) mean_out_p[lane * kDof + j] = mu_new;
+            mean_p[lane * kDof + j] = shift ? (lane + 1 < H ? mu_next : 0.0f) : mu_new;
         }
         if (cov) {
             // Eq. 5 per step: lane h updates sigma^2[h][j] from the variance at
             // step h; the shift moves it one step, sigma_init^2 appended
-            const float old = lane < H ? P.sigma2[lane * kDof + j] : 0.0f;
-            const float s2n = ok ? fmaxf(fmaf(alpha_sigma, var - old, old), sigma2_min) : old;
+            const float old = sig_old;  // sigma^2[lane][j] (0 past H)
+            const float s2n = ok ? fmaxf(fmaf(a_sigma, var - old, old), s2_min) : old;
             const float s2_next = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s2n), 0x130, 0xf, 0xf,
                                                                              true));  // wave_shl:1
             if (lane < H) {
-                if (sigma2_out) sigma2_out[lane * kDof + j] = s2n;
-                P.sigma2[lane * kDof + j] = shift ? (lane + 1 < H ? s2_next : P.tables[kTabSig0 + j]) : s2n;
+                if (sigma2_out_p) sigma2_out_p[lane * kDof + j] = s2n;
+                sigma2_p[lane * kDof + j] = shift ? (lane + 1 < H ? s2_next : sig_init) : s2n;
             }
         }
     }
 }
 
-// The fields the first loads depend on come first, as scalar arguments, so
-// that they are preloaded into SGPRs; the rest of the problem follows in P.
-// kCov: one variance per (step, joint) instead of one per joint.
+// The fields the first loads depend on, and the scalars of the tail, come
+// first, as scalar arguments, so that they are preloaded into SGPRs (16
+// dwords); the rest of the problem follows in P.  kCov: one variance per
+// (step, joint) instead of one per joint.
 template <bool kCov, int kSlots>
 __global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, float *mean, float *sigma2, int32_t N,
-                                                          int32_t H, float beta, ProblemDev P,
+                                                          int32_t H, float beta, float alpha_mu, float alpha_sigma,
+                                                          float sigma2_min, int shift, ProblemDev P,
                                                           float *__restrict__ mean_out, float *__restrict__ sigma2_out,
-                                                          float *__restrict__ cmd, int shift)
+                                                          float *__restrict__ cmd)
 {
     __shared__ UpdateLds L;
     ProblemDev Q = P;
@@ -387,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void update_kernel(float *C, float *u, fl
     Q.N = N;
     Q.H = H;
     Q.beta = beta;
-    update_joint<kSlots>(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift, kCov, L);
+    update_joint<kSlots>(Q, blockIdx.x, mean_out, sigma2_out, cmd, shift, kCov, alpha_mu, alpha_sigma, sigma2_min, L);
 }
 
 // Workgroup (p, j) of a batch; commands go to cmd[p][7].
@@ -400,11 +438,14 @@ __global__ __launch_bounds__(kThreads) void update_batch_kernel(const ProblemDev
     const int slots = update_slots(P.N, P.H);
     float *c = cmd + (size_t)p * kDof;
     if (slots == 8)
-        update_joint<8>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, L);
+        update_joint<8>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, P.alpha_mu, P.alpha_sigma, P.sigma2_min,
+                          L);
     else if (slots == 16)
-        update_joint<16>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, L);
+        update_joint<16>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, P.alpha_mu, P.alpha_sigma, P.sigma2_min,
+                          L);
     else
-        update_joint<32>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, L);
+        update_joint<32>(P, j, nullptr, nullptr, c, shift, P.cov_step != 0u, P.alpha_mu, P.alpha_sigma, P.sigma2_min,
+                          L);
 }
 
 }  // namespace
@@ -426,8 +467,8 @@ hipError_t launch_update(const ProblemDev &P, float *mean_out, float *sigma2_out
                              : (slots == 8    ? update_kernel<false, 8>
                                 : slots == 16 ? update_kernel<false, 16>
                                               : update_kernel<false, 32>);
-    hipLaunchKernelGGL(kernel, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2, P.N, P.H, P.beta, P,
-                       mean_out, sigma2_out, cmd, shift);
+    hipLaunchKernelGGL(kernel, dim3(kDof), dim3(kThreads), 0, stream, P.C, P.u, P.mean, P.sigma2, P.N, P.H, P.beta,
+                       P.alpha_mu, P.alpha_sigma, P.sigma2_min, shift, P, mean_out, sigma2_out, cmd);
     return hipGetLastError();
 }
 

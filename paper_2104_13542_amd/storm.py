@@ -88,7 +88,7 @@ EXPORTS = (
     "storm_batch_set_config", "storm_batch_get_config", "storm_batch_autotune", "storm_batch_get_state",
     "storm_batch_set_state", "storm_batch_costs", "storm_batch_destroy", "storm_plant_step",
     "storm_rollout_grad", "storm_rollout_grad_noalloc", "storm_rollout_refine", "storm_rollout_graph_create_refine",
-    "storm_batch_refine", "storm_batch_graph_create_refine", "storm_rollout_set_ball",
+    "storm_batch_refine", "storm_batch_graph_create_refine", "storm_rollout_set_ball", "storm_rollout_control",
 )
 
 
@@ -111,6 +111,7 @@ def lib():
                                          ctypes.POINTER(storm_robot), ctypes.POINTER(storm_scene), vp]
         L.storm_rollout_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(storm_debug), vp, vp]
         L.storm_rollout_update.argtypes = [vp, vp, vp, vp, i32, vp]
+        L.storm_rollout_control.argtypes = [vp, vp, vp, vp, i32, i32, vp]
         L.storm_rollout_set_ball.argtypes = [vp, vp, vp]
         L.storm_rollout_destroy.argtypes = [vp]
         L.storm_rollout_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
@@ -162,7 +163,8 @@ def _ptr(t):
 
 
 def _stream():
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    # the raw handle of the current stream, without building a Stream object
+    return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device())
 
 
 def make_params(p: "inputs.Params"):
@@ -312,6 +314,13 @@ class Rollout:
         _check(lib().storm_rollout_update(self._h, _ptr(mean), _ptr(sigma2), _ptr(cmd), int(bool(shift)),
                                           _stream()), "storm_rollout_update")
         return cmd, mean, sigma2
+
+    def control(self, x0, goal, cmd, iterations=1, shift=True):
+        """One whole control step (Alg. 1) in one call: `iterations` rounds
+        of step + update, the shift after the last; writes cmd [7]."""
+        _check(lib().storm_rollout_control(self._h, x0.data_ptr(), goal.data_ptr(), cmd.data_ptr(), int(iterations),
+                                           int(bool(shift)), _stream()), "storm_rollout_control")
+        return cmd
 
     # -- state -------------------------------------------------------------
     def get_state(self):

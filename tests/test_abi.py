@@ -196,6 +196,7 @@ def test_call_validation_before_device(storm):
     E = storm
     assert L.storm_rollout_step(None, None, None, None, None, None, None) == E.STORM_E_NULL
     assert L.storm_rollout_update(None, None, None, None, 1, None) == E.STORM_E_NULL
+    assert L.storm_rollout_control(None, None, None, None, 1, 1, None) == E.STORM_E_NULL
     assert L.storm_rollout_destroy(None) == E.STORM_OK
     assert L.storm_rollout_status(None, None, None) == E.STORM_E_NULL
     assert L.storm_rollout_get_state(None, None, None, None, None) == E.STORM_E_NULL

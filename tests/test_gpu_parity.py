@@ -332,6 +332,11 @@ def test_abi_errors_on_gpu():
         with pytest.raises(storm.StormError) as e:
             r.update()
         assert e.value.code == storm.STORM_E_STATE
+        cmd = torch.zeros(7, dtype=torch.float32, device="cuda")
+        goal = torch.zeros(12, dtype=torch.float32, device="cuda")
+        with pytest.raises(storm.StormError) as e:
+            r.control(r.x0, goal, cmd, iterations=0)
+        assert e.value.code == storm.STORM_E_RANGE
     finally:
         r.close()
 
@@ -340,34 +345,46 @@ def test_abi_errors_on_gpu():
 def test_graph_replays_match_eager(iterations):
     """A captured control step (K iterations of step + update, shift on the
     last) replayed several times, with eager work and host synchronisation
-    between the replays, equals the eager calls bit for bit at every replay."""
+    between the replays, equals the eager calls bit for bit at every replay;
+    so does the one-call eager control step (storm_rollout_control)."""
     from paper_2104_13542_amd import storm
 
     prob = inputs.config2(7, n_particles=300, horizon=30)
     eager = storm.Rollout(prob)
     graphed = storm.Rollout(prob)
+    control = storm.Rollout(prob)
     try:
         x0 = eager.x0.clone()
         goal = torch.tensor([1, 0, 0, 0, -1, 0, 0, 0, -1, 0.45, 0.1, 0.5], dtype=torch.float32, device="cuda")
         cmd_g = torch.zeros(7, dtype=torch.float32, device="cuda")
+        cmd_c = torch.zeros(7, dtype=torch.float32, device="cuda")
         g = graphed.graph(x0, goal, cmd_g, iterations=iterations, shift=True)
         for rep in range(4):
             for k in range(iterations):
                 eager.step(goal, x0=x0)
                 cmd_e, _, _ = eager.update(shift=(k == iterations - 1))
             g.launch()
+            control.control(x0, goal, cmd_c, iterations=iterations, shift=True)
             torch.cuda.synchronize()
             assert torch.equal(cmd_e, cmd_g), rep
+            assert torch.equal(cmd_e, cmd_c), rep
             me, se, ste = eager.get_state()
             mg, sg, stg = graphed.get_state()
+            mc, sc, stc = control.get_state()
             assert np.array_equal(me, mg) and np.array_equal(se, sg) and ste == stg == iterations * (rep + 1)
+            assert np.array_equal(me, mc) and np.array_equal(se, sc) and stc == ste
             # eager work on the graphed context's inputs between replays
             x0.add_(0.001)
             torch.cuda.synchronize()
         g.close()
+        # the control step leaves no step pending
+        with pytest.raises(storm.StormError) as e:
+            control.update()
+        assert e.value.code == storm.STORM_E_STATE
     finally:
         eager.close()
         graphed.close()
+        control.close()
 
 
 @pytest.mark.parametrize("N,H,beta", [(5000, 16, 1e6), (700, 30, 1e6), (3000, 8, 50.0), (2500, 30, 0.1),
