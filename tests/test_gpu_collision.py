@@ -160,3 +160,40 @@ def test_self_collision_odd_groups(oracle_lib, q0):
     g, ro, up, o, _ = run_pair(prob, oracle_lib)
     _config2_checks(g, ro, o, prob)
     assert np.mean(ro["terms"][..., 6] > 0) > 0.05, "the start should self-collide"
+
+
+@pytest.mark.parametrize("q_near", [[0.794, -0.812, -2.66, -3.022, 1.815, 3.424, 0.618],
+                                    [1.635, -1.566, 2.819, -2.644, 0.923, 0.507, -0.996],
+                                    [1.638, 1.227, 0.041, -3.039, 0.047, 1.228, 0.314]])
+def test_self_collision_grazing(oracle_lib, q_near):
+    """Start states at the edge of self-contact: on the segment from the
+    ready configuration (apart) to a folded one (penetrating), bisection with
+    the oracle's signed self distance finds the point of 0.2 mm penetration,
+    and small noise (sigma 0.01 rad) keeps the rollouts within millimetres of
+    contact on both sides.  The self-collision term, whose pair work the
+    kernel culls per (group, body) item, must equal the oracle's (which tests
+    every pair) at every point, penetrations of micrometres included."""
+    prob = inputs.config2(29, n_particles=128, horizon=30, n_obs_spheres=0, n_obs_cuboids=0)
+    o = oracle_lib.Oracle(prob)
+    qa, qb = inputs.PANDA_READY.copy(), np.array(q_near)
+    assert o.self_distance(qa) < 0.0 < o.self_distance(qb)
+    lo, hi = 0.0, 1.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        if o.self_distance(qa + mid * (qb - qa)) < 2e-4:
+            lo = mid
+        else:
+            hi = mid
+    prob.q0 = qa + hi * (qb - qa)
+    prob.params.sigma_init = np.full(7, 0.01)
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    s_g, s_o = g["terms"][..., 6], ro["terms"][..., 6]
+    touching = s_o > 0.0
+    assert 0.5 < touching.mean() < 0.95, "the rollouts should stay near contact on both sides"
+    assert np.mean(touching & (s_o < 1e-3)) > 0.3, "many penetrations below a millimetre"
+    # FP32 kinematics and distances err by a fraction of a micrometre; a pair the
+    # broad phase wrongly skipped would lose its whole penetration (up to
+    # millimetres here)
+    err = np.abs(s_g - s_o)
+    print("grazing self contact: %.0f%% of states touching, max |error| %.2g m" % (100 * touching.mean(), err.max()))
+    assert np.max(err) <= 2e-6, "max self-term error %.3g m" % np.max(err)  # measured 1.5e-7
