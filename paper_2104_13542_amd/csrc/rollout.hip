@@ -60,6 +60,11 @@ __device__ __forceinline__ float wave_max_nonneg(float x)
     return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)b, 63));
 }
 
+// Candidates of one 64-obstacle chunk above which the environment broad phase
+// refines the wave's ball into eight balls of eight lanes (measured: the
+// refinement pays for itself from about this many candidates on).
+constexpr int kFineCandidates = 8;
+
 // LDS copy of the goal (R row-major, p) and the cost weights, by index.
 constexpr int kParArot = 12, kParApos = 15, kParW = 18, kParKm = 25, kParCount = 26;
 
@@ -406,6 +411,42 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
                 const float reach = bd.w + rad_rs;
                 uint64_t cand = cull ? __builtin_amdgcn_ballot_w64(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < reach * reach)
                                      : __builtin_amdgcn_ballot_w64(o0 + lane < nobs);
+                if (cull && __builtin_popcountll(cand) > kFineCandidates) {
+                    // Many candidates: trajectories that sweep far over the
+                    // horizon make the wave's ball large.  Eight balls of
+                    // eight lanes instead (centre: the group's first lane;
+                    // radius: the group's largest distance to it); an
+                    // obstacle stays a candidate where it reaches one of them.
+                    // The centres come through swizzles within each 32-lane
+                    // half, the radii through DPP maxima within each group.
+                    float gx[8], gy[8], gz[8], gr[8];
+                    {
+                        const float cx = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x18));
+                        const float cy = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(y), 0x18));
+                        const float cz = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(z), 0x18));
+                        const float bx = x - cx, by = y - cy, bz = z - cz;
+                        uint32_t u = __float_as_uint(fmaf(bx, bx, fmaf(by, by, bz * bz)));
+                        u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xb1, 0xf, 0xf, false));
+                        u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4e, 0xf, 0xf, false));
+                        u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x141, 0xf, 0xf, false));
+                        const float r8 = fast_sqrt(__uint_as_float(u)) + rs;
+#pragma unroll
+                        for (int g = 0; g < 8; ++g) {
+                            gx[g] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 8 * g));
+                            gy[g] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 8 * g));
+                            gz[g] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), 8 * g));
+                            gr[g] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r8), 8 * g));
+                        }
+                    }
+                    bool hit = false;
+#pragma unroll
+                    for (int g = 0; g < 8; ++g) {
+                        const float ex = bd.x - gx[g], ey = bd.y - gy[g], ez = bd.z - gz[g];
+                        const float rg = bd.w + gr[g];
+                        hit |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rg * rg;
+                    }
+                    cand &= __builtin_amdgcn_ballot_w64(hit);
+                }
                 // Narrow phase over the candidates, in increasing obstacle
                 // order (the maximum does not depend on the order).
                 while (cand != 0) {

@@ -197,3 +197,22 @@ def test_self_collision_grazing(oracle_lib, q_near):
     err = np.abs(s_g - s_o)
     print("grazing self contact: %.0f%% of states touching, max |error| %.2g m" % (100 * touching.mean(), err.max()))
     assert np.max(err) <= 2e-6, "max self-term error %.3g m" % np.max(err)  # measured 1.5e-7
+
+
+def test_sweeping_trajectories_dense_scene(oracle_lib):
+    """Rollouts that sweep far over a long horizon (start velocity 2 rad/s,
+    H = 64, 100 obstacles in a metre cube): the wave's bounding ball of a
+    body sphere then meets most obstacles, so the broad phase refines it into
+    eight balls of eight lanes.  Every term must still equal the oracle's."""
+    prob = inputs.config5_problem(0)
+    prob.params.n_particles, prob.params.n_halton = 96, 48
+    prob.params.sigma_init = np.full(7, 0.03)
+    v = np.random.default_rng(77).normal(size=7)
+    prob.v0 = 2.0 * v / np.linalg.norm(v)
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    _config2_checks(g, ro, o, prob)
+    e_g, e_o = g["terms"][..., 7], ro["terms"][..., 7]
+    print("sweeping: %.0f%% of states touch an obstacle, max |env error| %.2g m" %
+          (100 * np.mean(e_o > 0), np.max(np.abs(e_g - e_o))))
+    assert np.mean(e_o > 0) > 0.2, "the sweeping rollouts should meet obstacles"
+    assert np.max(np.abs(e_g - e_o)) <= 2e-5 * max(1.0, float(np.max(e_o)))
