@@ -211,7 +211,9 @@ int32_t storm_rollout_step(storm_ctx ctx, const float *d_x0, const float *d_goal
                            const storm_debug *dbg, float *d_C, void *stream);
 
 /* Policy update (Alg. 1 update_distribution, Eq. 4-6) from the last step,
- * then next_command: d_cmd [7] = updated mu_0.  d_mean [H][7] and d_sigma2
+ * then next_command: d_cmd [7] = updated mu_0, written by the update kernel
+ * to device memory or to pinned host memory (hipHostMalloc; readable on the
+ * host once `stream` has synchronised, with no copy).  d_mean [H][7] and d_sigma2
  * ([7], or [H][7] with cov_per_step; nullable) receive the updated
  * (unshifted) mean and variance.  With shift != 0 the stored mean is shifted
  * one step and a zero mean appended (the warm start of the next control
@@ -290,7 +292,8 @@ int32_t storm_rollout_refine(storm_ctx ctx, const float *d_x0, const float *d_go
 /* One whole control step of Alg. 1 in a single call, launched eagerly:
  * `iterations` (K >= 1) rounds of storm_rollout_step + storm_rollout_update
  * on `stream`, the shift applied after the last round only, reading d_x0
- * [3][7] and d_goal [12] and writing d_cmd [7] (device memory).  Enqueues
+ * [3][7] and d_goal [12] (device memory) and writing d_cmd [7] (device or
+ * pinned host memory, as in storm_rollout_update).  Enqueues
  * exactly the kernels a graph of storm_rollout_graph_create would, with one
  * crossing of the interface per control step instead of 2K, and leaves no
  * step pending.  Allocates nothing.  Errors: E_NULL, E_RANGE
@@ -304,7 +307,8 @@ typedef struct storm_graph_s *storm_graph;
 /* Capture one whole control step of Alg. 1 into a HIP graph: `iterations`
  * (K >= 1) rounds of storm_rollout_step + storm_rollout_update, the shift
  * applied after the last round only, reading d_x0 [3][7] and d_goal [12]
- * and writing d_cmd [7] (device buffers whose addresses are baked into the
+ * and writing d_cmd [7] (device buffers, d_cmd also pinned host memory as
+ * in storm_rollout_update, whose addresses are baked into the
  * graph: refresh their contents before each launch).  `stream` is used for
  * the capture (NULL: a private stream); the context must not be used on
  * any other stream during the call.  Each launch advances the sampling step

@@ -387,6 +387,45 @@ def test_graph_replays_match_eager(iterations):
         control.close()
 
 
+def test_command_to_pinned_host_memory():
+    """The update kernel writes the command straight into pinned host memory
+    (readable after the stream synchronises, no copy): eager control steps
+    and graph replays give the same commands, bit for bit, as the same calls
+    writing device memory."""
+    from paper_2104_13542_amd import storm
+
+    prob = inputs.config2(11, n_particles=200, horizon=30)
+    prob.params.grad_mask = inputs.COST_POSE | inputs.COST_JOINT
+    modes = ("device", "pinned", "graph_device", "graph_pinned", "refine_device", "refine_pinned")
+    ctx = {m: storm.Rollout(prob) for m in modes}
+    try:
+        x0 = ctx["device"].x0.clone()
+        goal = torch.tensor([1, 0, 0, 0, -1, 0, 0, 0, -1, 0.45, 0.1, 0.5], dtype=torch.float32, device="cuda")
+        cmd = {m: (torch.zeros(7, dtype=torch.float32, pin_memory=True) if "pinned" in m
+                   else torch.zeros(7, dtype=torch.float32, device="cuda")) for m in ctx}
+        graphs = {m: ctx[m].graph(x0, goal, cmd[m], iterations=1, shift=True) for m in ("graph_device", "graph_pinned")}
+        # the refinement graph writes the command from the Adam kernel
+        graphs.update({m: ctx[m].graph(x0, goal, cmd[m], iterations=1, shift=True, refine_iters=2, lr=0.05)
+                       for m in ("refine_device", "refine_pinned")})
+        for step in range(5):
+            ctx["device"].control(x0, goal, cmd["device"])
+            ctx["pinned"].control(x0, goal, cmd["pinned"])
+            for m in graphs:
+                graphs[m].launch()
+            torch.cuda.synchronize()
+            ref = cmd["device"].cpu()
+            assert torch.equal(ref, cmd["pinned"]), step
+            assert torch.equal(ref, cmd["graph_device"].cpu()), step
+            assert torch.equal(ref, cmd["graph_pinned"]), step
+            assert torch.equal(cmd["refine_device"].cpu(), cmd["refine_pinned"]), step
+            x0.add_(0.002)
+        for g in graphs.values():
+            g.close()
+    finally:
+        for r in ctx.values():
+            r.close()
+
+
 @pytest.mark.parametrize("N,H,beta", [(5000, 16, 1e6), (700, 30, 1e6), (3000, 8, 50.0), (2500, 30, 0.1),
                                       (1088, 30, 1e6), (512, 64, 0.1), (2048, 16, 1e6)])
 def test_update_dense_and_sparse_paths(oracle_lib, N, H, beta):
