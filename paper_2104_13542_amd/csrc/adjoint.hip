@@ -275,8 +275,11 @@ __global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_kernel(const float 
     adjoint_chunk(Q, R, blockIdx.x, x0, goal, mean, noise);
 }
 
-// Batched form: workgroup k takes chunk items[k] = (problem, chunk).
-__global__ __launch_bounds__(kAdjWaves *kLanes) void adjoint_batch_kernel(const ProblemDev *__restrict__ probs,
+// Batched form: workgroup k takes chunk items[k] = (problem, chunk).  At
+// most 80 VGPRs (six waves per SIMD), so that three workgroups share a CU
+// (3 x 41.5 KB of LDS): the third one's serial phases fill the others'
+// stalls (large workload: 2.2 -> 1.65 ms per launch; 88 VGPRs unbounded).
+__global__ __launch_bounds__(kAdjWaves *kLanes) __attribute__((amdgpu_waves_per_eu(6))) void adjoint_batch_kernel(const ProblemDev *__restrict__ probs,
                                                                           const int2 *__restrict__ items,
                                                                           RobotDev R, const float *__restrict__ x0s,
                                                                           const float *__restrict__ goals)
