@@ -232,6 +232,35 @@ def cpu_baseline(seed, budget_s):
         out[name] = {"value": pr.params.n_particles * pr.params.horizon * steps / el, "unit": "rollout-steps/s",
                      "cores": 1, "ms_per_step": 1e3 * el / steps,
                      "sample": "%d whole steps, %.1f s, 1 thread" % (steps, el)}
+    # the batched workload: a sample of its problems, whole steps of each on
+    # one thread; the rate extrapolated to all 256 problems per control step
+    work, secs, n_steps = 0, 0.0, 0
+    sample = [inputs.config3_problem(k) for k in range(8)]
+    for pr in sample:
+        steps, el = _oracle_serial(pr, 0.025 * budget_s)
+        work += pr.params.n_particles * pr.params.horizon * steps
+        secs += el
+        n_steps += steps
+    rate = work / secs
+    total = sum(inputs.config3_problem(k).params.n_particles * inputs.config3_problem(k).params.horizon
+                for k in range(256))
+    out["config3_256_problems"] = {
+        "value": rate, "unit": "rollout-steps/s", "cores": 1,
+        "ms_per_step_extrapolated": 1e3 * total / rate,
+        "sample": "%d whole steps over problems 0-7 of the 256, %.1f s, 1 thread; the control step of all 256 "
+                  "problems extrapolated from the rate (%d particle-steps)" % (n_steps, secs, total)}
+    # the large workload: one problem's MPPI step (noise, rollout, update; no
+    # adjoint or Adam step) at 64 of its 4096 particles, on one thread
+    pr = inputs.config5_problem(0)
+    pr.params.n_particles, pr.params.n_halton = 64, 32
+    steps, el = _oracle_serial(pr, 0.2 * budget_s)
+    rate = 64 * pr.params.horizon * steps / el
+    out["config5_64x4096x64"] = {
+        "value": rate, "unit": "rollout-steps/s", "cores": 1,
+        "ms_per_step_extrapolated": 1e3 * 64 * 4096 * 64 / rate,
+        "sample": "%d MPPI steps (no adjoint or Adam step) of problem 0 at 64 of its 4096 particles, H=64, "
+                  "100 obstacles, %.1f s, 1 thread; the control step of 64 problems x 4096 particles "
+                  "extrapolated from the rate" % (steps, el)}
     return out
 
 
