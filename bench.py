@@ -547,7 +547,7 @@ def differentiable_bench(steps, latency_steps, warmup):
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
 
-    def timed(g):
+    def timed(g, closed_loop=False):
         for _ in range(warmup):
             g.launch()
         torch.cuda.synchronize()
@@ -563,10 +563,19 @@ def differentiable_bench(steps, latency_steps, warmup):
             g.launch()
             torch.cuda.current_stream().synchronize()
             lat.append((time.perf_counter() - t0) * 1e3)
+            if closed_loop:
+                # the command applied to the plant (0.01 s), after the timing
+                storm.plant_step(x0.reshape(1, 21), cmd.reshape(1, 7), 0.01)
         return ms, np.array(lat)
 
+    def position_error():
+        pose = storm.fk(x0[:7].reshape(1, 7).contiguous())[0][0]
+        return float(torch.linalg.norm(pose[9:12] - goal[9:12]))
+
     plain_ms, plain_lat = timed(g_plain)
-    ref_ms, ref_lat = timed(g_ref)
+    err_start = position_error()
+    ref_ms, ref_lat = timed(g_ref, closed_loop=True)
+    err_end = position_error()
     g_plain.close()
     g_ref.close()
 
@@ -596,7 +605,9 @@ def differentiable_bench(steps, latency_steps, warmup):
         "workload": "N=%d, H=%d, pose + joint-limit costs, dt 0.02; refinement: 3 Adam steps, lr 0.05" % (N, H),
         "refine_step": {"ms_per_step": ref_ms, "rollout_steps_per_s": N * H * 1e3 / ref_ms,
                         "latency_ms": {"p50": float(np.percentile(ref_lat, 50)),
-                                       "p99": float(np.percentile(ref_lat, 99)), "steps": int(len(ref_lat))}},
+                                       "p99": float(np.percentile(ref_lat, 99)), "steps": int(len(ref_lat)),
+                                       "closed_loop": True},
+                        "position_error_m": {"start": err_start, "after_closed_loop": err_end}},
         "plain_step": {"ms_per_step": plain_ms, "rollout_steps_per_s": N * H * 1e3 / plain_ms,
                        "latency_ms": {"p50": float(np.percentile(plain_lat, 50)),
                                       "p99": float(np.percentile(plain_lat, 99)), "steps": int(len(plain_lat))}},

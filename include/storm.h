@@ -416,7 +416,8 @@ int32_t storm_batch_costs(storm_batch b, int32_t problem, float *h_C, void *stre
 /* Free a batch (NULL is a no-op). */
 int32_t storm_batch_destroy(storm_batch b);
 
-/* Closed-loop plant used by the benchmarks: applies command d_cmd [n][7] to
+/* Closed-loop plant used by the benchmarks: applies command d_cmd [n][7]
+ * (device or pinned host memory) to
  * states d_x [n][3][7] for `dt` seconds with the integrator of Eq. 7
  * (v += dt u, q += dt v, a = u).  Errors: E_NULL, E_RANGE (n < 0), E_PARAM
  * (dt <= 0), E_DEVICE. */
