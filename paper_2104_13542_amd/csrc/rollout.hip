@@ -377,10 +377,11 @@ __device__ __forceinline__ void rollout_tile(const ProblemDev &P, const RobotDev
     __syncthreads();
 
     // ---- D: collision terms ---------------------------------------------------
-    // Both collision loops test four records per round: the squared distance
-    // of each is compared with its squared contact distance, the four lane
-    // masks are OR-ed in SGPRs and the square roots (penetration depths) run
-    // only when some lane of the wave touches one of them.
+    // Environment (spheres round robin over the waves), then self-collision
+    // (items from a queue).  Both cull first at the level of the whole wave
+    // and take exact distances (and their square roots) only where some lane
+    // of the wave may touch; a culled record touches at no lane, so the
+    // terms equal the brute-force ones.
     float env = 0.0f, selfpen = 0.0f;
     if (mask & STORM_COST_ENV) {
         const STORM_CONST_AS float *sob = uniform_ptr(reinterpret_cast<const float *>(P.sph_obs));
