@@ -89,6 +89,8 @@ def lib():
         L.oracle_bspline_basis.argtypes = [ctypes.c_int, ctypes.c_int, _PD]
         L.oracle_halton_noise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _PD]
         L.oracle_noise.argtypes = [ctypes.POINTER(OracleParams), ctypes.c_uint32, _PD]
+        L.oracle_noise_particles.argtypes = [ctypes.POINTER(OracleParams), ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _PD]
         L.oracle_integrate.argtypes = [ctypes.c_int, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
         L.oracle_fk.argtypes = [_PD, _PD, _PD]
         L.oracle_jacobian.argtypes = [_PD, _PD]
@@ -322,6 +324,15 @@ class Oracle:
         eps = np.zeros((self.N, self.H, DOF))
         if lib().oracle_noise(ctypes.byref(self.params), int(step), _d(eps)) != 0:
             raise RuntimeError("oracle_noise failed")
+        return eps
+
+    def noise_particles(self, step, idx):
+        """The rows of noise(step) for the particles idx only: [len(idx)][H][7]."""
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        eps = np.zeros((len(idx), self.H, DOF))
+        if lib().oracle_noise_particles(ctypes.byref(self.params), int(step),
+                                        idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(idx), _d(eps)) != 0:
+            raise RuntimeError("oracle_noise_particles failed")
         return eps
 
     def _sig(self, sigma):

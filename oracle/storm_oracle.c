@@ -234,35 +234,35 @@ int oracle_bspline_basis(int H, int K, double *B)
 
 static const uint32_t kPrimes[DOF] = {2, 3, 5, 7, 11, 13, 17};
 
-/* Halton noise table eps[i][h][j], i < n_halton: Halton point index
- * 1 + i K + k in dimension j (prime p_j), mapped to a standard normal by the
- * inverse CDF, then smoothed by the B-spline basis over k.  Index 0 (the
- * origin) is skipped.  Drawn once; the same table is used at every step. */
+/* Halton noise of particle i, row[h][j]: Halton point index 1 + i K + k in
+ * dimension j (prime p_j), mapped to a standard normal by the inverse CDF,
+ * then smoothed by the B-spline basis B [H][K] over k.  Index 0 (the origin)
+ * is skipped.  Z is scratch of K x 7. */
+static void halton_row(int i, int H, int K, const double *B, double *Z, double *row)
+{
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < DOF; ++j)
+            Z[k * DOF + j] = oracle_ndtri(oracle_radical_inverse((uint64_t)1 + (uint64_t)i * K + k, kPrimes[j]));
+    for (int h = 0; h < H; ++h)
+        for (int j = 0; j < DOF; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < K; ++k) acc += B[h * K + k] * Z[k * DOF + j];
+            row[(size_t)h * DOF + j] = acc;
+        }
+}
+
+/* Halton noise table eps[i][h][j], i < n_halton (halton_row of every
+ * particle).  Drawn once; the same table is used at every step. */
 int oracle_halton_noise(int n_halton, int H, int K, double *eps)
 {
     double *B = (double *)malloc(sizeof(double) * (size_t)H * (size_t)K);
     double *Z = (double *)malloc(sizeof(double) * (size_t)K * DOF);
-    if (!B || !Z) {
+    if (!B || !Z || oracle_bspline_basis(H, K, B) != 0) {
         free(B);
         free(Z);
         return -1;
     }
-    if (oracle_bspline_basis(H, K, B) != 0) {
-        free(B);
-        free(Z);
-        return -1;
-    }
-    for (int i = 0; i < n_halton; ++i) {
-        for (int k = 0; k < K; ++k)
-            for (int j = 0; j < DOF; ++j)
-                Z[k * DOF + j] = oracle_ndtri(oracle_radical_inverse((uint64_t)1 + (uint64_t)i * K + k, kPrimes[j]));
-        for (int h = 0; h < H; ++h)
-            for (int j = 0; j < DOF; ++j) {
-                double acc = 0.0;
-                for (int k = 0; k < K; ++k) acc += B[h * K + k] * Z[k * DOF + j];
-                eps[((size_t)i * H + h) * DOF + j] = acc;
-            }
-    }
+    for (int i = 0; i < n_halton; ++i) halton_row(i, H, K, B, Z, eps + (size_t)i * H * DOF);
     free(B);
     free(Z);
     return 0;
@@ -305,6 +305,43 @@ int oracle_noise(const oracle_params *p, uint32_t step, double *eps)
         for (int i = p->n_halton; i < N - p->n_null; ++i)
             for (int j = 0; j < DOF; ++j) comb_filter(H, p->comb, eps + (size_t)i * H * DOF + j);
     return 0;
+}
+
+/* The rows of oracle_noise for the particles idx[0 .. n_idx) only (any order,
+ * each in 0 .. N-1): eps[m][H][7] is particle idx[m]'s noise, so that a few
+ * particles of a large problem can be checked without the whole tensor. */
+int oracle_noise_particles(const oracle_params *p, uint32_t step, const int32_t *idx, int n_idx, double *eps)
+{
+    int N = p->n, H = p->h, K = p->n_knots;
+    double *B = NULL, *Z = NULL;
+    if (p->n_halton > 0) {
+        B = (double *)malloc(sizeof(double) * (size_t)H * (size_t)K);
+        Z = (double *)malloc(sizeof(double) * (size_t)K * DOF);
+        if (!B || !Z || oracle_bspline_basis(H, K, B) != 0) {
+            free(B);
+            free(Z);
+            return -1;
+        }
+    }
+    int rc = 0;
+    for (int m = 0; m < n_idx && rc == 0; ++m) {
+        const int i = idx[m];
+        double *row = eps + (size_t)m * H * DOF;
+        if (i < 0 || i >= N) {
+            rc = -1;
+        } else if (i < p->n_halton) {
+            halton_row(i, H, K, B, Z, row);
+        } else if (i >= N - p->n_null) {
+            for (int k = 0; k < H * DOF; ++k) row[k] = 0.0;
+        } else {
+            for (int h = 0; h < H; ++h) oracle_gauss7(p->seed, step, (uint32_t)i, (uint32_t)h, row + (size_t)h * DOF);
+            if (p->comb_filter)
+                for (int j = 0; j < DOF; ++j) comb_filter(H, p->comb, row + j);
+        }
+    }
+    free(B);
+    free(Z);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -155,6 +155,24 @@ def test_noise_layout(oracle_lib):
     np.testing.assert_allclose(eps[12, 4], oracle_lib.gauss7(prob.params.seed, 5, 12, 4), atol=0)
 
 
+@pytest.mark.parametrize("comb", [0, 1])
+def test_noise_of_selected_particles(oracle_lib, comb):
+    """noise_particles gives particle i the row noise() gives it, for every
+    kind (Halton, Gaussian with or without the comb filter, null), in any
+    order, and rejects an index outside 0 .. N-1."""
+    prob = inputs.config2(3, n_particles=40, horizon=11)
+    prob.params.n_null = 4
+    prob.params.comb_filter = comb
+    prob.params.comb = (0.4, 0.4, 0.2)
+    o = oracle_lib.Oracle(prob)
+    full = o.noise(7)
+    idx = np.array([39, 0, 19, 20, 21, 35, 36, 5, 5])
+    np.testing.assert_array_equal(o.noise_particles(7, idx), full[idx])
+    np.testing.assert_array_equal(o.noise_particles(7, np.arange(40)), full)
+    with pytest.raises(RuntimeError):
+        o.noise_particles(7, [40])
+
+
 def _comb_noise(oracle_lib, c, N=24, H=17, step=4):
     prob = inputs.config2(0, n_particles=N, horizon=H)
     prob.params.n_null = 3
