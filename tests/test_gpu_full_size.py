@@ -14,7 +14,13 @@ On a sample of the problems, the FP64 oracle is checked in two ways:
   The stored shifted mean, variance and command must agree to 1e-4.
 
 The large workload's Adam refinement is covered by the batched refinement
-tests (marked gpu)."""
+tests.
+
+The interface's maxima are checked too:
+- N = 2^20 particles (STORM_MAX_PARTICLES) in a plain context, on sampled
+  particles and on the update over all of them;
+- 64 body spheres with 256 obstacles at H=64, at every particle and step
+  (marked gpu)."""
 import copy
 
 import numpy as np
@@ -54,7 +60,8 @@ def _oracle(oracle, pr, goal):
     o = oracle.Oracle(pr, dh=f32(inputs.PANDA_DH), q_min=f32(inputs.PANDA_Q_MIN), q_max=f32(inputs.PANDA_Q_MAX),
                       qd_max=f32(inputs.PANDA_QD_MAX))
     o.dt = f32(pr.params.dt)
-    o.goal = goal
+    if goal is not None:
+        o.goal = goal
     return o
 
 
@@ -139,3 +146,110 @@ def test_uneven_batched_workload_full_size(oracle_lib):
 def test_large_workload_full_size(oracle_lib):
     probs = [_as_run(inputs.config5_problem(p)) for p in range(64)]
     _check_sampled(oracle_lib, probs, [0, 21, 42, 63], 20, 53)
+
+
+@pytest.mark.parametrize("beta", [1e-4, 0.1, 1e6])
+def test_maximum_particles(oracle_lib, beta):
+    """N = 2^20 (the largest N the interface takes), H = 8: 131072 tiles of
+    eight particles, half Halton + B-spline, the last three null, every cost
+    term.  Sampled particles (the first and last of each kind among them)
+    against the oracle: controls and states to 1e-5, horizon cost to 1e-4
+    relative.  The update over all particles against the oracle's on the
+    kernel's costs and controls: with beta 1e-4 a few particles keep a
+    weight that is not zero in FP32 (the update's compacted list), with
+    beta 1e6 every particle does (its streaming gather); 0.1 is the value
+    the workloads run with."""
+    from paper_2104_13542_amd import storm
+    from tests.gpu_common import TOL_COST_REL, TOL_MEAN, TOL_STATE, cost_error, f32, manip_values
+
+    N, H = 1 << 20, 8
+    prob = _as_run(inputs.config2(41, n_particles=N, horizon=H, n_obs_spheres=5, n_obs_cuboids=5))
+    p = prob.params
+    p.beta = beta
+    p.n_null = 3
+    o = _oracle(oracle_lib, prob, None)
+    o.goal = f32(o.goal)
+    r = storm.Rollout(prob)
+    try:
+        out = r.step(torch.tensor(o.goal, dtype=torch.float32, device="cuda"), debug=True)
+        cmd, mean, sig2 = r.update(shift=True)
+        torch.cuda.synchronize()
+        gC = out["C"].cpu().double().numpy()
+        gu = out["u"].cpu().double().numpy().transpose(1, 2, 0)
+        gq = out["q"].cpu().numpy()
+        del out
+    finally:
+        r.close()
+    assert np.isfinite(gC).all()
+    sig2_0 = f32(np.asarray(p.sigma_init) ** 2)
+    mean0 = np.zeros((H, 7))
+
+    rng = np.random.default_rng(17)
+    nh = p.n_halton
+    fixed = np.array([0, nh - 1, nh, N - p.n_null - 1, N - p.n_null, N - 1])
+    idx = np.unique(np.concatenate([fixed, rng.choice(N, 40, replace=False)]))
+    sub = copy.deepcopy(prob)
+    sub.params.n_particles = len(idx)
+    sub.params.n_halton = int(np.sum(idx < nh))
+    sub.params.n_null = int(np.sum(idx >= N - p.n_null))
+    ro = _oracle(oracle_lib, sub, o.goal).rollout(mean0, np.sqrt(sig2_0), o.noise_particles(0, idx),
+                                                  want_terms=False)
+    assert np.max(np.abs(gu[idx] - ro["u"])) <= TOL_STATE
+    assert np.max(np.abs(gq[:, idx, :].transpose(1, 2, 0) - ro["q"])) <= TOL_STATE
+    near = (np.abs(manip_values(o, ro["q"]) - p.k_m) < 1e-4).any(axis=1)
+    assert (~near).sum() >= len(idx) // 2
+    err = cost_error(gC[idx], ro["C"])
+    assert np.max(err[~near]) <= TOL_COST_REL, idx[np.argmax(np.where(near, 0, err))]
+
+    upd = o.update(gC, gu, mean0, sig2_0)
+    # weights that are not zero in FP32, which pick the update's gather (the
+    # compacted list holds at most 4096)
+    gC32 = gC.astype(np.float32)
+    nonzero = int(np.sum(np.exp((gC32 - gC32.min()) * np.float32(-1.0 / beta)) > 0))
+    print("N=%d beta=%g: %d weights not zero in FP32, max C error %.2e" % (N, beta, nonzero, np.max(err[~near])),
+          flush=True)
+    if beta < 1e-3:
+        assert nonzero <= 4096
+    if beta > 1.0:
+        assert nonzero == N
+    assert np.max(np.abs(mean.cpu().double().numpy() - upd["mean"])) <= TOL_MEAN
+    assert np.max(np.abs(sig2.cpu().double().numpy() - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"])
+    assert np.max(np.abs(cmd.cpu().double().numpy() - upd["cmd"])) <= TOL_MEAN
+
+
+def _sphere_model_64():
+    """The 52-sphere body model plus copies of the end spheres of links 1-6
+    moved 1 cm along z: 64 spheres (the largest model the interface takes),
+    sorted by body."""
+    base = inputs.panda_spheres()
+    extra = []
+    for b in range(1, 7):
+        own = base[base[:, 0] == b]
+        for row in (own[0], own[-1]):
+            row = row.copy()
+            row[3] += 0.01
+            extra.append(row)
+    s = np.concatenate([base, np.array(extra)])
+    return s[np.argsort(s[:, 0], kind="stable")]
+
+
+def test_maximum_spheres_obstacles_horizon(oracle_lib):
+    """The interface's maxima together: 64 body spheres, 256 obstacles
+    (four 64-obstacle chunks; 128 of them planted on the arm, half spheres,
+    half cuboids) and H = 64.  Every particle and step against the oracle
+    (N = 40, the last two null): states, running and horizon costs, each
+    term."""
+    from tests.gpu_common import run_pair
+    from tests.test_gpu_collision import _planted_scene
+    from tests.test_gpu_parity import _config2_checks
+
+    rng = np.random.default_rng(64)
+    prob = inputs.config2(29, n_particles=40, horizon=64, n_obs_spheres=64, n_obs_cuboids=64)
+    prob.spheres = _sphere_model_64()
+    prob.params.n_null = 2
+    planted = _planted_scene(oracle_lib, prob, rng, 64, 64)
+    prob.obstacles = np.concatenate([prob.obstacles.reshape(-1, inputs.OBSTACLE_STRIDE), planted])
+    assert prob.spheres.shape[0] == 64 and prob.obstacles.shape[0] == 256
+    g, ro, up, o, _ = run_pair(prob, oracle_lib)
+    _config2_checks(g, ro, o, prob)
+    assert np.mean(ro["terms"][..., 7] > 0) > 0.1, "the planted scene should collide often"
