@@ -244,6 +244,32 @@ def test_zero_variance(oracle_lib):
     assert np.max(np.abs(g["cmd"] - upd["cmd"])) <= TOL_MEAN
 
 
+@pytest.mark.parametrize("kind", ["halton", "gaussian", "null"])
+def test_one_kind_of_particle(oracle_lib, kind):
+    """Every particle of one kind: all Halton + B-spline, all Gaussian, or
+    all null (u = 0 everywhere, so every particle holds the start state and
+    the weights are uniform: the update moves the mean to (1 - alpha_mu) mu).
+    Against the oracle: states, costs, terms and the update."""
+    prob = inputs.config2(19, n_particles=70, horizon=20, n_obs_spheres=8, n_obs_cuboids=8)
+    p = prob.params
+    N, H = p.n_particles, p.horizon
+    p.n_halton = N if kind == "halton" else 0
+    p.n_null = N if kind == "null" else 0
+    mean = (0.1 * np.cos(np.linspace(0.0, 2.0, H))[:, None] * np.linspace(1.0, -0.5, 7)[None, :]).astype(np.float32)
+    sig2 = f32(np.asarray(p.sigma_init) ** 2)
+    g, ro, up, o, _ = run_pair(prob, oracle_lib, step_index=2, mean=mean, sigma2=sig2)
+    _config2_checks(g, ro, o, prob)
+    upd = o.update(g["C"], g["u"], f32(mean), sig2)
+    assert np.max(np.abs(g["mean"] - upd["mean"])) <= TOL_MEAN
+    assert np.max(np.abs(g["sigma2"] - upd["sigma2"])) <= 1e-4 * np.max(upd["sigma2"])
+    if kind == "null":
+        assert np.all(g["u"] == 0.0)
+        # uniform on the oracle's own costs (the kernel's differ by the order
+        # of their sums, which beta = 0.1 turns into weights a few percent apart)
+        np.testing.assert_allclose(up["w"], 1.0 / N, rtol=1e-12)
+        np.testing.assert_allclose(g["mean"], (1.0 - p.alpha_mu) * f32(mean), atol=TOL_MEAN)
+
+
 def test_determinism():
     from paper_2104_13542_amd import storm
 
