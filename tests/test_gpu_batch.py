@@ -236,22 +236,21 @@ def _sized_problem(seed, N, H, n_obs):
     return pr
 
 
-def test_batch_against_oracle():
-    """Every problem of a batch with uneven shapes, up to the largest of
-    the batched workload (N = 1024, H = 40, 50 obstacles), against the FP64
-    oracle: horizon costs to 1e-4 relative (states within 1e-4 of the
-    manipulability threshold masked), and the update (the oracle's on the
-    kernel's costs) to 1e-4: stored shifted mean, variance and command; the
-    second control step samples with the advanced counter around the
-    shifted mean."""
+def _batch_against_oracle(shapes, seed0, steps):
+    """A batch of problems of the given (N, H, obstacles) shapes, null
+    particles on every other one, run for `steps` control steps and checked
+    against the FP64 oracle after each: horizon costs to 1e-4 relative
+    (states within 1e-4 of the manipulability threshold masked), and the
+    update (the oracle's on the kernel's costs) to 1e-4: stored shifted
+    mean, variance and command; each step samples with the advanced counter
+    around the shifted mean."""
     import oracle
     from paper_2104_13542_amd import storm
     from tests.gpu_common import TOL_COST_REL, TOL_MEAN, cost_error, f32, manip_values
 
-    shapes = [(1024, 40, 50), (997, 20, 10), (128, 33, 27), (801, 40, 50), (300, 23, 41)]
     probs = []
     for k, (N, H, n_obs) in enumerate(shapes):
-        pr = _sized_problem(40 + k, N, H, n_obs)
+        pr = _sized_problem(seed0 + k, N, H, n_obs)
         pr.params.n_null = k % 2
         pr.spheres, pr.obstacles = f32(pr.spheres), f32(pr.obstacles)
         pr.q0, pr.v0, pr.a0 = f32(pr.q0), f32(pr.v0), f32(pr.a0)
@@ -269,7 +268,7 @@ def test_batch_against_oracle():
     means = [np.zeros((pr.params.horizon, 7)) for pr in probs]
     sig2s = [f32(np.asarray(pr.params.sigma_init) ** 2) for pr in probs]
     try:
-        for step in range(2):
+        for step in range(steps):
             b.step(goals)
             cmd = b.update(shift=True).cpu().double().numpy()
             torch.cuda.synchronize()
@@ -293,6 +292,21 @@ def test_batch_against_oracle():
                 means[k], sig2s[k] = f32(mb), f32(sb)
     finally:
         b.close()
+
+
+def test_batch_against_oracle():
+    """Uneven shapes up to the largest of the batched workload (N = 1024,
+    H = 40, 50 obstacles), two control steps."""
+    _batch_against_oracle([(1024, 40, 50), (997, 20, 10), (128, 33, 27), (801, 40, 50), (300, 23, 41)], 40, 2)
+
+
+def test_batch_extreme_shapes_against_oracle():
+    """Problems at the edges of the shapes a batch takes, side by side: one
+    particle over one step and no obstacle, one null particle over 64 steps,
+    two particles over 33 steps, 700 particles over 7 steps (nine particles
+    per tile) with 64 obstacles, and 65 particles over 64 steps with 130
+    obstacles (three obstacle chunks)."""
+    _batch_against_oracle([(1, 1, 0), (1, 64, 10), (2, 33, 0), (700, 7, 64), (65, 64, 130)], 81, 2)
 
 
 def test_batch_variants_against_oracle():
