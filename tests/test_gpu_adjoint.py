@@ -56,8 +56,11 @@ def _dev(a):
 @pytest.mark.parametrize("mask", [inputs.COST_POSE | inputs.COST_JOINT,
                                   inputs.COST_POSE | inputs.COST_JOINT | inputs.COST_VEL | inputs.COST_STOP])
 @pytest.mark.parametrize("N,H,n_null", [(128, 30, 0), (67, 21, 3), (5, 64, 1), (1024, 30, 0), (2000, 30, 2),
-                                        (700, 64, 0)])
+                                        (700, 64, 0), (1, 1, 0), (3, 64, 3)])
 def test_grad_matches_oracle(oracle_lib, mask, N, H, n_null):
+    """Gradient and expected cost against the oracle's, in norm and element
+    by element; the shapes include one particle over one step and a problem
+    whose particles are all null (gradient exactly zero)."""
     from paper_2104_13542_amd import storm
 
     prob, o, eps, mean = _setup(oracle_lib, N=N, H=H, mask=mask, n_null=n_null)
